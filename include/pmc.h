@@ -1,0 +1,135 @@
+/*
+ * pmc.h -- C-ABI of the MI355X progressive multi-component compression library.
+ *
+ * Method: Magri & Lindstrom, "A General Framework for Progressive Data
+ * Compression and Retrieval".  A field x is stored as components y_1..y_n,
+ * y_i = C(x - x~_{i-1}, tau_i), x~_i = x~_{i-1} + D(y_i), for a strictly
+ * decreasing tolerance sequence (Sec. 4.1, Alg. 1).  The sum of the first k
+ * decoded components, added left to right in the precision of x (Sec. 3), is
+ * the progressive reconstruction x~_k (Sec. 4.2, Alg. 2) and satisfies
+ * max|x - x~_k| <= tau_k (Sec. 4.3, Eq. (1)).  The codec C / D is a zfp-style
+ * fixed-accuracy codec on 4x4x4 blocks (stream format version 1).
+ *
+ * Conventions for every call:
+ *  - Device pointers (d_*) are allocated by the caller (e.g. PyTorch); the
+ *    library never allocates device memory.  Host pointers are plain memory.
+ *  - Work is enqueued on the HIP stream given to pmc_ctx_create; calls return
+ *    once their kernels are enqueued unless stated otherwise.
+ *  - Fields are dense, C order, x fastest: element (x, y, z) is at
+ *    x + nx * (y + ny * z).  Lower-dimensional data use extents of 1.
+ *  - Return value: PMC_OK (0) or a negative pmc_status; the context keeps a
+ *    message for pmc_last_error.  On error no output is valid.
+ *  - One context per host thread.
+ */
+#ifndef PMC_H
+#define PMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PMC_OK = 0,
+  PMC_E_ARG = -1,         /* bad argument: dims, n, tau not strictly decreasing (Alg. 1 input) or not > 0 */
+  PMC_E_NONFINITE = -2,   /* NaN or Inf in the input; the method does not handle them (Sec. 6.1) */
+  PMC_E_NOMEM = -3,       /* workspace or stream capacity too small; the size needed is reported */
+  PMC_E_CORRUPT = -4,     /* malformed stream */
+  PMC_E_UNREACHABLE = -5, /* requested tolerance is below the last component's */
+  PMC_E_BOUND = -6,       /* an Eq. (1) bound was missed (not expected; see the acceptance rule) */
+  PMC_E_DEVICE = -7       /* HIP runtime error */
+} pmc_status;
+
+typedef enum { PMC_F32 = 1, PMC_F64 = 2 } pmc_dtype;
+
+/* A 3-D field: extents (x fastest) and element type. */
+typedef struct {
+  uint64_t nx, ny, nz;
+  int32_t dtype; /* pmc_dtype */
+  int32_t reserved;
+} pmc_field;
+
+typedef struct pmc_ctx pmc_ctx;
+typedef struct pmc_store pmc_store;
+
+/* ---- context ------------------------------------------------------------ */
+/* Bind to HIP device `device` and stream `hip_stream` (a hipStream_t; NULL for
+ * the default stream). */
+pmc_status pmc_ctx_create(int device, void* hip_stream, pmc_ctx** out);
+void pmc_ctx_destroy(pmc_ctx* ctx);
+/* Message of the last failed call on this context ("" if none). */
+const char* pmc_last_error(const pmc_ctx* ctx);
+
+/* Options:
+ *  PMC_OPT_FUSED_DECODE (default 1): retrieval decodes all requested
+ *    components of a chunk in one pass and writes x~_k once; 0 runs one pass
+ *    per component (x~ read and written each time), the literal Alg. 2 loop.
+ *    Both give bit-identical results.
+ *  PMC_OPT_SYNC_CHECK (default 0): decode calls synchronise the stream and
+ *    report PMC_E_CORRUPT when a kernel found a malformed stream. */
+enum { PMC_OPT_FUSED_DECODE = 1, PMC_OPT_SYNC_CHECK = 2 };
+pmc_status pmc_ctx_set_option(pmc_ctx* ctx, int option, int value);
+
+/* ---- range (tau_0 of the tolerance schedule, Sec. 5.1) --------------------
+ * min and max of the field in float64 and the number of non-finite values.
+ * d_ws: at least 256 bytes of device scratch.  Synchronises the stream. */
+pmc_status pmc_range(pmc_ctx* ctx, const pmc_field* f, const void* d_x, void* d_ws, size_t ws_bytes,
+                     double* vmin, double* vmax, uint64_t* nonfinite);
+
+/* ---- multi-component compression (Alg. 1, Sec. 4.1) ----------------------
+ * Sizes for pmc_compress: device workspace bytes, and the capacity one
+ * component's stream can need in the worst case (all blocks raw).  The total
+ * stream capacity is at most n * stream_cap_per_comp (each stream starts on a
+ * 256-byte boundary). */
+pmc_status pmc_compress_sizes(const pmc_field* f, int n, size_t* ws_bytes, size_t* stream_cap_per_comp);
+
+/* Compress d_x into n components with tolerances tau[0] > tau[1] > ... > 0
+ * (absolute, pointwise).  Streams are written one after another into d_streams
+ * (capacity streams_cap bytes), which must stay alive as long as the store.
+ * On success *out holds per-component metadata: prescribed tau and measured
+ * max|x - x~_i| in float64 (Sec. 4.3, last paragraph), stream bytes, block
+ * counts.  Synchronises the stream once at the end to read the sizes. */
+pmc_status pmc_compress(pmc_ctx* ctx, const pmc_field* f, const void* d_x, int n, const double* tau,
+                        void* d_ws, size_t ws_bytes, void* d_streams, size_t streams_cap, pmc_store** out);
+
+/* Per-component metadata (arrays of store n entries; any may be NULL). */
+pmc_status pmc_store_info(const pmc_store* s, int* n, double* tau, double* linf, uint64_t* bytes,
+                          uint64_t* nraw, uint64_t* nesc);
+/* Field of a store. */
+pmc_status pmc_store_field(const pmc_store* s, pmc_field* f);
+/* Device address and byte size of component i's stream (0-based). */
+pmc_status pmc_store_stream(const pmc_store* s, int i, const void** d_stream, uint64_t* bytes);
+
+/* Smallest k with tau_k <= tol (use_measured = 0) or with the measured error
+ * <= tol (use_measured = 1), following Sec. 6.2 (tolerances or measured
+ * errors stored as per-component metadata).  PMC_E_UNREACHABLE if none. */
+pmc_status pmc_select_k(const pmc_store* s, double tol, int use_measured, int* k);
+
+/* ---- progressive reconstruction (Alg. 2, Sec. 4.2) ----------------------
+ * Device scratch needed by the decode calls (status word). */
+size_t pmc_decode_ws_bytes(void);
+/* d_out <- x~_k = (...((+0 + x_1) + x_2) ...) + x_k, 1 <= k <= n. */
+pmc_status pmc_retrieve(pmc_ctx* ctx, const pmc_store* s, int k, void* d_out, void* d_ws, size_t ws_bytes);
+/* d_inout holds x~_{k_from}; add components k_from+1..k_to in order
+ * (incremental refinement without decoder state, Sec. 4.2 last paragraph). */
+pmc_status pmc_refine(pmc_ctx* ctx, const pmc_store* s, int k_from, int k_to, void* d_inout, void* d_ws,
+                      size_t ws_bytes);
+
+/* ---- persistence --------------------------------------------------------
+ * Serialise metadata and streams to host memory (synchronises).  With
+ * host_buf == NULL only *used is set to the size needed. */
+pmc_status pmc_store_serialize(pmc_ctx* ctx, const pmc_store* s, void* host_buf, size_t cap, size_t* used);
+/* Rebuild a store from a serialised blob, uploading its streams into
+ * d_streams (capacity cap, caller-owned; see pmc_store_device_bytes).  Stream
+ * headers and chunk indexes are validated on the host (PMC_E_CORRUPT). */
+pmc_status pmc_store_device_bytes(const void* host_buf, size_t size, size_t* need);
+pmc_status pmc_store_deserialize(pmc_ctx* ctx, const void* host_buf, size_t size, void* d_streams, size_t cap,
+                                 pmc_store** out);
+void pmc_store_free(pmc_store* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PMC_H */

@@ -1,0 +1,593 @@
+// capi.cpp -- C-ABI of the progressive multi-component codec (see include/pmc.h).
+// Host code only: argument checks, workspace layout, kernel sequencing, and
+// the per-component metadata of the store.  Every arithmetic step of the path
+// runs in the HIP kernels of kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pmc.h"
+#include "launch.hpp"
+
+using namespace pmc;
+
+struct pmc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  int fused_decode = 1;
+  int sync_check = 0;
+};
+
+struct pmc_store {
+  pmc_field f{};
+  Geo g{};
+  int n = 0;
+  std::vector<double> tau, linf;
+  std::vector<int> minexp;
+  std::vector<uint64_t> bytes, offset, words, nempty, ncoded, nraw, nesc, nmiss;
+  const uint8_t* d_base = nullptr;  // caller-owned device memory holding the streams
+};
+
+namespace {
+
+pmc_status fail(pmc_ctx* ctx, pmc_status st, const char* fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return st;
+}
+
+pmc_status hipfail(pmc_ctx* ctx, hipError_t e, const char* what) {
+  return fail(ctx, PMC_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool make_geo(const pmc_field* f, Geo* g) {
+  if (!f || f->nx < 1 || f->ny < 1 || f->nz < 1) return false;
+  if (f->dtype != PMC_F32 && f->dtype != PMC_F64) return false;
+  if (f->nx > (1ull << 40) || f->ny > (1ull << 40) || f->nz > (1ull << 40)) return false;
+  g->nx = f->nx;
+  g->ny = f->ny;
+  g->nz = f->nz;
+  g->nbx = (f->nx + 3) / 4;
+  g->nby = (f->ny + 3) / 4;
+  g->nbz = (f->nz + 3) / 4;
+  g->nblocks = g->nbx * g->nby * g->nbz;
+  g->nchunks = (g->nblocks + 15) / 16;
+  g->rows_aligned = (f->nx % 4) == 0;
+  g->pad = 0;
+  return true;
+}
+
+uint64_t elem_size(const pmc_field* f) { return f->dtype == PMC_F32 ? 4 : 8; }
+uint64_t align256(uint64_t v) { return (v + 255) & ~255ull; }
+
+// floor(log2(tau)) of a positive finite double, from its bits
+int floor_log2(double tau) {
+  uint64_t b;
+  std::memcpy(&b, &tau, 8);
+  int biased = (int)((b >> 52) & 0x7ff);
+  uint64_t mant = b & ((1ull << 52) - 1);
+  if (biased == 0) {  // subnormal: position of the leading mantissa bit
+    int lead = 63 - __builtin_clzll(mant);
+    return lead - 1074;
+  }
+  return biased - 1023;
+}
+
+struct WsLayout {
+  uint64_t xt, staging, chunk_words, offsets, meta, total;
+};
+
+WsLayout ws_layout(const pmc_field* f, const Geo& g, int n) {
+  WsLayout w{};
+  uint64_t o = 0;
+  w.xt = o;
+  if (n > 1) o += align256(g.nx * g.ny * g.nz * elem_size(f));
+  w.staging = o;
+  o += align256(g.nchunks * chunk_cap_words_host(f->dtype) * 4);
+  w.chunk_words = o;
+  o += align256(g.nchunks * 4);
+  w.offsets = o;
+  o += align256(g.nchunks * 4);
+  w.meta = o;
+  o += align256((uint64_t)n * sizeof(CompMeta));
+  w.total = o;
+  return w;
+}
+
+uint64_t stream_cap_one(const Geo& g, int dtype) {
+  return kStreamHeader + 4 * g.nchunks + 4 * g.nchunks * chunk_cap_words_host(dtype);
+}
+
+}  // namespace
+
+extern "C" {
+
+pmc_status pmc_ctx_create(int device, void* hip_stream, pmc_ctx** out) {
+  if (!out) return PMC_E_ARG;
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || device < 0 || device >= count) return PMC_E_DEVICE;
+  pmc_ctx* c = new pmc_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  *out = c;
+  return PMC_OK;
+}
+
+void pmc_ctx_destroy(pmc_ctx* ctx) { delete ctx; }
+
+const char* pmc_last_error(const pmc_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+pmc_status pmc_ctx_set_option(pmc_ctx* ctx, int option, int value) {
+  if (!ctx) return PMC_E_ARG;
+  if (option == PMC_OPT_FUSED_DECODE) ctx->fused_decode = value ? 1 : 0;
+  else if (option == PMC_OPT_SYNC_CHECK) ctx->sync_check = value ? 1 : 0;
+  else return fail(ctx, PMC_E_ARG, "unknown option %d", option);
+  return PMC_OK;
+}
+
+pmc_status pmc_range(pmc_ctx* ctx, const pmc_field* f, const void* d_x, void* d_ws, size_t ws_bytes,
+                     double* vmin, double* vmax, uint64_t* nonfinite) {
+  if (!ctx) return PMC_E_ARG;
+  Geo g;
+  if (!make_geo(f, &g) || !d_x) return fail(ctx, PMC_E_ARG, "bad field");
+  if (!d_ws || ws_bytes < 256) return fail(ctx, PMC_E_NOMEM, "range needs 256 bytes of workspace");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hipfail(ctx, e, "hipSetDevice");
+  unsigned long long* w = (unsigned long long*)d_ws;
+  const uint64_t n = g.nx * g.ny * g.nz;
+  if ((e = launch_fill64(w, 1, ~0ull, ctx->stream)) != hipSuccess) return hipfail(ctx, e, "fill");
+  if ((e = launch_fill64(w + 1, 2, 0ull, ctx->stream)) != hipSuccess) return hipfail(ctx, e, "fill");
+  if (f->dtype == PMC_F32) e = launch_range<float>((const float*)d_x, n, w, ctx->stream);
+  else e = launch_range<double>((const double*)d_x, n, w, ctx->stream);
+  if (e != hipSuccess) return hipfail(ctx, e, "range kernel");
+  unsigned long long h[3];
+  if ((e = hipMemcpyAsync(h, w, sizeof(h), hipMemcpyDeviceToHost, ctx->stream)) != hipSuccess)
+    return hipfail(ctx, e, "copy");
+  if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return hipfail(ctx, e, "sync");
+  auto unorder = [](unsigned long long o) {
+    uint64_t b = (o >> 63) ? (o & 0x7FFFFFFFFFFFFFFFull) : ~o;
+    double v;
+    std::memcpy(&v, &b, 8);
+    return v;
+  };
+  if (nonfinite) *nonfinite = h[2];
+  if (h[2] == n) {  // nothing finite
+    if (vmin) *vmin = NAN;
+    if (vmax) *vmax = NAN;
+  } else {
+    if (vmin) *vmin = unorder(h[0]);
+    if (vmax) *vmax = unorder(h[1]);
+  }
+  return PMC_OK;
+}
+
+pmc_status pmc_compress_sizes(const pmc_field* f, int n, size_t* ws_bytes, size_t* stream_cap_per_comp) {
+  Geo g;
+  if (!make_geo(f, &g) || n < 1 || n > kMaxComps) return PMC_E_ARG;
+  WsLayout w = ws_layout(f, g, n);
+  if (ws_bytes) *ws_bytes = w.total;
+  if (stream_cap_per_comp) *stream_cap_per_comp = align256(stream_cap_one(g, f->dtype));
+  return PMC_OK;
+}
+
+pmc_status pmc_compress(pmc_ctx* ctx, const pmc_field* f, const void* d_x, int n, const double* tau, void* d_ws,
+                        size_t ws_bytes, void* d_streams, size_t streams_cap, pmc_store** out) {
+  if (!ctx) return PMC_E_ARG;
+  if (out) *out = nullptr;
+  Geo g;
+  if (!make_geo(f, &g)) return fail(ctx, PMC_E_ARG, "bad field");
+  if (!d_x || !tau || !out || !d_streams) return fail(ctx, PMC_E_ARG, "null argument");
+  if (n < 1 || n > kMaxComps) return fail(ctx, PMC_E_ARG, "n must be in [1, %d]", kMaxComps);
+  for (int i = 0; i < n; ++i) {
+    if (!(tau[i] > 0.0) || !std::isfinite(tau[i])) return fail(ctx, PMC_E_ARG, "tau[%d] must be > 0 and finite", i);
+    if (i > 0 && !(tau[i] < tau[i - 1])) return fail(ctx, PMC_E_ARG, "tau must be strictly decreasing");
+  }
+  WsLayout w = ws_layout(f, g, n);
+  if (!d_ws || ws_bytes < w.total)
+    return fail(ctx, PMC_E_NOMEM, "workspace too small: need %llu bytes", (unsigned long long)w.total);
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hipfail(ctx, e, "hipSetDevice");
+  uint8_t* ws = (uint8_t*)d_ws;
+  CompMeta* meta = (CompMeta*)(ws + w.meta);
+  if ((e = launch_fill64((unsigned long long*)meta, (uint64_t)n * sizeof(CompMeta) / 8, 0ull, ctx->stream)) !=
+      hipSuccess)
+    return hipfail(ctx, e, "meta init");
+
+  std::vector<int> minexp(n);
+  for (int i = 0; i < n; ++i) {
+    minexp[i] = floor_log2(tau[i]);
+    ScanArgs sa{};
+    sa.chunk_words = (const uint32_t*)(ws + w.chunk_words);
+    sa.offsets = (uint32_t*)(ws + w.offsets);
+    sa.nchunks = g.nchunks;
+    sa.meta = meta;
+    sa.comp = i;
+    sa.ncomp = n;
+    sa.streams_cap = streams_cap;
+    PackArgs pa{};
+    pa.staging = (const uint32_t*)(ws + w.staging);
+    pa.chunk_words = sa.chunk_words;
+    pa.offsets = sa.offsets;
+    pa.nchunks = g.nchunks;
+    pa.meta = meta;
+    pa.comp = i;
+    pa.minexp = minexp[i];
+    pa.streams = (uint8_t*)d_streams;
+    pa.g = g;
+    pa.tau = tau[i];
+    if (f->dtype == PMC_F32) {
+      EncArgs<float> a{};
+      a.x = (const float*)d_x;
+      a.xt = (float*)(ws + w.xt);
+      a.g = g;
+      a.tau = tau[i];
+      a.minexp = minexp[i];
+      a.first = i == 0;
+      a.last = i == n - 1;
+      a.staging = (uint32_t*)(ws + w.staging);
+      a.chunk_words = (uint32_t*)(ws + w.chunk_words);
+      a.meta = meta + i;
+      if ((e = launch_encode<float>(a, ctx->stream)) != hipSuccess) return hipfail(ctx, e, "encode");
+      if ((e = launch_scan(sa, ctx->stream)) != hipSuccess) return hipfail(ctx, e, "scan");
+      if ((e = launch_pack<float>(pa, ctx->stream)) != hipSuccess) return hipfail(ctx, e, "pack");
+    } else {
+      EncArgs<double> a{};
+      a.x = (const double*)d_x;
+      a.xt = (double*)(ws + w.xt);
+      a.g = g;
+      a.tau = tau[i];
+      a.minexp = minexp[i];
+      a.first = i == 0;
+      a.last = i == n - 1;
+      a.staging = (uint32_t*)(ws + w.staging);
+      a.chunk_words = (uint32_t*)(ws + w.chunk_words);
+      a.meta = meta + i;
+      if ((e = launch_encode<double>(a, ctx->stream)) != hipSuccess) return hipfail(ctx, e, "encode");
+      if ((e = launch_scan(sa, ctx->stream)) != hipSuccess) return hipfail(ctx, e, "scan");
+      if ((e = launch_pack<double>(pa, ctx->stream)) != hipSuccess) return hipfail(ctx, e, "pack");
+    }
+  }
+  std::vector<CompMeta> hm(n);
+  if ((e = hipMemcpyAsync(hm.data(), meta, n * sizeof(CompMeta), hipMemcpyDeviceToHost, ctx->stream)) !=
+      hipSuccess)
+    return hipfail(ctx, e, "meta copy");
+  if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return hipfail(ctx, e, "sync");
+
+  unsigned int flags = 0;
+  unsigned long long misses = 0;
+  for (int i = 0; i < n; ++i) {
+    flags |= hm[i].flags;
+    misses += hm[i].nmiss;
+  }
+  if (flags & FLAG_NONFINITE) return fail(ctx, PMC_E_NONFINITE, "input holds NaN or Inf");
+  if (flags & FLAG_INDEX) return fail(ctx, PMC_E_NOMEM, "a stream exceeds 2^32 payload words");
+  if (flags & FLAG_OVERFLOW) {
+    unsigned long long need = 0;
+    for (int i = 0; i < n; ++i) need = align256(need) + hm[i].stream_bytes;
+    return fail(ctx, PMC_E_NOMEM, "stream capacity too small: need %llu bytes", need);
+  }
+  pmc_store* s = new pmc_store();
+  s->f = *f;
+  s->g = g;
+  s->n = n;
+  s->d_base = (const uint8_t*)d_streams;
+  for (int i = 0; i < n; ++i) {
+    double l;
+    std::memcpy(&l, &hm[i].linf_bits, 8);
+    s->tau.push_back(tau[i]);
+    s->linf.push_back(l);
+    s->minexp.push_back(minexp[i]);
+    s->bytes.push_back(hm[i].stream_bytes);
+    s->offset.push_back(hm[i].stream_offset);
+    s->words.push_back(hm[i].payload_words);
+    s->nempty.push_back(hm[i].nempty);
+    s->ncoded.push_back(hm[i].ncoded);
+    s->nraw.push_back(hm[i].nraw);
+    s->nesc.push_back(hm[i].nesc);
+    s->nmiss.push_back(hm[i].nmiss);
+  }
+  *out = s;
+  if (misses) return fail(ctx, PMC_E_BOUND, "%llu blocks missed their tolerance", misses);
+  return PMC_OK;
+}
+
+pmc_status pmc_store_info(const pmc_store* s, int* n, double* tau, double* linf, uint64_t* bytes, uint64_t* nraw,
+                          uint64_t* nesc) {
+  if (!s) return PMC_E_ARG;
+  if (n) *n = s->n;
+  for (int i = 0; i < s->n; ++i) {
+    if (tau) tau[i] = s->tau[i];
+    if (linf) linf[i] = s->linf[i];
+    if (bytes) bytes[i] = s->bytes[i];
+    if (nraw) nraw[i] = s->nraw[i];
+    if (nesc) nesc[i] = s->nesc[i];
+  }
+  return PMC_OK;
+}
+
+pmc_status pmc_store_field(const pmc_store* s, pmc_field* f) {
+  if (!s || !f) return PMC_E_ARG;
+  *f = s->f;
+  return PMC_OK;
+}
+
+pmc_status pmc_store_stream(const pmc_store* s, int i, const void** d_stream, uint64_t* bytes) {
+  if (!s || i < 0 || i >= s->n) return PMC_E_ARG;
+  if (d_stream) *d_stream = s->d_base + s->offset[i];
+  if (bytes) *bytes = s->bytes[i];
+  return PMC_OK;
+}
+
+pmc_status pmc_select_k(const pmc_store* s, double tol, int use_measured, int* k) {
+  if (!s || !k) return PMC_E_ARG;
+  for (int i = 0; i < s->n; ++i) {
+    const double v = use_measured ? s->linf[i] : s->tau[i];
+    if (v <= tol) {
+      *k = i + 1;
+      return PMC_OK;
+    }
+  }
+  *k = 0;
+  return PMC_E_UNREACHABLE;
+}
+
+size_t pmc_decode_ws_bytes(void) { return 256; }
+
+static pmc_status decode_range(pmc_ctx* ctx, const pmc_store* s, int k0, int k1, const void* d_in, void* d_out,
+                               void* d_ws, size_t ws_bytes) {
+  if (!d_ws || ws_bytes < pmc_decode_ws_bytes()) return fail(ctx, PMC_E_NOMEM, "decode needs 256 bytes of workspace");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hipfail(ctx, e, "hipSetDevice");
+  unsigned int* status = (unsigned int*)d_ws;
+  if ((e = launch_fill64((unsigned long long*)status, 1, 0ull, ctx->stream)) != hipSuccess)
+    return hipfail(ctx, e, "status init");
+  const int group = ctx->fused_decode ? kMaxDecode : 1;
+  const void* in = d_in;
+  for (int i0 = k0; i0 < k1; i0 += group) {
+    const int i1 = i0 + group < k1 ? i0 + group : k1;
+    if (s->f.dtype == PMC_F32) {
+      DecArgs<float> a{};
+      for (int i = i0; i < i1; ++i) {
+        a.s[i - i0] = s->d_base + s->offset[i];
+        a.words[i - i0] = s->words[i];
+        a.minexp[i - i0] = s->minexp[i];
+      }
+      a.ncomp = i1 - i0;
+      a.in = (const float*)in;
+      a.out = (float*)d_out;
+      a.g = s->g;
+      a.status = status;
+      e = launch_decode<float>(a, ctx->stream);
+    } else {
+      DecArgs<double> a{};
+      for (int i = i0; i < i1; ++i) {
+        a.s[i - i0] = s->d_base + s->offset[i];
+        a.words[i - i0] = s->words[i];
+        a.minexp[i - i0] = s->minexp[i];
+      }
+      a.ncomp = i1 - i0;
+      a.in = (const double*)in;
+      a.out = (double*)d_out;
+      a.g = s->g;
+      a.status = status;
+      e = launch_decode<double>(a, ctx->stream);
+    }
+    if (e != hipSuccess) return hipfail(ctx, e, "decode");
+    in = d_out;
+  }
+  if (ctx->sync_check) {
+    unsigned int h = 0;
+    if ((e = hipMemcpyAsync(&h, status, 4, hipMemcpyDeviceToHost, ctx->stream)) != hipSuccess)
+      return hipfail(ctx, e, "status copy");
+    if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return hipfail(ctx, e, "sync");
+    if (h) return fail(ctx, PMC_E_CORRUPT, "malformed stream");
+  }
+  return PMC_OK;
+}
+
+pmc_status pmc_retrieve(pmc_ctx* ctx, const pmc_store* s, int k, void* d_out, void* d_ws, size_t ws_bytes) {
+  if (!ctx) return PMC_E_ARG;
+  if (!s || !d_out) return fail(ctx, PMC_E_ARG, "null argument");
+  if (k < 1 || k > s->n) return fail(ctx, PMC_E_ARG, "k must be in [1, %d]", s->n);
+  return decode_range(ctx, s, 0, k, nullptr, d_out, d_ws, ws_bytes);
+}
+
+pmc_status pmc_refine(pmc_ctx* ctx, const pmc_store* s, int k_from, int k_to, void* d_inout, void* d_ws,
+                      size_t ws_bytes) {
+  if (!ctx) return PMC_E_ARG;
+  if (!s || !d_inout) return fail(ctx, PMC_E_ARG, "null argument");
+  if (k_from < 0 || k_to > s->n || k_from > k_to) return fail(ctx, PMC_E_ARG, "bad component range");
+  if (k_from == k_to) return PMC_OK;
+  return decode_range(ctx, s, k_from, k_to, k_from == 0 ? nullptr : d_inout, d_inout, d_ws, ws_bytes);
+}
+
+// ---- persistence -----------------------------------------------------------
+// blob: u32 "PMCS", u32 version, u32 n, u32 0 | u64 nx ny nz, i32 dtype, i32 0 |
+//       n x {f64 tau, f64 linf, u64 bytes, nempty, ncoded, nraw, nesc, nmiss} |
+//       (256-aligned) streams, each on a 256-byte boundary of the region
+static const uint32_t kBlobMagic = 0x53434D50u;
+
+static uint64_t blob_header_bytes(int n) { return align256(48 + 64ull * n); }
+
+pmc_status pmc_store_serialize(pmc_ctx* ctx, const pmc_store* s, void* host_buf, size_t cap, size_t* used) {
+  if (!ctx) return PMC_E_ARG;
+  if (!s || !used) return fail(ctx, PMC_E_ARG, "null argument");
+  uint64_t region = 0;
+  for (int i = 0; i < s->n; ++i) region = align256(region) + s->bytes[i];
+  const uint64_t total = blob_header_bytes(s->n) + align256(region);
+  *used = total;
+  if (!host_buf) return PMC_OK;
+  if (cap < total) return fail(ctx, PMC_E_NOMEM, "need %llu bytes", (unsigned long long)total);
+  uint8_t* b = (uint8_t*)host_buf;
+  std::memset(b, 0, total);
+  uint32_t h32[4] = {kBlobMagic, 1u, (uint32_t)s->n, 0u};
+  std::memcpy(b, h32, 16);
+  uint64_t dims[3] = {s->f.nx, s->f.ny, s->f.nz};
+  std::memcpy(b + 16, dims, 24);
+  int32_t dt[2] = {s->f.dtype, 0};
+  std::memcpy(b + 40, dt, 8);
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hipfail(ctx, e, "hipSetDevice");
+  uint64_t off = 0;
+  for (int i = 0; i < s->n; ++i) {
+    uint8_t* c = b + 48 + 64ull * i;
+    uint64_t v[8];
+    std::memcpy(&v[0], &s->tau[i], 8);
+    std::memcpy(&v[1], &s->linf[i], 8);
+    v[2] = s->bytes[i];
+    v[3] = s->nempty[i];
+    v[4] = s->ncoded[i];
+    v[5] = s->nraw[i];
+    v[6] = s->nesc[i];
+    v[7] = s->nmiss[i];
+    std::memcpy(c, v, 64);
+    off = align256(off);
+    e = hipMemcpyAsync(b + blob_header_bytes(s->n) + off, s->d_base + s->offset[i], s->bytes[i],
+                       hipMemcpyDeviceToHost, ctx->stream);
+    if (e != hipSuccess) return hipfail(ctx, e, "stream copy");
+    off += s->bytes[i];
+  }
+  if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return hipfail(ctx, e, "sync");
+  return PMC_OK;
+}
+
+struct BlobView {
+  int n;
+  pmc_field f;
+  std::vector<uint64_t> rec;  // 8 words per component
+  uint64_t region_off, region_bytes;
+};
+
+static bool parse_blob(const void* host_buf, size_t size, BlobView* v) {
+  const uint8_t* b = (const uint8_t*)host_buf;
+  if (!b || size < 48) return false;
+  uint32_t h32[4];
+  std::memcpy(h32, b, 16);
+  if (h32[0] != kBlobMagic || h32[1] != 1u) return false;
+  int n = (int)h32[2];
+  if (n < 1 || n > kMaxComps) return false;
+  if (size < blob_header_bytes(n)) return false;
+  v->n = n;
+  uint64_t dims[3];
+  std::memcpy(dims, b + 16, 24);
+  int32_t dt[2];
+  std::memcpy(dt, b + 40, 8);
+  v->f.nx = dims[0];
+  v->f.ny = dims[1];
+  v->f.nz = dims[2];
+  v->f.dtype = dt[0];
+  v->f.reserved = 0;
+  v->rec.resize(8ull * n);
+  std::memcpy(v->rec.data(), b + 48, 64ull * n);
+  uint64_t region = 0;
+  for (int i = 0; i < n; ++i) region = align256(region) + v->rec[8 * i + 2];
+  v->region_off = blob_header_bytes(n);
+  v->region_bytes = region;
+  if (v->region_off + region > size) return false;
+  return true;
+}
+
+// host-side validation of one stream (header fields and chunk index)
+static bool check_stream(const uint8_t* p, uint64_t bytes, const pmc_field* f, const Geo& g, double tau,
+                         uint64_t* words) {
+  if (bytes < 64) return false;
+  uint32_t h[16];
+  std::memcpy(h, p, 64);
+  if (h[0] != kStreamMagic) return false;
+  if ((h[1] & 0xFFFF) != kStreamVersion || ((h[1] >> 16) & 0xFF) != (uint32_t)f->dtype || (h[1] >> 24) != 3u)
+    return false;
+  uint64_t nx = h[2] | ((uint64_t)h[3] << 32), ny = h[4] | ((uint64_t)h[5] << 32), nz = h[6] | ((uint64_t)h[7] << 32);
+  if (nx != f->nx || ny != f->ny || nz != f->nz) return false;
+  uint64_t tb = h[8] | ((uint64_t)h[9] << 32);
+  double t;
+  std::memcpy(&t, &tb, 8);
+  if (!(t == tau) || (int32_t)h[10] != floor_log2(tau) || h[11] != 16u) return false;
+  uint64_t nch = h[12] | ((uint64_t)h[13] << 32), w = h[14] | ((uint64_t)h[15] << 32);
+  if (nch != g.nchunks) return false;
+  if (bytes != 64 + 4 * nch + 4 * w) return false;
+  const uint32_t* idx = (const uint32_t*)(p + 64);
+  uint64_t prev = 0;
+  for (uint64_t c = 0; c < nch; ++c) {
+    if (idx[c] < prev || idx[c] > w) return false;
+    prev = idx[c];
+  }
+  *words = w;
+  return true;
+}
+
+pmc_status pmc_store_device_bytes(const void* host_buf, size_t size, size_t* need) {
+  BlobView v;
+  if (!need || !parse_blob(host_buf, size, &v)) return PMC_E_CORRUPT;
+  *need = align256(v.region_bytes);
+  return PMC_OK;
+}
+
+pmc_status pmc_store_deserialize(pmc_ctx* ctx, const void* host_buf, size_t size, void* d_streams, size_t cap,
+                                 pmc_store** out) {
+  if (!ctx) return PMC_E_ARG;
+  if (!out || !d_streams) return fail(ctx, PMC_E_ARG, "null argument");
+  *out = nullptr;
+  BlobView v;
+  if (!parse_blob(host_buf, size, &v)) return fail(ctx, PMC_E_CORRUPT, "malformed store blob");
+  Geo g;
+  if (!make_geo(&v.f, &g)) return fail(ctx, PMC_E_CORRUPT, "bad field in blob");
+  if (cap < v.region_bytes) return fail(ctx, PMC_E_NOMEM, "need %llu bytes", (unsigned long long)v.region_bytes);
+  const uint8_t* region = (const uint8_t*)host_buf + v.region_off;
+  pmc_store* s = new pmc_store();
+  s->f = v.f;
+  s->g = g;
+  s->n = v.n;
+  s->d_base = (const uint8_t*)d_streams;
+  uint64_t off = 0;
+  for (int i = 0; i < v.n; ++i) {
+    const uint64_t* r = &v.rec[8 * i];
+    double tau, linf;
+    std::memcpy(&tau, &r[0], 8);
+    std::memcpy(&linf, &r[1], 8);
+    off = align256(off);
+    uint64_t words = 0;
+    if (!(tau > 0.0) || !std::isfinite(tau) || (i > 0 && !(tau < s->tau[i - 1])) ||
+        !check_stream(region + off, r[2], &v.f, g, tau, &words)) {
+      delete s;
+      return fail(ctx, PMC_E_CORRUPT, "component %d: malformed stream", i);
+    }
+    s->tau.push_back(tau);
+    s->linf.push_back(linf);
+    s->minexp.push_back(floor_log2(tau));
+    s->bytes.push_back(r[2]);
+    s->offset.push_back(off);
+    s->words.push_back(words);
+    s->nempty.push_back(r[3]);
+    s->ncoded.push_back(r[4]);
+    s->nraw.push_back(r[5]);
+    s->nesc.push_back(r[6]);
+    s->nmiss.push_back(r[7]);
+    off += r[2];
+  }
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_streams, region, v.region_bytes, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    delete s;
+    return hipfail(ctx, e, "stream upload");
+  }
+  *out = s;
+  return PMC_OK;
+}
+
+void pmc_store_free(pmc_store* s) { delete s; }
+
+}  // extern "C"

@@ -1,0 +1,497 @@
+// codec_device.hpp -- device-side pieces of the zfp-style fixed-accuracy block
+// codec for CDNA4 (gfx950).  One lane owns one 4x4x4 block: the 64 values, the
+// quantised integers and the negabinary coefficients all live in registers
+// (fully unrolled loops with compile-time indices), so the coefficient
+// reordering is free register renaming.  Bit planes are produced 16 at a time
+// by an in-register 32x32 bit-matrix transpose instead of 64 bit extractions
+// per plane.
+//
+// The codec realises, for d = 3, the compressor the paper plugs into its
+// multi-component loop (Sec. 4, Alg. 1 and Alg. 2): one common exponent per
+// block and component (Sec. 4.4), a decorrelating block transform with bit-plane
+// coding (Sec. 5, compressor list), group tests over bit planes (Sec. 2), and
+// blocks of 4^d values that decode independently (Sec. 6.1).  Format version 1.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pmc {
+
+constexpr int kVals = 64;         // values per block
+constexpr int kChunkBlocks = 16;  // blocks per chunk (unit of the stream index)
+constexpr int kGuard = 8;         // guard planes 2(d+1) for d = 3
+constexpr int kHeaderBytes = 64;  // stream header
+constexpr uint32_t kMagic = 0x31434D50u;
+constexpr int kVersion = 1;
+constexpr int kMaxComponents = 32;
+
+template <class T> struct FT;
+template <> struct FT<float> {
+  typedef uint32_t U;  // P-bit unsigned word
+  typedef int32_t S;   // P-bit signed word
+  static constexpr int P = 32, EBITS = 8, BIAS = 127, MANT = 23, CODE = 1;
+  static constexpr uint32_t NB = 0xAAAAAAAAu;
+  static constexpr int RAW_BITS = 2 + kVals * 32;
+};
+template <> struct FT<double> {
+  typedef uint64_t U;
+  typedef int64_t S;
+  static constexpr int P = 64, EBITS = 11, BIAS = 1023, MANT = 52, CODE = 2;
+  static constexpr uint64_t NB = 0xAAAAAAAAAAAAAAAAull;
+  static constexpr int RAW_BITS = 2 + kVals * 64;
+};
+
+// capacity of one chunk in 32-bit words: 16 raw blocks (coded blocks are never
+// larger than raw ones, the acceptance rule falls back to raw first)
+template <class T> constexpr int chunk_cap_words() {
+  return (kChunkBlocks * FT<T>::RAW_BITS + 31) / 32;
+}
+
+// ---------------------------------------------------------------------------
+// coefficient order: total sequency lx+ly+lz ascending, ties by local index.
+// Generated at compile time level by level.
+struct Order {
+  int8_t at[64];
+};
+constexpr Order make_order() {
+  Order o{};
+  int r = 0;
+  for (int level = 0; level <= 9; ++level)
+    for (int l = 0; l < 64; ++l)
+      if ((l & 3) + ((l >> 2) & 3) + ((l >> 4) & 3) == level) o.at[r++] = (int8_t)l;
+  return o;
+}
+constexpr Order kOrder = make_order();
+
+// ---------------------------------------------------------------------------
+// wrapping integer helpers (two's complement P-bit words)
+template <class S> __device__ __forceinline__ S wadd(S a, S b) {
+  typedef typename std::make_unsigned<S>::type W;
+  return (S)((W)a + (W)b);
+}
+template <class S> __device__ __forceinline__ S wsub(S a, S b) {
+  typedef typename std::make_unsigned<S>::type W;
+  return (S)((W)a - (W)b);
+}
+template <class S> __device__ __forceinline__ S wdbl(S a) {
+  typedef typename std::make_unsigned<S>::type W;
+  return (S)((W)a << 1);
+}
+template <class S> __device__ __forceinline__ S half(S a) { return a >> 1; }  // floor(a/2)
+
+// 4-point lifting realisation of the basis (1/16)[[4,4,4,4],[5,1,-1,-5],
+// [-4,4,4,-4],[-2,6,-6,2]]: the sums of the outer and inner pairs give the
+// DC and second-order terms; the two half-differences are mixed by one
+// halving step and two lifting steps into the first- and third-order terms.
+template <class S> __device__ __forceinline__ void lift_fwd(S& a, S& b, S& c, S& d) {
+  S s0 = half(wadd(a, d)), t0 = wsub(a, s0);
+  S s1 = half(wadd(b, c)), t1 = wsub(b, s1);
+  S dc = half(wadd(s0, s1)), q2 = wsub(s1, dc);
+  S w = half(wadd(t0, t1));
+  S q3 = wsub(t1, half(w));
+  S q1 = wsub(w, half(q3));
+  a = dc; b = q1; c = q2; d = q3;
+}
+template <class S> __device__ __forceinline__ void lift_inv(S& a, S& b, S& c, S& d) {
+  S dc = a, q1 = b, q2 = c, q3 = d;
+  S w = wadd(q1, half(q3));
+  S t1 = wadd(q3, half(w));
+  S t0 = wsub(wdbl(w), t1);
+  S s1 = wadd(q2, dc);
+  S s0 = wsub(wdbl(dc), s1);
+  a = wadd(t0, s0);
+  d = wsub(wdbl(s0), a);
+  b = wadd(t1, s1);
+  c = wsub(wdbl(s1), b);
+}
+
+// separable forward transform on local index l = lx + 4 ly + 16 lz
+template <class S> __device__ __forceinline__ void xform_fwd(S q[64]) {
+#pragma unroll
+  for (int l = 0; l < 16; ++l) {  // x lines: base 4*l
+    const int b = 4 * l;
+    lift_fwd(q[b], q[b + 1], q[b + 2], q[b + 3]);
+  }
+#pragma unroll
+  for (int l = 0; l < 16; ++l) {  // y lines: base 16*z + x
+    const int b = 16 * (l >> 2) + (l & 3);
+    lift_fwd(q[b], q[b + 4], q[b + 8], q[b + 12]);
+  }
+#pragma unroll
+  for (int l = 0; l < 16; ++l) {  // z lines: base 4*y + x
+    const int b = l;
+    lift_fwd(q[b], q[b + 16], q[b + 32], q[b + 48]);
+  }
+}
+template <class S> __device__ __forceinline__ void xform_inv(S q[64]) {
+#pragma unroll
+  for (int l = 0; l < 16; ++l) {
+    const int b = l;
+    lift_inv(q[b], q[b + 16], q[b + 32], q[b + 48]);
+  }
+#pragma unroll
+  for (int l = 0; l < 16; ++l) {
+    const int b = 16 * (l >> 2) + (l & 3);
+    lift_inv(q[b], q[b + 4], q[b + 8], q[b + 12]);
+  }
+#pragma unroll
+  for (int l = 0; l < 16; ++l) {
+    const int b = 4 * l;
+    lift_inv(q[b], q[b + 1], q[b + 2], q[b + 3]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 32x32 bit-matrix transpose in registers: afterwards A[r] bit c equals the
+// old A[c] bit r.  Recursive block swap with strides 16, 8, 4, 2, 1.
+template <int J, uint32_t M> __device__ __forceinline__ void tstage(uint32_t A[32]) {
+#pragma unroll
+  for (int k = 0; k < 32; ++k) {
+    if (k & J) continue;
+    uint32_t t = ((A[k] >> J) ^ A[k + J]) & M;
+    A[k + J] ^= t;
+    A[k] ^= t << J;
+  }
+}
+__device__ __forceinline__ void transpose32(uint32_t A[32]) {
+  tstage<16, 0x0000FFFFu>(A);
+  tstage<8, 0x00FF00FFu>(A);
+  tstage<4, 0x0F0F0F0Fu>(A);
+  tstage<2, 0x33333333u>(A);
+  tstage<1, 0x55555555u>(A);
+}
+
+// 16 bits [base, base+16) of coefficients j and j+32 packed as one word
+__device__ __forceinline__ uint32_t slice16(uint32_t v, int base) { return (v >> base) & 0xFFFFu; }
+__device__ __forceinline__ uint32_t slice16(uint64_t v, int base) {
+  return (uint32_t)(v >> base) & 0xFFFFu;
+}
+
+// planes [base, base+16) of the 64 coefficients as 32 words T:
+//   plane base+r has coefficients 0..31 in T[r] and 32..63 in T[16+r]
+template <class U> __device__ __forceinline__ void plane_group(const U u[64], int base, uint32_t T[32]) {
+#pragma unroll
+  for (int j = 0; j < 32; ++j) T[j] = slice16(u[j], base) | (slice16(u[j + 32], base) << 16);
+  transpose32(T);
+}
+
+// bits one plane costs with the group-testing coder, given the significant
+// prefix n (updated); closed form of the coder's emissions
+__device__ __forceinline__ uint32_t plane_cost(uint64_t wd, uint32_t& n) {
+  uint32_t c = n;
+  if (n < 64) {
+    uint64_t rest = wd >> n;
+    if (rest == 0) {
+      c += 1;
+    } else {
+      uint32_t m = (uint32_t)__popcll(rest);
+      uint32_t h = 63u - (uint32_t)__clzll(rest) + n;
+      c += m + (h - n + 1) + (h < 63 ? 1u : 0u) - (h == 63 ? 1u : 0u);
+      n = h + 1;
+    }
+  }
+  return c;
+}
+
+// ---------------------------------------------------------------------------
+// LDS bit writer: bits LSB-first at an arbitrary start bit of a zeroed word
+// buffer; words shared with neighbouring lanes are merged with ds_or.
+struct LdsBits {
+  uint32_t* buf;
+  uint32_t word;
+  uint32_t nacc;
+  uint64_t acc;
+  __device__ __forceinline__ void init(uint32_t* b, uint32_t bitpos) {
+    buf = b;
+    word = bitpos >> 5;
+    nacc = bitpos & 31u;
+    acc = 0;
+  }
+  // count <= 32, value holds only its low `count` bits
+  __device__ __forceinline__ void put(uint64_t value, uint32_t count) {
+    acc |= value << nacc;
+    nacc += count;
+    if (nacc >= 32) {
+      atomicOr(&buf[word], (uint32_t)acc);
+      ++word;
+      acc >>= 32;
+      nacc -= 32;
+    }
+  }
+  // count <= 64
+  __device__ __forceinline__ void put64(uint64_t value, uint32_t count) {
+    if (count > 32) {
+      put(value & 0xFFFFFFFFull, 32);
+      put(value >> 32, count - 32);
+    } else {
+      put(value, count);
+    }
+  }
+  __device__ __forceinline__ void flush() {
+    if (nacc > 0) atomicOr(&buf[word], (uint32_t)acc);
+  }
+};
+
+// emit one plane with the group-testing coder, n = significant prefix
+__device__ __forceinline__ void plane_emit(LdsBits& w, uint64_t wd, uint32_t& n) {
+  if (n > 0) w.put64(n == 64 ? wd : (wd & ((1ull << n) - 1ull)), n);
+  if (n < 64) {
+    uint64_t rest = wd >> n;
+    while (rest != 0) {
+      uint32_t z = (uint32_t)__builtin_ctzll(rest);
+      uint32_t j = n + z;
+      if (j == 63) {  // the one at the last position is implied
+        w.put64(1ull, z + 1);
+        n = 64;
+        rest = 0;
+      } else {
+        w.put64(1ull | (1ull << (z + 1)), z + 2);
+        n = j + 1;
+        rest >>= (z + 1);
+      }
+    }
+    if (n < 64) w.put(0, 1);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// global-memory bit reader over one chunk [p, end) (never reads past end)
+struct GBits {
+  const uint32_t* p;
+  const uint32_t* end;
+  uint64_t buf;
+  uint32_t nbuf;
+  uint32_t overrun;  // words requested past the end
+  __device__ __forceinline__ void init(const uint32_t* begin, const uint32_t* e) {
+    p = begin;
+    end = e;
+    buf = 0;
+    nbuf = 0;
+    overrun = 0;
+  }
+  __device__ __forceinline__ void refill() {
+    if (nbuf <= 32) {
+      uint32_t v = 0;
+      if (p < end) v = *p;
+      else overrun = 1;
+      ++p;
+      buf |= (uint64_t)v << nbuf;
+      nbuf += 32;
+    }
+  }
+  __device__ __forceinline__ uint32_t get(uint32_t count) {  // count <= 32
+    refill();
+    uint64_t v = count == 32 ? (buf & 0xFFFFFFFFull) : (buf & ((1ull << count) - 1ull));
+    buf >>= count;
+    nbuf -= count;
+    return (uint32_t)v;
+  }
+  __device__ __forceinline__ uint64_t get64(uint32_t count) {  // count <= 64
+    if (count > 32) {
+      uint64_t lo = get(32);
+      return lo | ((uint64_t)get(count - 32) << 32);
+    }
+    return get(count);
+  }
+  __device__ __forceinline__ void skip(uint32_t count) {  // count <= 32
+    refill();
+    buf >>= count;
+    nbuf -= count;
+  }
+  // bits consumed past the end of the chunk: the partially used buffer words
+  // beyond `end` are fine as long as their bits were not consumed
+  __device__ __forceinline__ bool bad() const {
+    if (!overrun) return false;
+    // p - end words were fetched past the end; nbuf of them are unconsumed
+    int64_t past_bits = (int64_t)(p - end) * 32 - (int64_t)nbuf;
+    return past_bits > 0;
+  }
+};
+
+__device__ __forceinline__ uint64_t plane_read(GBits& r, uint32_t& n) {
+  uint64_t wd = 0;
+  if (n > 0) wd = r.get64(n);
+  while (n < 64) {
+    if (!r.get(1)) break;  // negative group test
+    for (;;) {
+      if (n == 63) {  // implied one
+        wd |= 1ull << 63;
+        n = 64;
+        break;
+      }
+      r.refill();
+      uint32_t look = 63u - n;
+      if (look > 32u) look = 32u;
+      uint64_t window = r.buf & ((1ull << look) - 1ull);
+      if (window != 0) {
+        uint32_t z = (uint32_t)__builtin_ctzll(window);
+        r.skip(z + 1);
+        wd |= 1ull << (n + z);
+        n = n + z + 1;
+        break;
+      }
+      r.skip(look);
+      n += look;
+    }
+  }
+  return wd;
+}
+
+// ---------------------------------------------------------------------------
+// block-floating-point quantisation and its inverse
+__device__ __forceinline__ int32_t quantize(float e, int emax) {
+  return (int32_t)__builtin_ldexpf(e, 30 - emax);  // exact scaling, truncation
+}
+__device__ __forceinline__ int64_t quantize(double e, int emax) {
+  return (int64_t)__builtin_ldexp(e, 62 - emax);
+}
+// q * 2^(emax-30) with one rounding: exact in double, then the cast rounds
+__device__ __forceinline__ float dequantize(int32_t q, int emax) {
+  return (float)__builtin_ldexp((double)q, emax - 30);
+}
+// q * 2^(emax-62) with one rounding to double.  The int64 -> double
+// conversion rounds once and the scaling is exact while the result is normal;
+// when it would be subnormal the rounding is done on the integer instead.
+__device__ __forceinline__ double dequantize(int64_t q, int emax) {
+  if (q == 0) return 0.0;
+  uint64_t a = q < 0 ? (uint64_t)0 - (uint64_t)q : (uint64_t)q;
+  int lead = 63 - __clzll(a);  // leading bit position
+  int s = emax - 62;
+  if (lead + s >= -1022) return __builtin_ldexp((double)q, s);
+  // subnormal: units of 2^-1074, shift right by r with round-half-even
+  int r = -(s + 1074);
+  uint64_t m;
+  if (r <= 0) {
+    m = a << (-r);
+  } else if (r >= 64) {
+    m = 0;  // a < 2^63 so a * 2^-64 < 1/2
+  } else {
+    m = a >> r;
+    uint64_t rem = a & ((1ull << r) - 1ull);
+    uint64_t halfw = 1ull << (r - 1);
+    if (rem > halfw || (rem == halfw && (m & 1ull))) ++m;
+  }
+  uint64_t bits = m | (q < 0 ? 0x8000000000000000ull : 0ull);
+  return __longlong_as_double((long long)bits);
+}
+
+__device__ __forceinline__ uint32_t abs_bits(float v) { return __float_as_uint(v) & 0x7FFFFFFFu; }
+__device__ __forceinline__ uint64_t abs_bits(double v) {
+  return (uint64_t)__double_as_longlong(v) & 0x7FFFFFFFFFFFFFFFull;
+}
+__device__ __forceinline__ uint32_t raw_bits_lo(float v) { return __float_as_uint(v); }
+__device__ __forceinline__ uint64_t raw_bits_lo(double v) { return (uint64_t)__double_as_longlong(v); }
+__device__ __forceinline__ float from_raw(uint32_t b, float) { return __uint_as_float(b); }
+__device__ __forceinline__ double from_raw(uint64_t b, double) {
+  return __longlong_as_double((long long)b);
+}
+
+// max biased exponent -> emax (frexp convention, zero/subnormal -> 2-bias)
+template <class T> __device__ __forceinline__ int block_emax(typename FT<T>::U maxabs) {
+  int biased = (int)(maxabs >> FT<T>::MANT);
+  if (biased < 1) biased = 1;
+  return biased - FT<T>::BIAS + 1;
+}
+
+template <class T> __device__ __forceinline__ typename FT<T>::U to_nb(typename FT<T>::S q) {
+  typedef typename FT<T>::U U;
+  return ((U)q + FT<T>::NB) ^ FT<T>::NB;
+}
+template <class T> __device__ __forceinline__ typename FT<T>::S from_nb(typename FT<T>::U u) {
+  typedef typename FT<T>::U U;
+  typedef typename FT<T>::S S;
+  return (S)((u ^ FT<T>::NB) - FT<T>::NB);
+}
+
+// residual block -> negabinary coefficients in coded order (u[r])
+template <class T>
+__device__ __forceinline__ void forward_coeffs(const T e[64], int emax, typename FT<T>::U u[64]) {
+  typedef typename FT<T>::S S;
+  S q[64];
+#pragma unroll
+  for (int l = 0; l < 64; ++l) q[l] = (S)quantize(e[l], emax);
+  xform_fwd(q);
+#pragma unroll
+  for (int r = 0; r < 64; ++r) u[r] = to_nb<T>(q[kOrder.at[r]]);
+}
+
+// coefficients truncated to p planes -> decoded block values (in d[l])
+template <class T>
+__device__ __forceinline__ void inverse_values(const typename FT<T>::U u[64], int emax, T d[64]) {
+  typedef typename FT<T>::S S;
+  S q[64];
+#pragma unroll
+  for (int r = 0; r < 64; ++r) q[kOrder.at[r]] = from_nb<T>(u[r]);
+  xform_inv(q);
+#pragma unroll
+  for (int l = 0; l < 64; ++l) d[l] = dequantize(q[l], emax);
+}
+
+template <class U> __device__ __forceinline__ U plane_mask(int P, int p) {
+  return p >= P ? ~(U)0 : ~(((U)1 << (P - p)) - (U)1);
+}
+
+// bits of p planes from the top
+template <class T> __device__ __forceinline__ uint32_t planes_cost(const typename FT<T>::U u[64], int p) {
+  constexpr int P = FT<T>::P;
+  uint32_t n = 0, bits = 0;
+  for (int g = 0; 16 * g < p; ++g) {
+    uint32_t Tw[32];
+    plane_group(u, P - 16 * (g + 1), Tw);
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      if (16 * g + t < p) {
+        uint64_t wd = (uint64_t)Tw[15 - t] | ((uint64_t)Tw[31 - t] << 32);
+        bits += plane_cost(wd, n);
+      }
+    }
+  }
+  return bits;
+}
+
+template <class T> __device__ __forceinline__ void planes_emit(LdsBits& w, const typename FT<T>::U u[64], int p) {
+  constexpr int P = FT<T>::P;
+  uint32_t n = 0;
+  for (int g = 0; 16 * g < p; ++g) {
+    uint32_t Tw[32];
+    plane_group(u, P - 16 * (g + 1), Tw);
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      if (16 * g + t < p) {
+        uint64_t wd = (uint64_t)Tw[15 - t] | ((uint64_t)Tw[31 - t] << 32);
+        plane_emit(w, wd, n);
+      }
+    }
+  }
+}
+
+// read p planes from the top into u (zero below)
+template <class T> __device__ __forceinline__ void planes_read(GBits& r, typename FT<T>::U u[64], int p) {
+  typedef typename FT<T>::U U;
+  constexpr int P = FT<T>::P;
+#pragma unroll
+  for (int j = 0; j < 64; ++j) u[j] = 0;
+  uint32_t n = 0;
+  for (int g = 0; 16 * g < p; ++g) {
+    uint32_t Tw[32];
+#pragma unroll
+    for (int j = 0; j < 32; ++j) Tw[j] = 0;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      if (16 * g + t < p) {
+        uint64_t wd = plane_read(r, n);
+        Tw[15 - t] = (uint32_t)wd;
+        Tw[31 - t] = (uint32_t)(wd >> 32);
+      }
+    }
+    transpose32(Tw);  // back to 16-bit slices of coefficients j and j+32
+    const int base = P - 16 * (g + 1);
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+      u[j] |= (U)(Tw[j] & 0xFFFFu) << base;
+      u[j + 32] |= (U)(Tw[j] >> 16) << base;
+    }
+  }
+}
+
+}  // namespace pmc

@@ -1,0 +1,553 @@
+// kernels.hip -- HIP kernels of the multi-component codec for gfx950, and the
+// host-side launchers the C-ABI calls.
+//
+//  k_encode   one component of Alg. 1 (Sec. 4.1): residual (line 3), block
+//             coding (line 4), decode-for-verify (line 5), x~ update (line 6)
+//             and the measured error (Sec. 4.3); one lane per 4x4x4 block,
+//             one wave per 4 chunks, chunk bitstreams assembled in LDS
+//  k_scan     chunk word counts -> chunk offsets and stream size
+//  k_pack     staging -> final stream (header, chunk index, payload)
+//  k_decode   Alg. 2 (Sec. 4.2): decode components [k0, k1) of a chunk and
+//             add them left to right into x~; one lane per chunk of 16 blocks
+//  k_range    min / max / non-finite count (tau_0 = range, Sec. 5.1)
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "codec_device.hpp"
+#include "launch.hpp"
+
+namespace pmc {
+
+enum { MODE_EMPTY = 0, MODE_CODED = 1, MODE_RAW = 2 };
+
+// ---------------------------------------------------------------------------
+// block gather / scatter with edge replication for partial blocks
+struct BlockPos {
+  uint64_t x0, y0, z0;
+  uint32_t vx, vy, vz;  // valid extents (1..4)
+};
+
+__device__ __forceinline__ BlockPos block_pos(const Geo& g, uint64_t blk) {
+  BlockPos b;
+  uint64_t bx = blk % g.nbx;
+  uint64_t t = blk / g.nbx;
+  uint64_t by = t % g.nby;
+  uint64_t bz = t / g.nby;
+  b.x0 = 4 * bx;
+  b.y0 = 4 * by;
+  b.z0 = 4 * bz;
+  b.vx = (uint32_t)min<uint64_t>(4, g.nx - b.x0);
+  b.vy = (uint32_t)min<uint64_t>(4, g.ny - b.y0);
+  b.vz = (uint32_t)min<uint64_t>(4, g.nz - b.z0);
+  return b;
+}
+
+__device__ __forceinline__ bool lvalid(const BlockPos& b, int l) {
+  return (uint32_t)(l & 3) < b.vx && (uint32_t)((l >> 2) & 3) < b.vy && (uint32_t)(l >> 4) < b.vz;
+}
+
+template <class T>
+__device__ __forceinline__ void load_block(const T* __restrict__ f, const Geo& g, const BlockPos& b, T v[64]) {
+  const bool full = b.vx == 4 && b.vy == 4 && b.vz == 4;
+  if (full && g.rows_aligned) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const uint64_t y = b.y0 + (r & 3), z = b.z0 + (r >> 2);
+      const T* row = f + b.x0 + g.nx * (y + g.ny * z);
+      if constexpr (sizeof(T) == 4) {
+        float4 q = *reinterpret_cast<const float4*>(row);
+        v[4 * r] = q.x; v[4 * r + 1] = q.y; v[4 * r + 2] = q.z; v[4 * r + 3] = q.w;
+      } else {
+        double2 q0 = *reinterpret_cast<const double2*>(row);
+        double2 q1 = *reinterpret_cast<const double2*>(row + 2);
+        v[4 * r] = q0.x; v[4 * r + 1] = q0.y; v[4 * r + 2] = q1.x; v[4 * r + 3] = q1.y;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int l = 0; l < 64; ++l) {
+      const uint64_t x = b.x0 + min<uint32_t>(l & 3, b.vx - 1);
+      const uint64_t y = b.y0 + min<uint32_t>((l >> 2) & 3, b.vy - 1);
+      const uint64_t z = b.z0 + min<uint32_t>(l >> 4, b.vz - 1);
+      v[l] = f[x + g.nx * (y + g.ny * z)];
+    }
+  }
+}
+
+template <class T>
+__device__ __forceinline__ void store_block(T* __restrict__ f, const Geo& g, const BlockPos& b, const T v[64]) {
+  const bool full = b.vx == 4 && b.vy == 4 && b.vz == 4;
+  if (full && g.rows_aligned) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const uint64_t y = b.y0 + (r & 3), z = b.z0 + (r >> 2);
+      T* row = f + b.x0 + g.nx * (y + g.ny * z);
+      if constexpr (sizeof(T) == 4) {
+        *reinterpret_cast<float4*>(row) = make_float4(v[4 * r], v[4 * r + 1], v[4 * r + 2], v[4 * r + 3]);
+      } else {
+        *reinterpret_cast<double2*>(row) = make_double2(v[4 * r], v[4 * r + 1]);
+        *reinterpret_cast<double2*>(row + 2) = make_double2(v[4 * r + 2], v[4 * r + 3]);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int l = 0; l < 64; ++l) {
+      if (lvalid(b, l)) f[b.x0 + (l & 3) + g.nx * (b.y0 + ((l >> 2) & 3) + g.ny * (b.z0 + (l >> 4)))] = v[l];
+    }
+  }
+}
+
+// NaN-propagating max, matching "take a if not a <= m"
+__device__ __forceinline__ double nmax(double m, double a) { return a <= m ? m : a; }
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v = nmax(v, __shfl_xor(v, d, 64));
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// encode one component
+template <class T>
+__global__ __launch_bounds__(64) void k_encode(EncArgs<T> a) {
+  typedef typename FT<T>::U U;
+  constexpr int P = FT<T>::P;
+  constexpr int CAP = chunk_cap_words<T>();
+  __shared__ uint32_t lds[4 * CAP];
+
+  const uint32_t lane = threadIdx.x;
+  const uint64_t blk = (uint64_t)blockIdx.x * 64 + lane;
+  const bool active = blk < a.g.nblocks;
+
+  for (uint32_t i = lane; i < 4 * CAP; i += 64) lds[i] = 0;
+
+  BlockPos bp = block_pos(a.g, active ? blk : 0);
+  T xv[64], tv[64];
+  load_block(a.x, a.g, bp, xv);
+  if (a.first) {
+#pragma unroll
+    for (int l = 0; l < 64; ++l) tv[l] = (T)0;
+  } else {
+    load_block(a.xt, a.g, bp, tv);
+  }
+
+  // residual statistics: exponent, all-zero test, error before this component
+  U maxabs = 0;
+  double eb = 0.0;
+  bool nonfinite = false;
+#pragma unroll
+  for (int l = 0; l < 64; ++l) {
+    T ev = xv[l] - tv[l];
+    U ab = abs_bits(ev);
+    maxabs = ab > maxabs ? ab : maxabs;
+    if (lvalid(bp, l)) eb = nmax(eb, fabs((double)xv[l] - (double)tv[l]));
+    nonfinite |= !isfinite(xv[l]);
+  }
+  const int emax = block_emax<T>(maxabs);
+  int p = emax - a.minexp + kGuard;
+  p = p < 0 ? 0 : (p > P ? P : p);
+  int mode = MODE_EMPTY, delta = 0;
+  uint32_t nbits = 1;
+  double err = eb;
+
+  if (active && maxabs != 0) {
+    for (;;) {
+      U u[64];
+      {
+        T e[64];
+#pragma unroll
+        for (int l = 0; l < 64; ++l) e[l] = xv[l] - tv[l];
+        forward_coeffs<T>(e, emax, u);
+      }
+      bool feasible = false;
+      uint32_t cb = 0;
+      if (p >= 1 && p <= P) {
+        cb = 2u + (uint32_t)(delta + 1) + (uint32_t)FT<T>::EBITS + planes_cost<T>(u, p);
+        feasible = cb <= (uint32_t)FT<T>::RAW_BITS;
+      }
+      if (feasible) {
+        const U m = plane_mask<U>(P, p);
+#pragma unroll
+        for (int r = 0; r < 64; ++r) u[r] &= m;
+        T d[64];
+        inverse_values<T>(u, emax, d);
+        double ea = 0.0;
+#pragma unroll
+        for (int l = 0; l < 64; ++l) {
+          d[l] = tv[l] + d[l];  // x~_{i-1} + x_i in the field precision
+          if (lvalid(bp, l)) ea = nmax(ea, fabs((double)xv[l] - (double)d[l]));
+        }
+        if (ea <= a.tau && ea <= eb) {
+          mode = MODE_CODED;
+          nbits = cb;
+          err = ea;
+          if (!a.last) store_block(a.xt, a.g, bp, d);
+          break;
+        }
+      }
+      if (eb <= a.tau) {
+        mode = MODE_EMPTY;
+        nbits = 1;
+        err = eb;
+        break;
+      }
+      if (!feasible) {
+        mode = MODE_RAW;
+        nbits = (uint32_t)FT<T>::RAW_BITS;
+        break;
+      }
+      ++p;
+      ++delta;
+    }
+  }
+  bool miss = false;
+  if (active && mode == MODE_RAW) {
+    T d[64];
+    double ea = 0.0;
+#pragma unroll
+    for (int l = 0; l < 64; ++l) {
+      d[l] = tv[l] + (xv[l] - tv[l]);
+      if (lvalid(bp, l)) ea = nmax(ea, fabs((double)xv[l] - (double)d[l]));
+    }
+    err = ea;
+    miss = !(ea <= a.tau && ea <= eb);
+    if (!a.last) store_block(a.xt, a.g, bp, d);
+  } else if (active && mode == MODE_EMPTY) {
+    miss = !(eb <= a.tau);
+    // x~_i = x~_{i-1} + 0: only a fresh x~ (first component) needs writing
+    if (a.first && !a.last) {
+      T d[64];
+#pragma unroll
+      for (int l = 0; l < 64; ++l) d[l] = tv[l] + (T)0;
+      store_block(a.xt, a.g, bp, d);
+    }
+  }
+  if (!active) {
+    err = 0.0;
+    miss = false;
+    nbits = 0;
+  }
+
+  // per-component statistics
+  {
+    const unsigned long long be = __ballot(active && mode == MODE_EMPTY);
+    const unsigned long long bc = __ballot(active && mode == MODE_CODED);
+    const unsigned long long br = __ballot(active && mode == MODE_RAW);
+    const unsigned long long bs = __ballot(active && mode == MODE_CODED && delta > 0);
+    const unsigned long long bm = __ballot(miss);
+    const unsigned long long bn = __ballot(active && nonfinite);
+    const double wm = wave_max(err);
+    if (lane == 0) {
+      if (be) atomicAdd(&a.meta->nempty, (unsigned long long)__popcll(be));
+      if (bc) atomicAdd(&a.meta->ncoded, (unsigned long long)__popcll(bc));
+      if (br) atomicAdd(&a.meta->nraw, (unsigned long long)__popcll(br));
+      if (bs) atomicAdd(&a.meta->nesc, (unsigned long long)__popcll(bs));
+      if (bm) atomicAdd(&a.meta->nmiss, (unsigned long long)__popcll(bm));
+      if (bn) atomicOr(&a.meta->flags, (unsigned int)FLAG_NONFINITE);
+      atomicMax(&a.meta->linf_bits, (unsigned long long)__double_as_longlong(wm));
+    }
+  }
+
+  // offsets of the blocks inside their chunk (16 lanes = one chunk)
+  uint32_t incl = nbits;
+#pragma unroll
+  for (int s = 1; s < 16; s <<= 1) {
+    uint32_t y = __shfl_up(incl, s, 16);
+    if ((lane & 15) >= (uint32_t)s) incl += y;
+  }
+  const uint32_t off = incl - nbits;
+  __syncthreads();  // zeroed LDS visible to every lane
+
+  if (active) {
+    LdsBits w;
+    w.init(&lds[(lane >> 4) * CAP], off);
+    if (mode == MODE_EMPTY) {
+      w.put(0, 1);
+    } else if (mode == MODE_RAW) {
+      w.put(3, 2);
+#pragma unroll
+      for (int l = 0; l < 64; ++l) {
+        T ev = xv[l] - tv[l];
+        w.put64((uint64_t)raw_bits_lo(ev), (uint32_t)P);
+      }
+    } else {
+      w.put(1, 2);  // nonempty, coded
+      for (int t = 0; t < delta; ++t) w.put(1, 1);
+      w.put(0, 1);
+      w.put((uint64_t)(emax + FT<T>::BIAS), (uint32_t)FT<T>::EBITS);
+      U u[64];
+      {
+        T e[64];
+#pragma unroll
+        for (int l = 0; l < 64; ++l) e[l] = xv[l] - tv[l];
+        forward_coeffs<T>(e, emax, u);
+      }
+      planes_emit<T>(w, u, p);
+    }
+    w.flush();
+  }
+  __syncthreads();
+
+  // copy the four chunk bitstreams to their staging slots
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const uint32_t bits = __shfl(incl, 16 * c + 15, 64);
+    const uint64_t chunk = (uint64_t)blockIdx.x * 4 + c;
+    if (chunk < a.g.nchunks) {
+      const uint32_t words = (bits + 31) / 32;
+      uint32_t* dst = a.staging + chunk * (uint64_t)CAP;
+      for (uint32_t i = lane; i < words; i += 64) dst[i] = lds[c * CAP + i];
+      if (lane == 0) a.chunk_words[chunk] = words;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// chunk offsets: exclusive prefix sum of chunk word counts (one workgroup)
+__global__ __launch_bounds__(1024) void k_scan(ScanArgs a) {
+  __shared__ unsigned long long part[1024];
+  const uint32_t t = threadIdx.x;
+  const uint64_t per = (a.nchunks + 1023) / 1024;
+  const uint64_t lo = min<uint64_t>(a.nchunks, t * per), hi = min<uint64_t>(a.nchunks, lo + per);
+  unsigned long long s = 0;
+  for (uint64_t i = lo; i < hi; ++i) s += a.chunk_words[i];
+  part[t] = s;
+  __syncthreads();
+  for (uint32_t d = 1; d < 1024; d <<= 1) {
+    unsigned long long v = t >= d ? part[t - d] : 0ull;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  unsigned long long run = part[t] - s;  // exclusive
+  bool big = false;
+  for (uint64_t i = lo; i < hi; ++i) {
+    if (run > 0xFFFFFFFFull) big = true;
+    a.offsets[i] = (uint32_t)run;
+    run += a.chunk_words[i];
+  }
+  if (big) atomicOr(&a.meta[a.comp].flags, (unsigned int)FLAG_INDEX);
+  __syncthreads();
+  if (t == 1023) {
+    CompMeta* m = &a.meta[a.comp];
+    const unsigned long long words = part[1023];
+    const unsigned long long bytes = (unsigned long long)kHeaderBytes + 4ull * a.nchunks + 4ull * words;
+    m->payload_words = words;
+    m->stream_bytes = bytes;
+    const unsigned long long end = m->stream_offset + bytes;
+    if (end > a.streams_cap) m->flags |= FLAG_OVERFLOW;
+    if (a.comp + 1 < a.ncomp) a.meta[a.comp + 1].stream_offset = (end + 255ull) & ~255ull;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// staging -> stream: header, index, payload (16 lanes per chunk)
+template <class T>
+__global__ __launch_bounds__(64) void k_pack(PackArgs a) {
+  constexpr int CAP = chunk_cap_words<T>();
+  const CompMeta* m = &a.meta[a.comp];
+  if (m->flags & (FLAG_OVERFLOW | FLAG_INDEX)) return;
+  uint8_t* base = a.streams + m->stream_offset;
+  uint32_t* index = reinterpret_cast<uint32_t*>(base + kHeaderBytes);
+  uint32_t* payload = index + a.nchunks;
+  const uint32_t lane = threadIdx.x;
+  const uint64_t chunk = (uint64_t)blockIdx.x * 4 + (lane >> 4);
+  const uint32_t sub = lane & 15;
+  if (chunk < a.nchunks) {
+    const uint32_t words = a.chunk_words[chunk];
+    const uint32_t o = a.offsets[chunk];
+    const uint32_t* src = a.staging + chunk * (uint64_t)CAP;
+    for (uint32_t i = sub; i < words; i += 16) payload[o + i] = src[i];
+    if (sub == 0) index[chunk] = o;
+  }
+  if (blockIdx.x == 0 && lane < 16) {
+    uint32_t* h = reinterpret_cast<uint32_t*>(base);
+    const uint64_t taub = (uint64_t)__double_as_longlong(a.tau);
+    uint32_t v = 0;
+    switch (lane) {
+      case 0: v = kMagic; break;
+      case 1: v = (uint32_t)kVersion | ((uint32_t)FT<T>::CODE << 16) | (3u << 24); break;
+      case 2: v = (uint32_t)a.g.nx; break;
+      case 3: v = (uint32_t)(a.g.nx >> 32); break;
+      case 4: v = (uint32_t)a.g.ny; break;
+      case 5: v = (uint32_t)(a.g.ny >> 32); break;
+      case 6: v = (uint32_t)a.g.nz; break;
+      case 7: v = (uint32_t)(a.g.nz >> 32); break;
+      case 8: v = (uint32_t)taub; break;
+      case 9: v = (uint32_t)(taub >> 32); break;
+      case 10: v = (uint32_t)a.minexp; break;
+      case 11: v = (uint32_t)kChunkBlocks; break;
+      case 12: v = (uint32_t)a.nchunks; break;
+      case 13: v = (uint32_t)(a.nchunks >> 32); break;
+      case 14: v = (uint32_t)m->payload_words; break;
+      case 15: v = (uint32_t)(m->payload_words >> 32); break;
+    }
+    h[lane] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// decode components [0, ncomp) of DecArgs and add them into x~
+template <class T>
+__global__ __launch_bounds__(64) void k_decode(DecArgs<T> a) {
+  typedef typename FT<T>::U U;
+  constexpr int P = FT<T>::P;
+  __shared__ uint32_t s_pos[kMaxDecode][64];
+  __shared__ uint32_t s_end[kMaxDecode][64];
+  __shared__ uint32_t s_n[kMaxDecode][64];
+  __shared__ unsigned long long s_buf[kMaxDecode][64];
+
+  const uint32_t lane = threadIdx.x;
+  const uint64_t chunk = (uint64_t)blockIdx.x * 64 + lane;
+  if (chunk >= a.g.nchunks) return;
+  bool bad = false;
+
+  for (int i = 0; i < a.ncomp; ++i) {
+    const uint32_t* index = reinterpret_cast<const uint32_t*>(a.s[i] + kHeaderBytes);
+    const uint32_t start = index[chunk];
+    const uint64_t stop = chunk + 1 < a.g.nchunks ? (uint64_t)index[chunk + 1] : a.words[i];
+    if (start > stop || stop > a.words[i]) bad = true;
+    s_pos[i][lane] = start;
+    s_end[i][lane] = (uint32_t)(stop < start ? start : stop);
+    s_n[i][lane] = 0;
+    s_buf[i][lane] = 0;
+  }
+
+  const uint64_t b0 = chunk * kChunkBlocks;
+  const uint64_t b1 = min<uint64_t>(a.g.nblocks, b0 + kChunkBlocks);
+  for (uint64_t blk = b0; blk < b1 && !bad; ++blk) {
+    BlockPos bp = block_pos(a.g, blk);
+    T acc[64];
+    if (a.in) {
+      load_block(a.in, a.g, bp, acc);
+    } else {
+#pragma unroll
+      for (int l = 0; l < 64; ++l) acc[l] = (T)0;
+    }
+    for (int i = 0; i < a.ncomp && !bad; ++i) {
+      const uint32_t* payload =
+          reinterpret_cast<const uint32_t*>(a.s[i] + kHeaderBytes) + a.g.nchunks;
+      GBits r;
+      r.p = payload + s_pos[i][lane];
+      r.end = payload + s_end[i][lane];
+      r.buf = s_buf[i][lane];
+      r.nbuf = s_n[i][lane];
+      r.overrun = 0;
+      if (r.get(1)) {
+        if (r.get(1)) {  // raw block
+#pragma unroll
+          for (int l = 0; l < 64; ++l) {
+            T v = from_raw((U)r.get64((uint32_t)P), (T)0);
+            acc[l] = acc[l] + v;
+          }
+        } else {
+          int delta = 0;
+          while (r.get(1)) {
+            if (++delta > P) { bad = true; break; }
+          }
+          const int emax = (int)r.get((uint32_t)FT<T>::EBITS) - FT<T>::BIAS;
+          int p = emax - a.minexp[i] + kGuard;
+          p = (p < 0 ? 0 : (p > P ? P : p)) + delta;
+          if (emax < 2 - FT<T>::BIAS || p < 1 || p > P) bad = true;
+          if (!bad) {
+            U u[64];
+            planes_read<T>(r, u, p);
+            T dv[64];
+            inverse_values<T>(u, emax, dv);
+#pragma unroll
+            for (int l = 0; l < 64; ++l) acc[l] = acc[l] + dv[l];
+          }
+        }
+      }
+      if (r.bad()) bad = true;
+      s_pos[i][lane] = (uint32_t)(r.p - payload);
+      s_buf[i][lane] = r.buf;
+      s_n[i][lane] = r.nbuf;
+    }
+    if (!bad) store_block(a.out, a.g, bp, acc);
+  }
+  if (bad) atomicOr(a.status, 1u);
+}
+
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long ordered(double v) {
+  unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_range(const T* __restrict__ x, uint64_t n, unsigned long long* out) {
+  unsigned long long lo = ~0ull, hi = 0ull, bad = 0ull;
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
+    double v = (double)x[i];
+    if (!isfinite(v)) {
+      ++bad;
+      continue;
+    }
+    unsigned long long o = ordered(v);
+    lo = o < lo ? o : lo;
+    hi = o > hi ? o : hi;
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    unsigned long long a = __shfl_xor(lo, d, 64), b = __shfl_xor(hi, d, 64), c = __shfl_xor(bad, d, 64);
+    lo = a < lo ? a : lo;
+    hi = b > hi ? b : hi;
+    bad += c;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMin(&out[0], lo);
+    atomicMax(&out[1], hi);
+    if (bad) atomicAdd(&out[2], bad);
+  }
+}
+
+__global__ void k_fill64(unsigned long long* p, uint64_t n, unsigned long long v) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+template <class T> hipError_t launch_encode(const EncArgs<T>& a, hipStream_t s) {
+  const uint64_t wgs = (a.g.nblocks + 63) / 64;
+  hipLaunchKernelGGL(k_encode<T>, dim3((uint32_t)wgs), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_scan(const ScanArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, a);
+  return hipGetLastError();
+}
+template <class T> hipError_t launch_pack(const PackArgs& a, hipStream_t s) {
+  const uint64_t wgs = (a.nchunks + 3) / 4;
+  hipLaunchKernelGGL(k_pack<T>, dim3((uint32_t)wgs), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+template <class T> hipError_t launch_decode(const DecArgs<T>& a, hipStream_t s) {
+  const uint64_t wgs = (a.g.nchunks + 63) / 64;
+  hipLaunchKernelGGL(k_decode<T>, dim3((uint32_t)wgs), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+template <class T> hipError_t launch_range(const T* x, uint64_t n, unsigned long long* out, hipStream_t s) {
+  uint64_t wgs = (n + 255) / 256;
+  if (wgs > 4096) wgs = 4096;
+  if (wgs == 0) wgs = 1;
+  hipLaunchKernelGGL(k_range<T>, dim3((uint32_t)wgs), dim3(256), 0, s, x, n, out);
+  return hipGetLastError();
+}
+hipError_t launch_fill64(unsigned long long* p, uint64_t n, unsigned long long v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill64, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+template hipError_t launch_encode<float>(const EncArgs<float>&, hipStream_t);
+template hipError_t launch_encode<double>(const EncArgs<double>&, hipStream_t);
+template hipError_t launch_pack<float>(const PackArgs&, hipStream_t);
+template hipError_t launch_pack<double>(const PackArgs&, hipStream_t);
+template hipError_t launch_decode<float>(const DecArgs<float>&, hipStream_t);
+template hipError_t launch_decode<double>(const DecArgs<double>&, hipStream_t);
+template hipError_t launch_range<float>(const float*, uint64_t, unsigned long long*, hipStream_t);
+template hipError_t launch_range<double>(const double*, uint64_t, unsigned long long*, hipStream_t);
+
+}  // namespace pmc

@@ -1,0 +1,102 @@
+// launch.hpp -- kernel argument blocks and host launchers shared by the HIP
+// kernels (kernels.hip) and the C-ABI (capi.cpp).  Internal to the library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pmc {
+
+constexpr int kMaxDecode = 16;  // components decoded by one k_decode launch
+constexpr int kMaxComps = 32;   // components per store
+constexpr uint64_t kStreamHeader = 64;
+constexpr uint32_t kStreamMagic = 0x31434D50u;  // "PMC1"
+constexpr uint32_t kStreamVersion = 1;
+
+enum : unsigned int {
+  FLAG_NONFINITE = 1u,  // NaN / Inf in the input field
+  FLAG_OVERFLOW = 2u,   // stream capacity exceeded
+  FLAG_INDEX = 4u       // payload too large for 32-bit word offsets
+};
+
+// block grid of a field: 4x4x4 blocks, x fastest; chunks of 16 blocks
+struct Geo {
+  uint64_t nx, ny, nz;
+  uint64_t nbx, nby, nbz;
+  uint64_t nblocks, nchunks;
+  int rows_aligned;  // nx % 4 == 0: block rows can use 16-byte vector access
+  int pad;
+};
+
+// per-component results kept on the device during compression
+struct CompMeta {
+  unsigned long long linf_bits;  // max measured error, float64 bits (>= 0)
+  unsigned long long nempty, ncoded, nraw, nesc, nmiss;
+  unsigned long long payload_words;
+  unsigned long long stream_offset;  // byte offset of the stream in the output
+  unsigned long long stream_bytes;
+  unsigned int flags;
+  unsigned int pad;
+  unsigned long long reserved[6];
+};
+static_assert(sizeof(CompMeta) == 128, "CompMeta layout");
+
+template <class T> struct EncArgs {
+  const T* x;
+  T* xt;  // x~_{i-1} in, x~_i out (in place)
+  Geo g;
+  double tau;
+  int minexp;
+  int first;  // x~_{i-1} = 0: not read
+  int last;   // x~_i not written
+  uint32_t* staging;
+  uint32_t* chunk_words;
+  CompMeta* meta;  // this component's entry
+};
+
+struct ScanArgs {
+  const uint32_t* chunk_words;
+  uint32_t* offsets;
+  uint64_t nchunks;
+  CompMeta* meta;  // all components
+  int comp, ncomp;
+  unsigned long long streams_cap;
+};
+
+struct PackArgs {
+  const uint32_t* staging;
+  const uint32_t* chunk_words;
+  const uint32_t* offsets;
+  uint64_t nchunks;
+  const CompMeta* meta;
+  int comp;
+  int minexp;
+  uint8_t* streams;
+  Geo g;
+  double tau;
+};
+
+template <class T> struct DecArgs {
+  const uint8_t* s[kMaxDecode];  // stream starts
+  uint64_t words[kMaxDecode];    // payload words of each stream
+  int minexp[kMaxDecode];
+  int ncomp;
+  const T* in;  // x~ to continue from; NULL = +0
+  T* out;
+  Geo g;
+  unsigned int* status;  // bit 0: malformed stream
+};
+
+template <class T> hipError_t launch_encode(const EncArgs<T>& a, hipStream_t s);
+hipError_t launch_scan(const ScanArgs& a, hipStream_t s);
+template <class T> hipError_t launch_pack(const PackArgs& a, hipStream_t s);
+template <class T> hipError_t launch_decode(const DecArgs<T>& a, hipStream_t s);
+template <class T> hipError_t launch_range(const T* x, uint64_t n, unsigned long long* out, hipStream_t s);
+hipError_t launch_fill64(unsigned long long* p, uint64_t n, unsigned long long v, hipStream_t s);
+
+// capacity of one chunk's staging slot in 32-bit words
+inline uint64_t chunk_cap_words_host(int dtype) {
+  const uint64_t raw = dtype == 1 ? 2 + 64 * 32 : 2 + 64 * 64;
+  return (16 * raw + 31) / 32;
+}
+
+}  // namespace pmc

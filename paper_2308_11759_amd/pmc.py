@@ -1,0 +1,276 @@
+"""Python binding of the C-ABI in include/pmc.h (ctypes; argument marshalling only).
+
+PyTorch provides device memory and the HIP stream; every step of compression
+and retrieval runs in the HIP kernels of libpmc.so.  There is no CPU fallback:
+importing this module without the built library raises.
+
+Names follow the paper (Magri & Lindstrom): ``compress`` is Alg. 1 (Sec. 4.1),
+``retrieve`` is Alg. 2 (Sec. 4.2), ``refine`` continues Alg. 2 from a cached
+partial sum, ``select_k`` picks the component count for a tolerance from the
+per-component metadata (Sec. 6.2).
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpmc.so")
+
+OK, E_ARG, E_NONFINITE, E_NOMEM, E_CORRUPT, E_UNREACHABLE, E_BOUND, E_DEVICE = 0, -1, -2, -3, -4, -5, -6, -7
+F32, F64 = 1, 2
+OPT_FUSED_DECODE, OPT_SYNC_CHECK = 1, 2
+_NAMES = {0: "OK", -1: "E_ARG", -2: "E_NONFINITE", -3: "E_NOMEM", -4: "E_CORRUPT", -5: "E_UNREACHABLE",
+          -6: "E_BOUND", -7: "E_DEVICE"}
+
+
+class PmcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s (%d): %s" % (_NAMES.get(status, "?"), status, msg))
+        self.status = status
+
+
+class Field(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_uint64), ("ny", ctypes.c_uint64), ("nz", ctypes.c_uint64),
+                ("dtype", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+_lib = None
+
+# every exported symbol of include/pmc.h with (restype, argtypes)
+_vp, _sz, _u64, _dbl, _int = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint64, ctypes.c_double, ctypes.c_int
+_P = ctypes.POINTER
+SIGNATURES = {
+    "pmc_ctx_create": (_int, [_int, _vp, _P(_vp)]),
+    "pmc_ctx_destroy": (None, [_vp]),
+    "pmc_last_error": (ctypes.c_char_p, [_vp]),
+    "pmc_ctx_set_option": (_int, [_vp, _int, _int]),
+    "pmc_range": (_int, [_vp, _P(Field), _vp, _vp, _sz, _P(_dbl), _P(_dbl), _P(_u64)]),
+    "pmc_compress_sizes": (_int, [_P(Field), _int, _P(_sz), _P(_sz)]),
+    "pmc_compress": (_int, [_vp, _P(Field), _vp, _int, _P(_dbl), _vp, _sz, _vp, _sz, _P(_vp)]),
+    "pmc_store_info": (_int, [_vp, _P(_int), _P(_dbl), _P(_dbl), _P(_u64), _P(_u64), _P(_u64)]),
+    "pmc_store_field": (_int, [_vp, _P(Field)]),
+    "pmc_store_stream": (_int, [_vp, _int, _P(_vp), _P(_u64)]),
+    "pmc_select_k": (_int, [_vp, _dbl, _int, _P(_int)]),
+    "pmc_decode_ws_bytes": (_sz, []),
+    "pmc_retrieve": (_int, [_vp, _vp, _int, _vp, _vp, _sz]),
+    "pmc_refine": (_int, [_vp, _vp, _int, _int, _vp, _vp, _sz]),
+    "pmc_store_serialize": (_int, [_vp, _vp, _vp, _sz, _P(_sz)]),
+    "pmc_store_device_bytes": (_int, [_vp, _sz, _P(_sz)]),
+    "pmc_store_deserialize": (_int, [_vp, _vp, _sz, _vp, _sz, _P(_vp)]),
+    "pmc_store_free": (None, [_vp]),
+}
+
+
+def load(path=LIB_PATH):
+    """Load libpmc.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("libpmc.so not built (run __graft_entry__.build()): %s" % path)
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _dtype_code(dt):
+    if dt == torch.float32:
+        return F32
+    if dt == torch.float64:
+        return F64
+    raise TypeError("fields must be float32 or float64, got %s" % dt)
+
+
+def field_of(t):
+    """Field descriptor of a contiguous tensor with shape (nz, ny, nx), (ny, nx) or (nx,)."""
+    if not t.is_contiguous():
+        raise ValueError("field tensor must be contiguous")
+    shape = list(t.shape)
+    if not 1 <= len(shape) <= 3:
+        raise ValueError("fields are 1-D to 3-D")
+    dims = list(reversed(shape)) + [1] * (3 - len(shape))
+    f = Field()
+    f.nx, f.ny, f.nz = dims
+    f.dtype = _dtype_code(t.dtype)
+    return f
+
+
+def _torch_dtype(code):
+    return torch.float32 if code == F32 else torch.float64
+
+
+class Context:
+    """A pmc_ctx bound to a device and a HIP stream (default: torch's current)."""
+
+    def __init__(self, device=0, stream=None):
+        self.lib = load()
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        idx = self.device.index or 0
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        self._check(self.lib.pmc_ctx_create(idx, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)), ctx=None)
+        self.handle = h
+        self._ws = None
+        self._dec_ws = torch.empty(int(self.lib.pmc_decode_ws_bytes()), dtype=torch.uint8, device=self.device)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.pmc_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, ctx="self"):
+        if st != OK:
+            msg = ""
+            if ctx == "self" and getattr(self, "handle", None):
+                msg = (self.lib.pmc_last_error(self.handle) or b"").decode()
+            raise PmcError(st, msg)
+
+    def set_option(self, option, value):
+        self._check(self.lib.pmc_ctx_set_option(self.handle, option, int(value)))
+
+    def _workspace(self, nbytes):
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = None
+            self._ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def range(self, x):
+        """(min, max, non-finite count) of a device field."""
+        f = field_of(x)
+        ws = self._workspace(256)
+        lo, hi, bad = ctypes.c_double(), ctypes.c_double(), ctypes.c_uint64()
+        self._check(self.lib.pmc_range(self.handle, ctypes.byref(f), ctypes.c_void_p(x.data_ptr()),
+                                       ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.byref(lo),
+                                       ctypes.byref(hi), ctypes.byref(bad)))
+        return lo.value, hi.value, bad.value
+
+    def compress_sizes(self, x, n):
+        f = field_of(x)
+        ws, cap = ctypes.c_size_t(), ctypes.c_size_t()
+        self._check(self.lib.pmc_compress_sizes(ctypes.byref(f), int(n), ctypes.byref(ws), ctypes.byref(cap)))
+        return ws.value, cap.value
+
+    def compress(self, x, taus, streams=None):
+        """Alg. 1: compress a device field into len(taus) components."""
+        taus = [float(t) for t in taus]
+        n = len(taus)
+        f = field_of(x)
+        ws_bytes, cap1 = self.compress_sizes(x, n)
+        ws = self._workspace(ws_bytes)
+        if streams is None:
+            streams = torch.empty(cap1 * n, dtype=torch.uint8, device=self.device)
+        tau_arr = (ctypes.c_double * n)(*taus)
+        h = ctypes.c_void_p()
+        st = self.lib.pmc_compress(self.handle, ctypes.byref(f), ctypes.c_void_p(x.data_ptr()), n, tau_arr,
+                                   ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(streams.data_ptr()),
+                                   streams.numel(), ctypes.byref(h))
+        if st != OK:
+            if h.value:
+                self.lib.pmc_store_free(h)
+            self._check(st)
+        return Store(self, h, streams)
+
+    def retrieve(self, store, k, out=None):
+        """Alg. 2: x~_k = sum of the first k decoded components (left to right)."""
+        if out is None:
+            out = torch.empty(store.shape, dtype=store.dtype, device=self.device)
+        self._check(self.lib.pmc_retrieve(self.handle, store.handle, int(k), ctypes.c_void_p(out.data_ptr()),
+                                          ctypes.c_void_p(self._dec_ws.data_ptr()), self._dec_ws.numel()))
+        return out
+
+    def refine(self, store, k_from, k_to, xt):
+        """Add components k_from+1..k_to to x~_{k_from} in place."""
+        self._check(self.lib.pmc_refine(self.handle, store.handle, int(k_from), int(k_to),
+                                        ctypes.c_void_p(xt.data_ptr()), ctypes.c_void_p(self._dec_ws.data_ptr()),
+                                        self._dec_ws.numel()))
+        return xt
+
+    def deserialize(self, blob, streams=None):
+        """Rebuild a store from bytes written by Store.serialize (or any valid blob)."""
+        blob = bytes(blob)
+        need = ctypes.c_size_t()
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        self._check(self.lib.pmc_store_device_bytes(buf, len(blob), ctypes.byref(need)), ctx=None)
+        if streams is None:
+            streams = torch.empty(max(need.value, 256), dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        self._check(self.lib.pmc_store_deserialize(self.handle, buf, len(blob), ctypes.c_void_p(streams.data_ptr()),
+                                                   streams.numel(), ctypes.byref(h)))
+        return Store(self, h, streams)
+
+
+class Store:
+    """Handle of a pmc_store plus the device buffer that holds its streams."""
+
+    def __init__(self, ctx, handle, streams):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        self.handle = handle
+        self.streams = streams  # keeps the caller-owned stream memory alive
+        f = Field()
+        ctx._check(self.lib.pmc_store_field(handle, ctypes.byref(f)))
+        self.field = f
+        shape = [f.nz, f.ny, f.nx]
+        self.shape = tuple(int(s) for s in shape)
+        self.dtype = _torch_dtype(f.dtype)
+        self.info = self._info()
+
+    def _info(self):
+        n = ctypes.c_int()
+        self.lib.pmc_store_info(self.handle, ctypes.byref(n), None, None, None, None, None)
+        k = n.value
+        tau, linf = (ctypes.c_double * k)(), (ctypes.c_double * k)()
+        by, raw, esc = (ctypes.c_uint64 * k)(), (ctypes.c_uint64 * k)(), (ctypes.c_uint64 * k)()
+        self.lib.pmc_store_info(self.handle, ctypes.byref(n), tau, linf, by, raw, esc)
+        return [dict(tau=tau[i], linf=linf[i], bytes=by[i], nraw=raw[i], nesc=esc[i]) for i in range(k)]
+
+    @property
+    def n(self):
+        return len(self.info)
+
+    def select_k(self, tol, use_measured=False):
+        k = ctypes.c_int()
+        st = self.lib.pmc_select_k(self.handle, float(tol), int(bool(use_measured)), ctypes.byref(k))
+        if st == E_UNREACHABLE:
+            return None
+        self.ctx._check(st)
+        return k.value
+
+    def stream(self, i):
+        """Bytes of component i's stream as a uint8 device tensor view."""
+        p, nb = ctypes.c_void_p(), ctypes.c_uint64()
+        self.ctx._check(self.lib.pmc_store_stream(self.handle, int(i), ctypes.byref(p), ctypes.byref(nb)))
+        off = p.value - self.streams.data_ptr()
+        return self.streams[off:off + nb.value]
+
+    def serialize(self):
+        used = ctypes.c_size_t()
+        self.ctx._check(self.lib.pmc_store_serialize(self.ctx.handle, self.handle, None, 0, ctypes.byref(used)))
+        buf = ctypes.create_string_buffer(used.value)
+        self.ctx._check(self.lib.pmc_store_serialize(self.ctx.handle, self.handle, buf, used.value,
+                                                     ctypes.byref(used)))
+        return buf.raw[:used.value]
+
+    def free(self):
+        if getattr(self, "handle", None):
+            self.lib.pmc_store_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

@@ -1,0 +1,222 @@
+"""GPU (HIP, gfx950) vs CPU oracle, element by element, through the C-ABI.
+
+Integer and byte results (streams) must match bit for bit; reconstructions
+x~_k must match bit for bit as well (same left-to-right add order, no FMA
+contraction), and every component must meet Eq. (1) of Sec. 4.3.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import driver
+from oracle import lib as orc
+from paper_2308_11759_amd import inputs
+
+from helpers import chunk_payloads, oracle_run, store_blob
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2308_11759_amd import pmc
+    c = pmc.Context(0)
+    c.set_option(pmc.OPT_SYNC_CHECK, 1)
+    yield c
+    torch.cuda.synchronize()
+
+
+def to_dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+
+
+def check_against_oracle(ctx, x, taus, label):
+    say("case %s shape=%s dtype=%s n=%d" % (label, x.shape, x.dtype, len(taus)))
+    comps, meta, recon = oracle_run(x, taus)
+    store = ctx.compress(to_dev(x), taus)
+    for i in range(len(taus)):
+        got = store.stream(i).cpu().numpy()
+        assert got.size == comps[i].size, (label, i, got.size, comps[i].size)
+        if not np.array_equal(got, comps[i]):
+            bad = np.nonzero(got != comps[i])[0]
+            raise AssertionError("%s: stream %d differs at %d bytes, first %d" % (label, i, bad.size, bad[0]))
+        assert store.info[i]["linf"] == meta[i]["linf"], (label, i)
+        assert store.info[i]["linf"] <= taus[i]
+        assert store.info[i]["nraw"] == meta[i]["nraw"]
+    for k in range(1, len(taus) + 1):
+        out = ctx.retrieve(store, k).cpu().numpy()
+        assert np.array_equal(out, recon[k - 1]), (label, k)
+    return store, comps, meta, recon
+
+
+def test_small_blobs_f64(ctx):
+    """64^3 float64 blobs, 4 components, tau_i = range * 10^-i."""
+    x = inputs.blobs_field(64, seed=0)
+    r = float(x.max() - x.min())
+    check_against_oracle(ctx, x, [r * 10.0 ** -(i + 1) for i in range(4)], "blobs64")
+
+
+def test_ragged_spectral_f32(ctx):
+    """Ragged extents (partial blocks on every axis), several chunks and a partial last chunk."""
+    x = inputs.spectral_field((29, 22, 37), seed=11, dtype=np.float32)
+    check_against_oracle(ctx, x, [2.0 ** (-3 * (i + 1)) for i in range(8)], "ragged32")
+
+
+def test_ragged_spectral_f64(ctx):
+    x = inputs.spectral_field((13, 41, 18), seed=12, dtype=np.float64)
+    check_against_oracle(ctx, x, [2.0 * 4.0 ** -(i + 1) for i in range(6)], "ragged64")
+
+
+def test_tiny_and_thin_fields(ctx):
+    for shape in ((1, 1, 1), (1, 1, 7), (3, 1, 5), (1, 9, 4), (4, 4, 4)):
+        for dt in (np.float32, np.float64):
+            x = inputs.spectral_field((max(shape[0], 2), max(shape[1], 2), max(shape[2], 2)), seed=3,
+                                      dtype=dt)[: shape[0], : shape[1], : shape[2]].copy()
+            check_against_oracle(ctx, x, [0.5, 0.01, 1e-4], "tiny%s" % (shape,))
+
+
+def test_zero_and_constant_fields(ctx):
+    for dt in (np.float32, np.float64):
+        check_against_oracle(ctx, np.zeros((8, 8, 12), dtype=dt), [1.0, 0.1], "zeros")
+        check_against_oracle(ctx, np.full((8, 9, 12), 3.25, dtype=dt), [1.0, 0.1, 1e-3], "const")
+
+
+def test_extreme_exponents(ctx):
+    """Subnormal-range and near-overflow content, and mixed magnitudes."""
+    rng = np.random.default_rng(21)
+    for dt in (np.float32, np.float64):
+        fi = np.finfo(dt)
+        x = (rng.normal(size=(8, 8, 8)) * float(fi.tiny) * 0.25).astype(dt)
+        s = float(np.max(np.abs(x)))
+        check_against_oracle(ctx, x, [s, s * 1e-2, s * 2.0 ** -40], "subnormal")
+        x = (rng.uniform(-1, 1, size=(8, 8, 8)) * float(fi.max) * 0.25).astype(dt)
+        check_against_oracle(ctx, x, [float(fi.max) * 1e-2, float(fi.max) * 1e-6], "huge")
+        x = (rng.normal(size=(8, 8, 8)) * 10.0 ** rng.integers(-20, 20, size=(8, 8, 8))).astype(dt)
+        check_against_oracle(ctx, x, [1e10, 1e-5, 1e-20], "mixed")
+
+
+def test_lossless_limit(ctx):
+    """Tolerances below every float32 difference force x~_n == x (Sec. 5.1.3)."""
+    x = inputs.spectral_field((12, 16, 20), seed=5, dtype=np.float32)
+    taus = [2.0 ** (-16 * (i + 1)) for i in range(10)]
+    store, comps, meta, recon = check_against_oracle(ctx, x, taus, "lossless")
+    assert np.array_equal(recon[-1], x)
+
+
+def test_decode_oracle_streams(ctx):
+    """The GPU decoder reproduces the oracle's Alg. 2 on streams the oracle wrote."""
+    x = inputs.spectral_field((17, 20, 33), seed=8, dtype=np.float64)
+    taus = [1.0 * 8.0 ** -(i + 1) for i in range(5)]
+    comps, meta, recon = oracle_run(x, taus)
+    store = ctx.deserialize(store_blob(x.shape, x.dtype, comps, meta))
+    for k in range(1, 6):
+        assert np.array_equal(ctx.retrieve(store, k).cpu().numpy(), recon[k - 1])
+    # round trip through serialisation
+    blob = store.serialize()
+    again = ctx.deserialize(blob)
+    assert np.array_equal(ctx.retrieve(again, 5).cpu().numpy(), recon[-1])
+
+
+def test_fused_literal_refine_agree(ctx):
+    from paper_2308_11759_amd import pmc
+    x = inputs.spectral_field((24, 28, 40), seed=9, dtype=np.float32)
+    taus = [2.0 ** (-3 * (i + 1)) for i in range(8)]
+    comps, meta, recon = oracle_run(x, taus)
+    store = ctx.compress(to_dev(x), taus)
+    ctx.set_option(pmc.OPT_FUSED_DECODE, 0)
+    try:
+        lit = [ctx.retrieve(store, k).cpu().numpy() for k in range(1, 9)]
+    finally:
+        ctx.set_option(pmc.OPT_FUSED_DECODE, 1)
+    for k in range(8):
+        assert np.array_equal(lit[k], recon[k])
+    xt = ctx.retrieve(store, 2)
+    ctx.refine(store, 2, 5, xt)
+    assert np.array_equal(xt.cpu().numpy(), recon[4])
+    ctx.refine(store, 5, 8, xt)
+    assert np.array_equal(xt.cpu().numpy(), recon[7])
+
+
+def test_select_k(ctx):
+    x = inputs.blobs_field(16, seed=2)
+    r = float(x.max() - x.min())
+    taus = [r * 10.0 ** -(i + 1) for i in range(4)]
+    store = ctx.compress(to_dev(x), taus)
+    meta = [dict(tau=t, linf=m["linf"]) for t, m in zip(taus, store.info)]
+    for tol in (r, r * 0.05, r * 1e-3, r * 1e-4, r * 1e-6):
+        assert store.select_k(tol) == driver.select_k(meta, tol)
+        assert store.select_k(tol, True) == driver.select_k(meta, tol, True)
+
+
+def test_range(ctx):
+    x = inputs.spectral_field((9, 10, 11), seed=4, dtype=np.float32)
+    lo, hi, bad = ctx.range(to_dev(x))
+    assert (lo, hi, bad) == (float(x.min()), float(x.max()), 0)
+    y = x.astype(np.float64)
+    y[3, 4, 5] = np.nan
+    y[0, 0, 0] = np.inf
+    lo, hi, bad = ctx.range(to_dev(y))
+    finite = y[np.isfinite(y)]
+    assert (lo, hi, bad) == (float(finite.min()), float(finite.max()), 2)
+
+
+def test_error_paths(ctx):
+    from paper_2308_11759_amd import pmc
+    x = inputs.spectral_field((8, 8, 8), seed=4, dtype=np.float32)
+    xd = to_dev(x)
+    with pytest.raises(pmc.PmcError) as ei:
+        ctx.compress(xd, [0.1, 0.2])
+    assert ei.value.status == pmc.E_ARG
+    with pytest.raises(pmc.PmcError) as ei:
+        ctx.compress(xd, [0.1, -1.0])
+    assert ei.value.status == pmc.E_ARG
+    y = x.copy()
+    y[1, 2, 3] = np.nan
+    with pytest.raises(pmc.PmcError) as ei:
+        ctx.compress(to_dev(y), [0.1])
+    assert ei.value.status == pmc.E_NONFINITE
+    import torch
+    small = torch.empty(200, dtype=torch.uint8, device="cuda:0")
+    with pytest.raises(pmc.PmcError) as ei:
+        ctx.compress(xd, [0.1, 0.01], streams=small)
+    assert ei.value.status == pmc.E_NOMEM
+    store = ctx.compress(xd, [0.1, 0.01])
+    assert store.select_k(1e-9) is None
+    # corrupted header -> rejected on the host
+    blob = bytearray(store.serialize())
+    hdr_off = (48 + 64 * 2 + 255) & ~255
+    blob[hdr_off] ^= 0xFF
+    with pytest.raises(pmc.PmcError) as ei:
+        ctx.deserialize(bytes(blob))
+    assert ei.value.status == pmc.E_CORRUPT
+
+
+def test_corrupt_payload_is_contained(ctx):
+    """Flipped payload bits decode to something or report E_CORRUPT, never
+    read outside the chunk (bounded reader)."""
+    from paper_2308_11759_amd import pmc
+    x = inputs.spectral_field((8, 12, 16), seed=6, dtype=np.float32)
+    store = ctx.compress(to_dev(x), [1e-2, 1e-4])
+    blob = bytearray(store.serialize())
+    rng = np.random.default_rng(3)
+    head = (48 + 64 * 2 + 255) & ~255
+    first = store.info[0]["bytes"]
+    nchunks = (2 * 3 * 4 + 15) // 16
+    for t in range(20):
+        b = bytearray(blob)
+        pos = head + 64 + 4 * nchunks + int(rng.integers(0, first - 64 - 4 * nchunks))
+        b[pos] ^= 1 << int(rng.integers(0, 8))
+        s = ctx.deserialize(bytes(b))
+        try:
+            ctx.retrieve(s, 2)
+        except pmc.PmcError as e:
+            assert e.status == pmc.E_CORRUPT
