@@ -69,8 +69,20 @@ const char* pmc_last_error(const pmc_ctx* ctx);
  *    Both give bit-identical results.
  *  PMC_OPT_SYNC_CHECK (default 0): decode calls synchronise the stream and
  *    report PMC_E_CORRUPT when a kernel found a malformed stream. */
-enum { PMC_OPT_FUSED_DECODE = 1, PMC_OPT_SYNC_CHECK = 2 };
+/*  PMC_OPT_PROFILE (default 0): bracket every kernel launch with HIP events
+ *    on the context stream; pmc_prof_read returns the per-kernel totals. */
+enum { PMC_OPT_FUSED_DECODE = 1, PMC_OPT_SYNC_CHECK = 2, PMC_OPT_PROFILE = 3 };
 pmc_status pmc_ctx_set_option(pmc_ctx* ctx, int option, int value);
+
+/* Per-kernel launch count and summed duration (milliseconds, from HIP events)
+ * since the last reset.  Synchronises the stream.  Fills up to cap entries,
+ * sets *n to the number of kernels seen; reset != 0 clears the totals. */
+typedef struct {
+  char name[32];
+  uint64_t launches;
+  double ms;
+} pmc_prof_entry;
+pmc_status pmc_prof_read(pmc_ctx* ctx, pmc_prof_entry* out, int cap, int* n, int reset);
 
 /* ---- range (tau_0 of the tolerance schedule, Sec. 5.1) --------------------
  * min and max of the field in float64 and the number of non-finite values.
@@ -90,13 +102,19 @@ pmc_status pmc_compress_sizes(const pmc_field* f, int n, size_t* ws_bytes, size_
  * (capacity streams_cap bytes), which must stay alive as long as the store.
  * On success *out holds per-component metadata: prescribed tau and measured
  * max|x - x~_i| in float64 (Sec. 4.3, last paragraph), stream bytes, block
- * counts.  Synchronises the stream once at the end to read the sizes. */
+ * counts.  Synchronises the stream once at the end to read the sizes.
+ * PMC_E_BOUND still returns the store (valid streams; some blocks exceed
+ * their tolerance, counted as misses); the caller frees it. */
 pmc_status pmc_compress(pmc_ctx* ctx, const pmc_field* f, const void* d_x, int n, const double* tau,
                         void* d_ws, size_t ws_bytes, void* d_streams, size_t streams_cap, pmc_store** out);
 
 /* Per-component metadata (arrays of store n entries; any may be NULL). */
 pmc_status pmc_store_info(const pmc_store* s, int* n, double* tau, double* linf, uint64_t* bytes,
                           uint64_t* nraw, uint64_t* nesc);
+/* Block counts of component i (0-based): counts[0..4] = empty, coded, raw,
+ * escalated (coded with more planes than the tolerance alone asks for) and
+ * tolerance misses. */
+pmc_status pmc_store_counts(const pmc_store* s, int i, uint64_t counts[5]);
 /* Field of a store. */
 pmc_status pmc_store_field(const pmc_store* s, pmc_field* f);
 /* Device address and byte size of component i's stream (0-based). */

@@ -16,13 +16,71 @@
 
 using namespace pmc;
 
+struct ProfRec {
+  int kernel;
+  hipEvent_t start, stop;
+};
+
 struct pmc_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   std::string err;
   int fused_decode = 1;
   int sync_check = 0;
+  int profile = 0;
+  std::vector<std::string> prof_names;
+  std::vector<uint64_t> prof_launches;
+  std::vector<double> prof_ms;
+  std::vector<ProfRec> prof_pending;
+  std::vector<hipEvent_t> prof_pool;
 };
+
+namespace {
+
+hipEvent_t prof_event(pmc_ctx* c) {
+  if (!c->prof_pool.empty()) {
+    hipEvent_t e = c->prof_pool.back();
+    c->prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+int prof_kernel_id(pmc_ctx* c, const char* name) {
+  for (size_t i = 0; i < c->prof_names.size(); ++i)
+    if (c->prof_names[i] == name) return (int)i;
+  c->prof_names.push_back(name);
+  c->prof_launches.push_back(0);
+  c->prof_ms.push_back(0.0);
+  return (int)c->prof_names.size() - 1;
+}
+
+// brackets one kernel launch with events on the context stream when enabled
+struct ProfScope {
+  pmc_ctx* c;
+  ProfRec r{};
+  bool on;
+  ProfScope(pmc_ctx* ctx, const char* name) : c(ctx), on(ctx->profile != 0) {
+    if (!on) return;
+    r.kernel = prof_kernel_id(c, name);
+    r.start = prof_event(c);
+    r.stop = prof_event(c);
+    if (!r.start || !r.stop) {
+      on = false;
+      return;
+    }
+    hipEventRecord(r.start, c->stream);
+  }
+  ~ProfScope() {
+    if (!on) return;
+    hipEventRecord(r.stop, c->stream);
+    c->prof_pending.push_back(r);
+  }
+};
+
+}  // namespace
 
 struct pmc_store {
   pmc_field f{};
@@ -126,7 +184,49 @@ pmc_status pmc_ctx_create(int device, void* hip_stream, pmc_ctx** out) {
   return PMC_OK;
 }
 
-void pmc_ctx_destroy(pmc_ctx* ctx) { delete ctx; }
+void pmc_ctx_destroy(pmc_ctx* ctx) {
+  if (!ctx) return;
+  if (!ctx->prof_pending.empty()) hipStreamSynchronize(ctx->stream);
+  for (auto& r : ctx->prof_pending) {
+    hipEventDestroy(r.start);
+    hipEventDestroy(r.stop);
+  }
+  for (auto e : ctx->prof_pool) hipEventDestroy(e);
+  delete ctx;
+}
+
+pmc_status pmc_prof_read(pmc_ctx* ctx, pmc_prof_entry* out, int cap, int* n, int reset) {
+  if (!ctx) return PMC_E_ARG;
+  if (!ctx->prof_pending.empty()) {
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hipfail(ctx, e, "sync");
+    for (auto& r : ctx->prof_pending) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, r.start, r.stop) == hipSuccess) {
+        ctx->prof_ms[r.kernel] += ms;
+        ctx->prof_launches[r.kernel] += 1;
+      }
+      ctx->prof_pool.push_back(r.start);
+      ctx->prof_pool.push_back(r.stop);
+    }
+    ctx->prof_pending.clear();
+  }
+  const int k = (int)ctx->prof_names.size();
+  if (n) *n = k;
+  for (int i = 0; i < k && i < cap && out; ++i) {
+    std::memset(&out[i], 0, sizeof(out[i]));
+    std::snprintf(out[i].name, sizeof(out[i].name), "%s", ctx->prof_names[i].c_str());
+    out[i].launches = ctx->prof_launches[i];
+    out[i].ms = ctx->prof_ms[i];
+  }
+  if (reset) {
+    for (int i = 0; i < k; ++i) {
+      ctx->prof_launches[i] = 0;
+      ctx->prof_ms[i] = 0.0;
+    }
+  }
+  return PMC_OK;
+}
 
 const char* pmc_last_error(const pmc_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
 
@@ -134,6 +234,7 @@ pmc_status pmc_ctx_set_option(pmc_ctx* ctx, int option, int value) {
   if (!ctx) return PMC_E_ARG;
   if (option == PMC_OPT_FUSED_DECODE) ctx->fused_decode = value ? 1 : 0;
   else if (option == PMC_OPT_SYNC_CHECK) ctx->sync_check = value ? 1 : 0;
+  else if (option == PMC_OPT_PROFILE) ctx->profile = value ? 1 : 0;
   else return fail(ctx, PMC_E_ARG, "unknown option %d", option);
   return PMC_OK;
 }
@@ -240,9 +341,21 @@ pmc_status pmc_compress(pmc_ctx* ctx, const pmc_field* f, const void* d_x, int n
       a.staging = (uint32_t*)(ws + w.staging);
       a.chunk_words = (uint32_t*)(ws + w.chunk_words);
       a.meta = meta + i;
-      if ((e = launch_encode<float>(a, ctx->stream)) != hipSuccess) return hipfail(ctx, e, "encode");
-      if ((e = launch_scan(sa, ctx->stream)) != hipSuccess) return hipfail(ctx, e, "scan");
-      if ((e = launch_pack<float>(pa, ctx->stream)) != hipSuccess) return hipfail(ctx, e, "pack");
+      {
+        ProfScope ps(ctx, "k_encode_f32");
+        e = launch_encode<float>(a, ctx->stream);
+      }
+      if (e != hipSuccess) return hipfail(ctx, e, "encode");
+      {
+        ProfScope ps(ctx, "k_scan");
+        e = launch_scan(sa, ctx->stream);
+      }
+      if (e != hipSuccess) return hipfail(ctx, e, "scan");
+      {
+        ProfScope ps(ctx, "k_pack_f32");
+        e = launch_pack<float>(pa, ctx->stream);
+      }
+      if (e != hipSuccess) return hipfail(ctx, e, "pack");
     } else {
       EncArgs<double> a{};
       a.x = (const double*)d_x;
@@ -255,9 +368,21 @@ pmc_status pmc_compress(pmc_ctx* ctx, const pmc_field* f, const void* d_x, int n
       a.staging = (uint32_t*)(ws + w.staging);
       a.chunk_words = (uint32_t*)(ws + w.chunk_words);
       a.meta = meta + i;
-      if ((e = launch_encode<double>(a, ctx->stream)) != hipSuccess) return hipfail(ctx, e, "encode");
-      if ((e = launch_scan(sa, ctx->stream)) != hipSuccess) return hipfail(ctx, e, "scan");
-      if ((e = launch_pack<double>(pa, ctx->stream)) != hipSuccess) return hipfail(ctx, e, "pack");
+      {
+        ProfScope ps(ctx, "k_encode_f64");
+        e = launch_encode<double>(a, ctx->stream);
+      }
+      if (e != hipSuccess) return hipfail(ctx, e, "encode");
+      {
+        ProfScope ps(ctx, "k_scan");
+        e = launch_scan(sa, ctx->stream);
+      }
+      if (e != hipSuccess) return hipfail(ctx, e, "scan");
+      {
+        ProfScope ps(ctx, "k_pack_f64");
+        e = launch_pack<double>(pa, ctx->stream);
+      }
+      if (e != hipSuccess) return hipfail(ctx, e, "pack");
     }
   }
   std::vector<CompMeta> hm(n);
@@ -318,6 +443,16 @@ pmc_status pmc_store_info(const pmc_store* s, int* n, double* tau, double* linf,
   return PMC_OK;
 }
 
+pmc_status pmc_store_counts(const pmc_store* s, int i, uint64_t counts[5]) {
+  if (!s || !counts || i < 0 || i >= s->n) return PMC_E_ARG;
+  counts[0] = s->nempty[i];
+  counts[1] = s->ncoded[i];
+  counts[2] = s->nraw[i];
+  counts[3] = s->nesc[i];
+  counts[4] = s->nmiss[i];
+  return PMC_OK;
+}
+
 pmc_status pmc_store_field(const pmc_store* s, pmc_field* f) {
   if (!s || !f) return PMC_E_ARG;
   *f = s->f;
@@ -370,6 +505,7 @@ static pmc_status decode_range(pmc_ctx* ctx, const pmc_store* s, int k0, int k1,
       a.out = (float*)d_out;
       a.g = s->g;
       a.status = status;
+      ProfScope ps(ctx, "k_decode_f32");
       e = launch_decode<float>(a, ctx->stream);
     } else {
       DecArgs<double> a{};
@@ -383,6 +519,7 @@ static pmc_status decode_range(pmc_ctx* ctx, const pmc_store* s, int k0, int k1,
       a.out = (double*)d_out;
       a.g = s->g;
       a.status = status;
+      ProfScope ps(ctx, "k_decode_f64");
       e = launch_decode<double>(a, ctx->stream);
     }
     if (e != hipSuccess) return hipfail(ctx, e, "decode");

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libpmc.so")
 
 OK, E_ARG, E_NONFINITE, E_NOMEM, E_CORRUPT, E_UNREACHABLE, E_BOUND, E_DEVICE = 0, -1, -2, -3, -4, -5, -6, -7
 F32, F64 = 1, 2
-OPT_FUSED_DECODE, OPT_SYNC_CHECK = 1, 2
+OPT_FUSED_DECODE, OPT_SYNC_CHECK, OPT_PROFILE = 1, 2, 3
 _NAMES = {0: "OK", -1: "E_ARG", -2: "E_NONFINITE", -3: "E_NOMEM", -4: "E_CORRUPT", -5: "E_UNREACHABLE",
           -6: "E_BOUND", -7: "E_DEVICE"}
 
@@ -33,6 +33,10 @@ class PmcError(RuntimeError):
 class Field(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_uint64), ("ny", ctypes.c_uint64), ("nz", ctypes.c_uint64),
                 ("dtype", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class ProfEntry(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_uint64), ("ms", ctypes.c_double)]
 
 
 _lib = None
@@ -49,6 +53,7 @@ SIGNATURES = {
     "pmc_compress_sizes": (_int, [_P(Field), _int, _P(_sz), _P(_sz)]),
     "pmc_compress": (_int, [_vp, _P(Field), _vp, _int, _P(_dbl), _vp, _sz, _vp, _sz, _P(_vp)]),
     "pmc_store_info": (_int, [_vp, _P(_int), _P(_dbl), _P(_dbl), _P(_u64), _P(_u64), _P(_u64)]),
+    "pmc_store_counts": (_int, [_vp, _int, _P(_u64)]),
     "pmc_store_field": (_int, [_vp, _P(Field)]),
     "pmc_store_stream": (_int, [_vp, _int, _P(_vp), _P(_u64)]),
     "pmc_select_k": (_int, [_vp, _dbl, _int, _P(_int)]),
@@ -59,6 +64,7 @@ SIGNATURES = {
     "pmc_store_device_bytes": (_int, [_vp, _sz, _P(_sz)]),
     "pmc_store_deserialize": (_int, [_vp, _vp, _sz, _vp, _sz, _P(_vp)]),
     "pmc_store_free": (None, [_vp]),
+    "pmc_prof_read": (_int, [_vp, _P(ProfEntry), _int, _P(_int), _int]),
 }
 
 
@@ -141,6 +147,14 @@ class Context:
     def set_option(self, option, value):
         self._check(self.lib.pmc_ctx_set_option(self.handle, option, int(value)))
 
+    def prof_read(self, reset=True):
+        """{kernel name: (launches, total ms)} from the library's HIP events."""
+        cap = 64
+        arr = (ProfEntry * cap)()
+        n = ctypes.c_int()
+        self._check(self.lib.pmc_prof_read(self.handle, arr, cap, ctypes.byref(n), int(bool(reset))))
+        return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].ms)) for i in range(min(n.value, cap))}
+
     def _workspace(self, nbytes):
         if self._ws is None or self._ws.numel() < nbytes:
             self._ws = None
@@ -163,8 +177,11 @@ class Context:
         self._check(self.lib.pmc_compress_sizes(ctypes.byref(f), int(n), ctypes.byref(ws), ctypes.byref(cap)))
         return ws.value, cap.value
 
-    def compress(self, x, taus, streams=None):
-        """Alg. 1: compress a device field into len(taus) components."""
+    def compress(self, x, taus, streams=None, allow_bound_miss=False):
+        """Alg. 1: compress a device field into len(taus) components.
+
+        With allow_bound_miss a PMC_E_BOUND result still returns the store
+        (flagged ``bound_missed``); otherwise every error raises PmcError."""
         taus = [float(t) for t in taus]
         n = len(taus)
         f = field_of(x)
@@ -177,6 +194,10 @@ class Context:
         st = self.lib.pmc_compress(self.handle, ctypes.byref(f), ctypes.c_void_p(x.data_ptr()), n, tau_arr,
                                    ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(streams.data_ptr()),
                                    streams.numel(), ctypes.byref(h))
+        if st == E_BOUND and allow_bound_miss and h.value:
+            store = Store(self, h, streams)
+            store.bound_missed = True
+            return store
         if st != OK:
             if h.value:
                 self.lib.pmc_store_free(h)
@@ -226,6 +247,7 @@ class Store:
         shape = [f.nz, f.ny, f.nx]
         self.shape = tuple(int(s) for s in shape)
         self.dtype = _torch_dtype(f.dtype)
+        self.bound_missed = False
         self.info = self._info()
 
     def _info(self):
@@ -235,7 +257,13 @@ class Store:
         tau, linf = (ctypes.c_double * k)(), (ctypes.c_double * k)()
         by, raw, esc = (ctypes.c_uint64 * k)(), (ctypes.c_uint64 * k)(), (ctypes.c_uint64 * k)()
         self.lib.pmc_store_info(self.handle, ctypes.byref(n), tau, linf, by, raw, esc)
-        return [dict(tau=tau[i], linf=linf[i], bytes=by[i], nraw=raw[i], nesc=esc[i]) for i in range(k)]
+        out = []
+        for i in range(k):
+            c = (ctypes.c_uint64 * 5)()
+            self.lib.pmc_store_counts(self.handle, i, c)
+            out.append(dict(tau=tau[i], linf=linf[i], bytes=by[i], nempty=c[0], ncoded=c[1], nraw=c[2],
+                            nesc=c[3], nmiss=c[4]))
+        return out
 
     @property
     def n(self):

@@ -101,7 +101,29 @@ def test_extreme_exponents(ctx):
         x = (rng.uniform(-1, 1, size=(8, 8, 8)) * float(fi.max) * 0.25).astype(dt)
         check_against_oracle(ctx, x, [float(fi.max) * 1e-2, float(fi.max) * 1e-6], "huge")
         x = (rng.normal(size=(8, 8, 8)) * 10.0 ** rng.integers(-20, 20, size=(8, 8, 8))).astype(dt)
-        check_against_oracle(ctx, x, [1e10, 1e-5, 1e-20], "mixed")
+        check_against_oracle(ctx, x, [1e10, 1e4, 1e-2], "mixed")
+
+
+def test_bound_miss_reported_like_oracle(ctx):
+    """Tolerance ratios far below 2^-22 can leave a rounded residual that even
+    a raw block cannot fix; both sides count the same misses and the GPU call
+    reports E_BOUND while still returning its (valid) streams."""
+    from paper_2308_11759_amd import pmc
+    rng = np.random.default_rng(21)
+    x = (rng.normal(size=(8, 8, 8)) * 10.0 ** rng.integers(-20, 20, size=(8, 8, 8))).astype(np.float32)
+    taus = [1e10, 1e-5, 1e-20]
+    comps, meta, recon = oracle_run(x, taus)
+    assert sum(m["nmiss"] for m in meta) > 0
+    store = ctx.compress(to_dev(x), taus, allow_bound_miss=True)
+    assert store.bound_missed
+    for i in range(3):
+        assert np.array_equal(store.stream(i).cpu().numpy(), comps[i])
+        assert store.info[i]["nmiss"] == meta[i]["nmiss"]
+    for k in range(1, 4):
+        assert np.array_equal(ctx.retrieve(store, k).cpu().numpy(), recon[k - 1])
+    with pytest.raises(pmc.PmcError) as ei:
+        ctx.compress(to_dev(x), taus)
+    assert ei.value.status == pmc.E_BOUND
 
 
 def test_lossless_limit(ctx):
