@@ -110,7 +110,11 @@ def test_bound_miss_reported_like_oracle(ctx):
     reports E_BOUND while still returning its (valid) streams."""
     from paper_2308_11759_amd import pmc
     rng = np.random.default_rng(21)
+    fi = np.finfo(np.float32)
+    rng.normal(size=(8, 8, 8))
+    rng.uniform(-1, 1, size=(8, 8, 8))
     x = (rng.normal(size=(8, 8, 8)) * 10.0 ** rng.integers(-20, 20, size=(8, 8, 8))).astype(np.float32)
+    assert float(fi.max) > float(np.max(np.abs(x)))
     taus = [1e10, 1e-5, 1e-20]
     comps, meta, recon = oracle_run(x, taus)
     assert sum(m["nmiss"] for m in meta) > 0
