@@ -71,11 +71,11 @@ struct ProfScope {
       on = false;
       return;
     }
-    hipEventRecord(r.start, c->stream);
+    (void)hipEventRecord(r.start, c->stream);
   }
   ~ProfScope() {
     if (!on) return;
-    hipEventRecord(r.stop, c->stream);
+    (void)hipEventRecord(r.stop, c->stream);
     c->prof_pending.push_back(r);
   }
 };
@@ -88,7 +88,7 @@ struct pmc_store {
   int n = 0;
   std::vector<double> tau, linf;
   std::vector<int> minexp;
-  std::vector<uint64_t> bytes, offset, words, nempty, ncoded, nraw, nesc, nmiss;
+  std::vector<uint64_t> bytes, offset, aux_offset, words, nempty, ncoded, nraw, nesc, nmiss;
   const uint8_t* d_base = nullptr;  // caller-owned device memory holding the streams
 };
 
@@ -144,7 +144,7 @@ int floor_log2(double tau) {
 }
 
 struct WsLayout {
-  uint64_t xt, staging, chunk_words, offsets, meta, total;
+  uint64_t xt, staging, chunk_words, offsets, tile_sums, meta, total;
 };
 
 WsLayout ws_layout(const pmc_field* f, const Geo& g, int n) {
@@ -158,6 +158,8 @@ WsLayout ws_layout(const pmc_field* f, const Geo& g, int n) {
   o += align256(g.nchunks * 4);
   w.offsets = o;
   o += align256(g.nchunks * 4);
+  w.tile_sums = o;
+  o += align256((g.nchunks + kScanTile - 1) / kScanTile * 8);
   w.meta = o;
   o += align256((uint64_t)n * sizeof(CompMeta));
   w.total = o;
@@ -167,6 +169,11 @@ WsLayout ws_layout(const pmc_field* f, const Geo& g, int n) {
 uint64_t stream_cap_one(const Geo& g, int dtype) {
   return kStreamHeader + 4 * g.nchunks + 4 * g.nchunks * chunk_cap_words_host(dtype);
 }
+
+// the device buffer of a store holds, first, one per-block index (bit offset
+// of each block inside its chunk, 4 bytes per block) per component, then the
+// streams, each on a 256-byte boundary
+uint64_t aux_bytes(const Geo& g) { return align256(4 * g.nblocks); }
 
 }  // namespace
 
@@ -186,12 +193,12 @@ pmc_status pmc_ctx_create(int device, void* hip_stream, pmc_ctx** out) {
 
 void pmc_ctx_destroy(pmc_ctx* ctx) {
   if (!ctx) return;
-  if (!ctx->prof_pending.empty()) hipStreamSynchronize(ctx->stream);
+  if (!ctx->prof_pending.empty()) (void)hipStreamSynchronize(ctx->stream);
   for (auto& r : ctx->prof_pending) {
-    hipEventDestroy(r.start);
-    hipEventDestroy(r.stop);
+    (void)hipEventDestroy(r.start);
+    (void)hipEventDestroy(r.stop);
   }
-  for (auto e : ctx->prof_pool) hipEventDestroy(e);
+  for (auto e : ctx->prof_pool) (void)hipEventDestroy(e);
   delete ctx;
 }
 
@@ -280,7 +287,7 @@ pmc_status pmc_compress_sizes(const pmc_field* f, int n, size_t* ws_bytes, size_
   if (!make_geo(f, &g) || n < 1 || n > kMaxComps) return PMC_E_ARG;
   WsLayout w = ws_layout(f, g, n);
   if (ws_bytes) *ws_bytes = w.total;
-  if (stream_cap_per_comp) *stream_cap_per_comp = align256(stream_cap_one(g, f->dtype));
+  if (stream_cap_per_comp) *stream_cap_per_comp = aux_bytes(g) + align256(stream_cap_one(g, f->dtype));
   return PMC_OK;
 }
 
@@ -299,12 +306,22 @@ pmc_status pmc_compress(pmc_ctx* ctx, const pmc_field* f, const void* d_x, int n
   WsLayout w = ws_layout(f, g, n);
   if (!d_ws || ws_bytes < w.total)
     return fail(ctx, PMC_E_NOMEM, "workspace too small: need %llu bytes", (unsigned long long)w.total);
+  // the per-block indexes sit at the front of d_streams and are written by
+  // the encoder directly; the streams themselves are capacity-checked on the
+  // device before they are packed
+  const uint64_t min_cap = (uint64_t)n * aux_bytes(g) + (uint64_t)n * align256(kStreamHeader + 4 * g.nchunks);
+  if (streams_cap < min_cap)
+    return fail(ctx, PMC_E_NOMEM, "stream capacity too small: need at least %llu bytes",
+                (unsigned long long)min_cap);
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hipfail(ctx, e, "hipSetDevice");
   uint8_t* ws = (uint8_t*)d_ws;
   CompMeta* meta = (CompMeta*)(ws + w.meta);
   if ((e = launch_fill64((unsigned long long*)meta, (uint64_t)n * sizeof(CompMeta) / 8, 0ull, ctx->stream)) !=
       hipSuccess)
+    return hipfail(ctx, e, "meta init");
+  const uint64_t auxb = aux_bytes(g);
+  if ((e = launch_fill64(&meta[0].stream_offset, 1, (unsigned long long)(n * auxb), ctx->stream)) != hipSuccess)
     return hipfail(ctx, e, "meta init");
 
   std::vector<int> minexp(n);
@@ -313,6 +330,8 @@ pmc_status pmc_compress(pmc_ctx* ctx, const pmc_field* f, const void* d_x, int n
     ScanArgs sa{};
     sa.chunk_words = (const uint32_t*)(ws + w.chunk_words);
     sa.offsets = (uint32_t*)(ws + w.offsets);
+    sa.tile_sums = (unsigned long long*)(ws + w.tile_sums);
+    sa.aux_bytes = auxb;
     sa.nchunks = g.nchunks;
     sa.meta = meta;
     sa.comp = i;
@@ -340,6 +359,7 @@ pmc_status pmc_compress(pmc_ctx* ctx, const pmc_field* f, const void* d_x, int n
       a.last = i == n - 1;
       a.staging = (uint32_t*)(ws + w.staging);
       a.chunk_words = (uint32_t*)(ws + w.chunk_words);
+      a.aux = (uint32_t*)((uint8_t*)d_streams + i * auxb);
       a.meta = meta + i;
       {
         ProfScope ps(ctx, "k_encode_f32");
@@ -367,6 +387,7 @@ pmc_status pmc_compress(pmc_ctx* ctx, const pmc_field* f, const void* d_x, int n
       a.last = i == n - 1;
       a.staging = (uint32_t*)(ws + w.staging);
       a.chunk_words = (uint32_t*)(ws + w.chunk_words);
+      a.aux = (uint32_t*)((uint8_t*)d_streams + i * auxb);
       a.meta = meta + i;
       {
         ProfScope ps(ctx, "k_encode_f64");
@@ -400,7 +421,7 @@ pmc_status pmc_compress(pmc_ctx* ctx, const pmc_field* f, const void* d_x, int n
   if (flags & FLAG_NONFINITE) return fail(ctx, PMC_E_NONFINITE, "input holds NaN or Inf");
   if (flags & FLAG_INDEX) return fail(ctx, PMC_E_NOMEM, "a stream exceeds 2^32 payload words");
   if (flags & FLAG_OVERFLOW) {
-    unsigned long long need = 0;
+    unsigned long long need = n * auxb;
     for (int i = 0; i < n; ++i) need = align256(need) + hm[i].stream_bytes;
     return fail(ctx, PMC_E_NOMEM, "stream capacity too small: need %llu bytes", need);
   }
@@ -417,6 +438,7 @@ pmc_status pmc_compress(pmc_ctx* ctx, const pmc_field* f, const void* d_x, int n
     s->minexp.push_back(minexp[i]);
     s->bytes.push_back(hm[i].stream_bytes);
     s->offset.push_back(hm[i].stream_offset);
+    s->aux_offset.push_back(i * auxb);
     s->words.push_back(hm[i].payload_words);
     s->nempty.push_back(hm[i].nempty);
     s->ncoded.push_back(hm[i].ncoded);
@@ -497,6 +519,7 @@ static pmc_status decode_range(pmc_ctx* ctx, const pmc_store* s, int k0, int k1,
       DecArgs<float> a{};
       for (int i = i0; i < i1; ++i) {
         a.s[i - i0] = s->d_base + s->offset[i];
+        a.aux[i - i0] = (const uint32_t*)(s->d_base + s->aux_offset[i]);
         a.words[i - i0] = s->words[i];
         a.minexp[i - i0] = s->minexp[i];
       }
@@ -511,6 +534,7 @@ static pmc_status decode_range(pmc_ctx* ctx, const pmc_store* s, int k0, int k1,
       DecArgs<double> a{};
       for (int i = i0; i < i1; ++i) {
         a.s[i - i0] = s->d_base + s->offset[i];
+        a.aux[i - i0] = (const uint32_t*)(s->d_base + s->aux_offset[i]);
         a.words[i - i0] = s->words[i];
         a.minexp[i - i0] = s->minexp[i];
       }
@@ -667,8 +691,9 @@ static bool check_stream(const uint8_t* p, uint64_t bytes, const pmc_field* f, c
 
 pmc_status pmc_store_device_bytes(const void* host_buf, size_t size, size_t* need) {
   BlobView v;
-  if (!need || !parse_blob(host_buf, size, &v)) return PMC_E_CORRUPT;
-  *need = align256(v.region_bytes);
+  Geo g;
+  if (!need || !parse_blob(host_buf, size, &v) || !make_geo(&v.f, &g)) return PMC_E_CORRUPT;
+  *need = v.n * aux_bytes(g) + align256(v.region_bytes);
   return PMC_OK;
 }
 
@@ -681,7 +706,9 @@ pmc_status pmc_store_deserialize(pmc_ctx* ctx, const void* host_buf, size_t size
   if (!parse_blob(host_buf, size, &v)) return fail(ctx, PMC_E_CORRUPT, "malformed store blob");
   Geo g;
   if (!make_geo(&v.f, &g)) return fail(ctx, PMC_E_CORRUPT, "bad field in blob");
-  if (cap < v.region_bytes) return fail(ctx, PMC_E_NOMEM, "need %llu bytes", (unsigned long long)v.region_bytes);
+  const uint64_t auxb = aux_bytes(g);
+  const uint64_t need = v.n * auxb + align256(v.region_bytes);
+  if (cap < need) return fail(ctx, PMC_E_NOMEM, "need %llu bytes", (unsigned long long)need);
   const uint8_t* region = (const uint8_t*)host_buf + v.region_off;
   pmc_store* s = new pmc_store();
   s->f = v.f;
@@ -705,7 +732,8 @@ pmc_status pmc_store_deserialize(pmc_ctx* ctx, const void* host_buf, size_t size
     s->linf.push_back(linf);
     s->minexp.push_back(floor_log2(tau));
     s->bytes.push_back(r[2]);
-    s->offset.push_back(off);
+    s->offset.push_back(v.n * auxb + off);
+    s->aux_offset.push_back(i * auxb);
     s->words.push_back(words);
     s->nempty.push_back(r[3]);
     s->ncoded.push_back(r[4]);
@@ -715,7 +743,21 @@ pmc_status pmc_store_deserialize(pmc_ctx* ctx, const void* host_buf, size_t size
     off += r[2];
   }
   hipError_t e = hipSetDevice(ctx->device);
-  if (e == hipSuccess) e = hipMemcpyAsync(d_streams, region, v.region_bytes, hipMemcpyHostToDevice, ctx->stream);
+  uint8_t* base = (uint8_t*)d_streams;
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(base + v.n * auxb, region, v.region_bytes, hipMemcpyHostToDevice, ctx->stream);
+  // rebuild the per-block index of every stream; a malformed payload leaves
+  // offsets the decoder rejects (it bounds every offset by its chunk)
+  for (int i = 0; i < v.n && e == hipSuccess; ++i) {
+    AuxArgs a{};
+    a.s = base + s->offset[i];
+    a.aux = (uint32_t*)(base + s->aux_offset[i]);
+    a.words = s->words[i];
+    a.minexp = s->minexp[i];
+    a.g = g;
+    a.status = nullptr;
+    e = s->f.dtype == PMC_F32 ? launch_aux<float>(a, ctx->stream) : launch_aux<double>(a, ctx->stream);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) {
     delete s;

@@ -398,7 +398,6 @@ template <class T> __device__ __forceinline__ typename FT<T>::U to_nb(typename F
   return ((U)q + FT<T>::NB) ^ FT<T>::NB;
 }
 template <class T> __device__ __forceinline__ typename FT<T>::S from_nb(typename FT<T>::U u) {
-  typedef typename FT<T>::U U;
   typedef typename FT<T>::S S;
   return (S)((u ^ FT<T>::NB) - FT<T>::NB);
 }
@@ -492,6 +491,28 @@ template <class T> __device__ __forceinline__ void planes_read(GBits& r, typenam
       u[j + 32] |= (U)(Tw[j] >> 16) << base;
     }
   }
+}
+
+// advance a reader over one block without reconstructing it; returns false
+// on a malformed header
+template <class T> __device__ __forceinline__ bool block_skip(GBits& r, int minexp) {
+  constexpr int P = FT<T>::P;
+  if (!r.get(1)) return true;  // empty
+  if (r.get(1)) {              // raw
+    for (int l = 0; l < 64; ++l) r.get64((uint32_t)P);
+    return true;
+  }
+  int delta = 0;
+  while (r.get(1)) {
+    if (++delta > P) return false;
+  }
+  const int emax = (int)r.get((uint32_t)FT<T>::EBITS) - FT<T>::BIAS;
+  int p = emax - minexp + kGuard;
+  p = (p < 0 ? 0 : (p > P ? P : p)) + delta;
+  if (emax < 2 - FT<T>::BIAS || p < 1 || p > P) return false;
+  uint32_t n = 0;
+  for (int t = 0; t < p; ++t) (void)plane_read(r, n);
+  return true;
 }
 
 }  // namespace pmc

@@ -5,10 +5,12 @@
 //             coding (line 4), decode-for-verify (line 5), x~ update (line 6)
 //             and the measured error (Sec. 4.3); one lane per 4x4x4 block,
 //             one wave per 4 chunks, chunk bitstreams assembled in LDS
-//  k_scan     chunk word counts -> chunk offsets and stream size
+//  k_tile_*   chunk word counts -> chunk offsets and stream size
 //  k_pack     staging -> final stream (header, chunk index, payload)
-//  k_decode   Alg. 2 (Sec. 4.2): decode components [k0, k1) of a chunk and
-//             add them left to right into x~; one lane per chunk of 16 blocks
+//  k_decode   Alg. 2 (Sec. 4.2): decode components [k0, k1) of a block and
+//             add them left to right into x~; one lane per block, located by
+//             the chunk index plus a per-block bit offset written by k_encode
+//  k_aux      rebuild those per-block offsets for streams written elsewhere
 //  k_range    min / max / non-finite count (tau_0 = range, Sec. 5.1)
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -256,6 +258,7 @@ __global__ __launch_bounds__(64) void k_encode(EncArgs<T> a) {
     if ((lane & 15) >= (uint32_t)s) incl += y;
   }
   const uint32_t off = incl - nbits;
+  if (active) a.aux[blk] = off;
   __syncthreads();  // zeroed LDS visible to every lane
 
   if (active) {
@@ -303,41 +306,74 @@ __global__ __launch_bounds__(64) void k_encode(EncArgs<T> a) {
 }
 
 // ---------------------------------------------------------------------------
-// chunk offsets: exclusive prefix sum of chunk word counts (one workgroup)
-__global__ __launch_bounds__(1024) void k_scan(ScanArgs a) {
-  __shared__ unsigned long long part[1024];
-  const uint32_t t = threadIdx.x;
-  const uint64_t per = (a.nchunks + 1023) / 1024;
-  const uint64_t lo = min<uint64_t>(a.nchunks, t * per), hi = min<uint64_t>(a.nchunks, lo + per);
-  unsigned long long s = 0;
-  for (uint64_t i = lo; i < hi; ++i) s += a.chunk_words[i];
-  part[t] = s;
+// chunk offsets: exclusive prefix sum of chunk word counts in three passes
+// over tiles of kScanTile chunks (tile sums, scan of the tile sums with the
+// stream size bookkeeping, per-tile scans)
+__device__ __forceinline__ unsigned long long wave_incl_scan(unsigned long long v, uint32_t lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    unsigned long long y = __shfl_up(v, d, 64);
+    if (lane >= (uint32_t)d) v += y;
+  }
+  return v;
+}
+
+// block-wide inclusive scan of one value per thread (1024 threads)
+__device__ __forceinline__ unsigned long long block_incl_scan(unsigned long long v, unsigned long long* sh) {
+  const uint32_t t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  v = wave_incl_scan(v, lane);
+  if (lane == 63) sh[wave] = v;
   __syncthreads();
-  for (uint32_t d = 1; d < 1024; d <<= 1) {
-    unsigned long long v = t >= d ? part[t - d] : 0ull;
-    __syncthreads();
-    part[t] += v;
+  if (wave == 0) {
+    unsigned long long w = lane < 16 ? sh[lane] : 0ull;
+    w = wave_incl_scan(w, lane);
+    if (lane < 16) sh[lane] = w;
+  }
+  __syncthreads();
+  if (wave > 0) v += sh[wave - 1];
+  __syncthreads();
+  return v;
+}
+
+__global__ __launch_bounds__(1024) void k_tile_sums(ScanArgs a) {
+  __shared__ unsigned long long sh[16];
+  const uint64_t i = (uint64_t)blockIdx.x * kScanTile + threadIdx.x;
+  unsigned long long v = i < a.nchunks ? a.chunk_words[i] : 0ull;
+  v = block_incl_scan(v, sh);
+  if (threadIdx.x == kScanTile - 1) a.tile_sums[blockIdx.x] = v;
+}
+
+__global__ __launch_bounds__(1024) void k_tile_scan(ScanArgs a) {
+  __shared__ unsigned long long sh[16];
+  const uint64_t ntiles = (a.nchunks + kScanTile - 1) / kScanTile;
+  unsigned long long carry = 0;
+  for (uint64_t base = 0; base < ntiles; base += 1024) {  // exclusive scan in place
+    const uint64_t i = base + threadIdx.x;
+    unsigned long long v = i < ntiles ? a.tile_sums[i] : 0ull;
+    unsigned long long inc = block_incl_scan(v, sh);
+    if (i < ntiles) a.tile_sums[i] = carry + inc - v;
+    carry += sh[15];  // tile total (read before the barrier below)
     __syncthreads();
   }
-  unsigned long long run = part[t] - s;  // exclusive
-  bool big = false;
-  for (uint64_t i = lo; i < hi; ++i) {
-    if (run > 0xFFFFFFFFull) big = true;
-    a.offsets[i] = (uint32_t)run;
-    run += a.chunk_words[i];
-  }
-  if (big) atomicOr(&a.meta[a.comp].flags, (unsigned int)FLAG_INDEX);
-  __syncthreads();
-  if (t == 1023) {
+  if (threadIdx.x == 0) {
     CompMeta* m = &a.meta[a.comp];
-    const unsigned long long words = part[1023];
+    const unsigned long long words = carry;
     const unsigned long long bytes = (unsigned long long)kHeaderBytes + 4ull * a.nchunks + 4ull * words;
     m->payload_words = words;
     m->stream_bytes = bytes;
     const unsigned long long end = m->stream_offset + bytes;
     if (end > a.streams_cap) m->flags |= FLAG_OVERFLOW;
+    if (words > 0xFFFFFFFFull) m->flags |= FLAG_INDEX;
     if (a.comp + 1 < a.ncomp) a.meta[a.comp + 1].stream_offset = (end + 255ull) & ~255ull;
   }
+}
+
+__global__ __launch_bounds__(1024) void k_tile_offsets(ScanArgs a) {
+  __shared__ unsigned long long sh[16];
+  const uint64_t i = (uint64_t)blockIdx.x * kScanTile + threadIdx.x;
+  unsigned long long v = i < a.nchunks ? a.chunk_words[i] : 0ull;
+  unsigned long long inc = block_incl_scan(v, sh);
+  if (i < a.nchunks) a.offsets[i] = (uint32_t)(a.tile_sums[blockIdx.x] + inc - v);
 }
 
 // ---------------------------------------------------------------------------
@@ -387,86 +423,93 @@ __global__ __launch_bounds__(64) void k_pack(PackArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// decode components [0, ncomp) of DecArgs and add them into x~
+// Alg. 2 over one block per lane: x~ = (((x~_in or +0) + x_1) + x_2) ... in
+// the field precision; the block's bits start at its chunk's word offset plus
+// the block's bit offset from the per-block index
 template <class T>
-__global__ __launch_bounds__(64) void k_decode(DecArgs<T> a) {
+__device__ __forceinline__ bool decode_block_add(GBits& r, int minexp, T acc[64]) {
   typedef typename FT<T>::U U;
   constexpr int P = FT<T>::P;
-  __shared__ uint32_t s_pos[kMaxDecode][64];
-  __shared__ uint32_t s_end[kMaxDecode][64];
-  __shared__ uint32_t s_n[kMaxDecode][64];
-  __shared__ unsigned long long s_buf[kMaxDecode][64];
+  if (!r.get(1)) return true;  // empty: x_i = 0 leaves x~ unchanged
+  if (r.get(1)) {              // raw block
+#pragma unroll
+    for (int l = 0; l < 64; ++l) {
+      T v = from_raw((U)r.get64((uint32_t)P), (T)0);
+      acc[l] = acc[l] + v;
+    }
+    return true;
+  }
+  int delta = 0;
+  while (r.get(1)) {
+    if (++delta > P) return false;
+  }
+  const int emax = (int)r.get((uint32_t)FT<T>::EBITS) - FT<T>::BIAS;
+  int p = emax - minexp + kGuard;
+  p = (p < 0 ? 0 : (p > P ? P : p)) + delta;
+  if (emax < 2 - FT<T>::BIAS || p < 1 || p > P) return false;
+  U u[64];
+  planes_read<T>(r, u, p);
+  T dv[64];
+  inverse_values<T>(u, emax, dv);
+#pragma unroll
+  for (int l = 0; l < 64; ++l) acc[l] = acc[l] + dv[l];
+  return true;
+}
 
-  const uint32_t lane = threadIdx.x;
-  const uint64_t chunk = (uint64_t)blockIdx.x * 64 + lane;
-  if (chunk >= a.g.nchunks) return;
-  bool bad = false;
-
-  for (int i = 0; i < a.ncomp; ++i) {
+template <class T>
+__global__ __launch_bounds__(64) void k_decode(DecArgs<T> a) {
+  const uint64_t blk = (uint64_t)blockIdx.x * 64 + threadIdx.x;
+  if (blk >= a.g.nblocks) return;
+  const BlockPos bp = block_pos(a.g, blk);
+  const uint64_t chunk = blk / kChunkBlocks;
+  T acc[64];
+  if (a.in) {
+    load_block(a.in, a.g, bp, acc);
+  } else {
+#pragma unroll
+    for (int l = 0; l < 64; ++l) acc[l] = (T)0;
+  }
+  bool ok = true;
+  for (int i = 0; i < a.ncomp && ok; ++i) {
     const uint32_t* index = reinterpret_cast<const uint32_t*>(a.s[i] + kHeaderBytes);
-    const uint32_t start = index[chunk];
+    const uint32_t* payload = index + a.g.nchunks;
+    const uint64_t start = index[chunk];
     const uint64_t stop = chunk + 1 < a.g.nchunks ? (uint64_t)index[chunk + 1] : a.words[i];
-    if (start > stop || stop > a.words[i]) bad = true;
-    s_pos[i][lane] = start;
-    s_end[i][lane] = (uint32_t)(stop < start ? start : stop);
-    s_n[i][lane] = 0;
-    s_buf[i][lane] = 0;
+    const uint64_t off = a.aux[i][blk];
+    if (start > stop || stop > a.words[i] || off >= (stop - start) * 32) {
+      ok = false;
+      break;
+    }
+    GBits r;
+    r.init(payload + start + (off >> 5), payload + stop);
+    r.skip((uint32_t)(off & 31));
+    ok = decode_block_add<T>(r, a.minexp[i], acc) && !r.bad();
   }
+  if (ok) store_block(a.out, a.g, bp, acc);
+  else atomicOr(a.status, 1u);
+}
 
-  const uint64_t b0 = chunk * kChunkBlocks;
-  const uint64_t b1 = min<uint64_t>(a.g.nblocks, b0 + kChunkBlocks);
-  for (uint64_t blk = b0; blk < b1 && !bad; ++blk) {
-    BlockPos bp = block_pos(a.g, blk);
-    T acc[64];
-    if (a.in) {
-      load_block(a.in, a.g, bp, acc);
-    } else {
-#pragma unroll
-      for (int l = 0; l < 64; ++l) acc[l] = (T)0;
-    }
-    for (int i = 0; i < a.ncomp && !bad; ++i) {
-      const uint32_t* payload =
-          reinterpret_cast<const uint32_t*>(a.s[i] + kHeaderBytes) + a.g.nchunks;
-      GBits r;
-      r.p = payload + s_pos[i][lane];
-      r.end = payload + s_end[i][lane];
-      r.buf = s_buf[i][lane];
-      r.nbuf = s_n[i][lane];
-      r.overrun = 0;
-      if (r.get(1)) {
-        if (r.get(1)) {  // raw block
-#pragma unroll
-          for (int l = 0; l < 64; ++l) {
-            T v = from_raw((U)r.get64((uint32_t)P), (T)0);
-            acc[l] = acc[l] + v;
-          }
-        } else {
-          int delta = 0;
-          while (r.get(1)) {
-            if (++delta > P) { bad = true; break; }
-          }
-          const int emax = (int)r.get((uint32_t)FT<T>::EBITS) - FT<T>::BIAS;
-          int p = emax - a.minexp[i] + kGuard;
-          p = (p < 0 ? 0 : (p > P ? P : p)) + delta;
-          if (emax < 2 - FT<T>::BIAS || p < 1 || p > P) bad = true;
-          if (!bad) {
-            U u[64];
-            planes_read<T>(r, u, p);
-            T dv[64];
-            inverse_values<T>(u, emax, dv);
-#pragma unroll
-            for (int l = 0; l < 64; ++l) acc[l] = acc[l] + dv[l];
-          }
-        }
-      }
-      if (r.bad()) bad = true;
-      s_pos[i][lane] = (uint32_t)(r.p - payload);
-      s_buf[i][lane] = r.buf;
-      s_n[i][lane] = r.nbuf;
-    }
-    if (!bad) store_block(a.out, a.g, bp, acc);
+// per-block bit offsets of a stream written elsewhere: parse each chunk
+template <class T>
+__global__ __launch_bounds__(64) void k_aux(AuxArgs a) {
+  const uint64_t chunk = (uint64_t)blockIdx.x * 64 + threadIdx.x;
+  if (chunk >= a.g.nchunks) return;
+  const uint32_t* index = reinterpret_cast<const uint32_t*>(a.s + kHeaderBytes);
+  const uint32_t* payload = index + a.g.nchunks;
+  const uint64_t start = index[chunk];
+  const uint64_t stop = chunk + 1 < a.g.nchunks ? (uint64_t)index[chunk + 1] : a.words;
+  bool ok = start <= stop && stop <= a.words;
+  GBits r;
+  r.init(payload + start, payload + (ok ? stop : start));
+  uint64_t consumed = 0;
+  const uint64_t b0 = chunk * kChunkBlocks, b1 = min<uint64_t>(a.g.nblocks, b0 + kChunkBlocks);
+  for (uint64_t blk = b0; blk < b1; ++blk) {
+    // bits consumed so far = words fetched * 32 - bits still buffered
+    consumed = (uint64_t)(r.p - (payload + start)) * 32 - r.nbuf;
+    a.aux[blk] = ok ? (uint32_t)consumed : 0u;
+    if (ok) ok = block_skip<T>(r, a.minexp) && !r.bad();
   }
-  if (bad) atomicOr(a.status, 1u);
+  if (!ok && a.status) atomicOr(a.status, 1u);
 }
 
 // ---------------------------------------------------------------------------
@@ -515,7 +558,10 @@ template <class T> hipError_t launch_encode(const EncArgs<T>& a, hipStream_t s) 
   return hipGetLastError();
 }
 hipError_t launch_scan(const ScanArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, a);
+  const uint64_t tiles = (a.nchunks + kScanTile - 1) / kScanTile;
+  hipLaunchKernelGGL(k_tile_sums, dim3((uint32_t)tiles), dim3(kScanTile), 0, s, a);
+  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, a);
+  hipLaunchKernelGGL(k_tile_offsets, dim3((uint32_t)tiles), dim3(kScanTile), 0, s, a);
   return hipGetLastError();
 }
 template <class T> hipError_t launch_pack(const PackArgs& a, hipStream_t s) {
@@ -524,8 +570,13 @@ template <class T> hipError_t launch_pack(const PackArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 template <class T> hipError_t launch_decode(const DecArgs<T>& a, hipStream_t s) {
-  const uint64_t wgs = (a.g.nchunks + 63) / 64;
+  const uint64_t wgs = (a.g.nblocks + 63) / 64;
   hipLaunchKernelGGL(k_decode<T>, dim3((uint32_t)wgs), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+template <class T> hipError_t launch_aux(const AuxArgs& a, hipStream_t s) {
+  const uint64_t wgs = (a.g.nchunks + 63) / 64;
+  hipLaunchKernelGGL(k_aux<T>, dim3((uint32_t)wgs), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 template <class T> hipError_t launch_range(const T* x, uint64_t n, unsigned long long* out, hipStream_t s) {
@@ -547,6 +598,8 @@ template hipError_t launch_pack<float>(const PackArgs&, hipStream_t);
 template hipError_t launch_pack<double>(const PackArgs&, hipStream_t);
 template hipError_t launch_decode<float>(const DecArgs<float>&, hipStream_t);
 template hipError_t launch_decode<double>(const DecArgs<double>&, hipStream_t);
+template hipError_t launch_aux<float>(const AuxArgs&, hipStream_t);
+template hipError_t launch_aux<double>(const AuxArgs&, hipStream_t);
 template hipError_t launch_range<float>(const float*, uint64_t, unsigned long long*, hipStream_t);
 template hipError_t launch_range<double>(const double*, uint64_t, unsigned long long*, hipStream_t);
 

@@ -50,14 +50,21 @@ template <class T> struct EncArgs {
   int last;   // x~_i not written
   uint32_t* staging;
   uint32_t* chunk_words;
+  uint32_t* aux;   // per block: bit offset of the block inside its chunk
   CompMeta* meta;  // this component's entry
 };
+
+// chunk offsets are an exclusive scan of chunk word counts, done in tiles of
+// kScanTile chunks: tile sums, a scan of the tile sums, then per-tile scans
+constexpr int kScanTile = 1024;
 
 struct ScanArgs {
   const uint32_t* chunk_words;
   uint32_t* offsets;
+  unsigned long long* tile_sums;  // ceil(nchunks / kScanTile) entries
   uint64_t nchunks;
-  CompMeta* meta;  // all components
+  uint64_t aux_bytes;  // device bytes of one component's block index (256-aligned)
+  CompMeta* meta;      // all components
   int comp, ncomp;
   unsigned long long streams_cap;
 };
@@ -76,8 +83,9 @@ struct PackArgs {
 };
 
 template <class T> struct DecArgs {
-  const uint8_t* s[kMaxDecode];  // stream starts
-  uint64_t words[kMaxDecode];    // payload words of each stream
+  const uint8_t* s[kMaxDecode];    // stream starts
+  const uint32_t* aux[kMaxDecode];  // per-block bit offsets inside the chunk
+  uint64_t words[kMaxDecode];      // payload words of each stream
   int minexp[kMaxDecode];
   int ncomp;
   const T* in;  // x~ to continue from; NULL = +0
@@ -86,8 +94,19 @@ template <class T> struct DecArgs {
   unsigned int* status;  // bit 0: malformed stream
 };
 
+// rebuild the per-block bit offsets of one stream (one lane per chunk)
+struct AuxArgs {
+  const uint8_t* s;
+  uint32_t* aux;
+  uint64_t words;
+  int minexp;
+  Geo g;
+  unsigned int* status;  // optional (NULL): set when a chunk fails to parse
+};
+
 template <class T> hipError_t launch_encode(const EncArgs<T>& a, hipStream_t s);
 hipError_t launch_scan(const ScanArgs& a, hipStream_t s);
+template <class T> hipError_t launch_aux(const AuxArgs& a, hipStream_t s);
 template <class T> hipError_t launch_pack(const PackArgs& a, hipStream_t s);
 template <class T> hipError_t launch_decode(const DecArgs<T>& a, hipStream_t s);
 template <class T> hipError_t launch_range(const T* x, uint64_t n, unsigned long long* out, hipStream_t s);
