@@ -195,24 +195,33 @@ __device__ __forceinline__ uint32_t plane_cost(uint64_t wd, uint32_t& n) {
 
 // ---------------------------------------------------------------------------
 // LDS bit writer: bits LSB-first at an arbitrary start bit of a zeroed word
-// buffer; words shared with neighbouring lanes are merged with ds_or.
+// buffer; words shared with neighbouring lanes are merged with ds_or.  Only
+// words inside the window [w0, w0 + nw) are stored (buf points at word w0),
+// so a chunk larger than the LDS window is emitted in several passes.
 struct LdsBits {
   uint32_t* buf;
-  uint32_t word;
+  uint32_t word;  // absolute word index of the word being filled
   uint32_t nacc;
+  uint32_t w0, nw;
   uint64_t acc;
-  __device__ __forceinline__ void init(uint32_t* b, uint32_t bitpos) {
+  __device__ __forceinline__ void init(uint32_t* b, uint32_t bitpos, uint32_t win0, uint32_t nwin) {
     buf = b;
     word = bitpos >> 5;
     nacc = bitpos & 31u;
     acc = 0;
+    w0 = win0;
+    nw = nwin;
+  }
+  __device__ __forceinline__ void emit_word(uint32_t v) {
+    const uint32_t k = word - w0;  // wraps to a large value below the window
+    if (k < nw && v != 0u) atomicOr(&buf[k], v);
   }
   // count <= 32, value holds only its low `count` bits
   __device__ __forceinline__ void put(uint64_t value, uint32_t count) {
     acc |= value << nacc;
     nacc += count;
     if (nacc >= 32) {
-      atomicOr(&buf[word], (uint32_t)acc);
+      emit_word((uint32_t)acc);
       ++word;
       acc >>= 32;
       nacc -= 32;
@@ -228,7 +237,7 @@ struct LdsBits {
     }
   }
   __device__ __forceinline__ void flush() {
-    if (nacc > 0) atomicOr(&buf[word], (uint32_t)acc);
+    if (nacc > 0) emit_word((uint32_t)acc);
   }
 };
 
@@ -269,6 +278,7 @@ struct GBits {
     nbuf = 0;
     overrun = 0;
   }
+  // afterwards at least 32 bits are buffered
   __device__ __forceinline__ void refill() {
     if (nbuf <= 32) {
       uint32_t v = 0;
@@ -279,12 +289,16 @@ struct GBits {
       nbuf += 32;
     }
   }
-  __device__ __forceinline__ uint32_t get(uint32_t count) {  // count <= 32
-    refill();
-    uint64_t v = count == 32 ? (buf & 0xFFFFFFFFull) : (buf & ((1ull << count) - 1ull));
+  __device__ __forceinline__ void drop(uint32_t count) {  // count <= buffered bits
     buf >>= count;
     nbuf -= count;
-    return (uint32_t)v;
+  }
+  __device__ __forceinline__ uint32_t get(uint32_t count) {  // count <= 32
+    refill();
+    uint32_t lo = (uint32_t)buf;
+    uint32_t v = count >= 32 ? lo : (lo & ((1u << count) - 1u));
+    drop(count);
+    return v;
   }
   __device__ __forceinline__ uint64_t get64(uint32_t count) {  // count <= 64
     if (count > 32) {
@@ -295,43 +309,65 @@ struct GBits {
   }
   __device__ __forceinline__ void skip(uint32_t count) {  // count <= 32
     refill();
-    buf >>= count;
-    nbuf -= count;
+    drop(count);
   }
-  // bits consumed past the end of the chunk: the partially used buffer words
-  // beyond `end` are fine as long as their bits were not consumed
+  // bits consumed past the end of the chunk (fetched-but-unused zero words
+  // beyond `end` are fine)
   __device__ __forceinline__ bool bad() const {
     if (!overrun) return false;
-    // p - end words were fetched past the end; nbuf of them are unconsumed
     int64_t past_bits = (int64_t)(p - end) * 32 - (int64_t)nbuf;
     return past_bits > 0;
   }
 };
 
+// read one plane: n verbatim bits, then group tests; each positive test and
+// its run "0...01" is taken in one step from a 32-bit peek of the buffer
 __device__ __forceinline__ uint64_t plane_read(GBits& r, uint32_t& n) {
   uint64_t wd = 0;
   if (n > 0) wd = r.get64(n);
   while (n < 64) {
-    if (!r.get(1)) break;  // negative group test
-    for (;;) {
-      if (n == 63) {  // implied one
-        wd |= 1ull << 63;
-        n = 64;
-        break;
+    r.refill();
+    const uint32_t lo = (uint32_t)r.buf;
+    if ((lo & 1u) == 0u) {  // negative group test ends the plane
+      r.drop(1);
+      break;
+    }
+    const uint32_t limit = 63u - n;  // explicit run positions n..62
+    const uint32_t vis = limit < 31u ? limit : 31u;
+    const uint32_t run = (lo >> 1) & ((1u << vis) - 1u);
+    if (run != 0u) {
+      const uint32_t z = (uint32_t)__builtin_ctz(run);
+      r.drop(z + 2);
+      wd |= 1ull << (n + z);
+      n += z + 1;
+    } else if (limit <= 31u) {  // all explicit positions zero: the last one is implied
+      r.drop(limit + 1);
+      wd |= 1ull << 63;
+      n = 64;
+    } else {  // a run of more than 31 zeros: continue it without group bits
+      r.drop(32);
+      n += 31;
+      for (;;) {
+        r.refill();
+        const uint32_t lo2 = (uint32_t)r.buf;
+        const uint32_t lim2 = 63u - n;
+        const uint32_t run2 = lim2 >= 32u ? lo2 : (lo2 & ((1u << lim2) - 1u));
+        if (run2 != 0u) {
+          const uint32_t z = (uint32_t)__builtin_ctz(run2);
+          r.drop(z + 1);
+          wd |= 1ull << (n + z);
+          n += z + 1;
+          break;
+        }
+        if (lim2 <= 32u) {
+          r.drop(lim2);
+          wd |= 1ull << 63;
+          n = 64;
+          break;
+        }
+        r.drop(32);
+        n += 32;
       }
-      r.refill();
-      uint32_t look = 63u - n;
-      if (look > 32u) look = 32u;
-      uint64_t window = r.buf & ((1ull << look) - 1ull);
-      if (window != 0) {
-        uint32_t z = (uint32_t)__builtin_ctzll(window);
-        r.skip(z + 1);
-        wd |= 1ull << (n + z);
-        n = n + z + 1;
-        break;
-      }
-      r.skip(look);
-      n += look;
     }
   }
   return wd;
@@ -430,59 +466,63 @@ template <class U> __device__ __forceinline__ U plane_mask(int P, int p) {
   return p >= P ? ~(U)0 : ~(((U)1 << (P - p)) - (U)1);
 }
 
+// Plane words of one 16-plane group are kept in LDS, one column per lane:
+// word r of the calling lane at pw[r * 64] (plane base+r of coefficients
+// 0..31 in r, of 32..63 in 16+r), so the plane loops below run as ordinary
+// loops instead of 16 unrolled copies.
+template <class U> __device__ __forceinline__ void group_to_lds(const U u[64], int base, uint32_t* pw) {
+  uint32_t Tw[32];
+  plane_group(u, base, Tw);
+#pragma unroll
+  for (int r = 0; r < 32; ++r) pw[r * 64] = Tw[r];
+}
+// t-th plane from the top of the group
+__device__ __forceinline__ uint64_t lds_plane(const uint32_t* pw, int t) {
+  return (uint64_t)pw[(15 - t) * 64] | ((uint64_t)pw[(31 - t) * 64] << 32);
+}
+
 // bits of p planes from the top
-template <class T> __device__ __forceinline__ uint32_t planes_cost(const typename FT<T>::U u[64], int p) {
+template <class T>
+__device__ __forceinline__ uint32_t planes_cost(const typename FT<T>::U u[64], int p, uint32_t* pw) {
   constexpr int P = FT<T>::P;
   uint32_t n = 0, bits = 0;
   for (int g = 0; 16 * g < p; ++g) {
-    uint32_t Tw[32];
-    plane_group(u, P - 16 * (g + 1), Tw);
-#pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      if (16 * g + t < p) {
-        uint64_t wd = (uint64_t)Tw[15 - t] | ((uint64_t)Tw[31 - t] << 32);
-        bits += plane_cost(wd, n);
-      }
-    }
+    group_to_lds(u, P - 16 * (g + 1), pw);
+    const int tmax = p - 16 * g < 16 ? p - 16 * g : 16;
+    for (int t = 0; t < tmax; ++t) bits += plane_cost(lds_plane(pw, t), n);
   }
   return bits;
 }
 
-template <class T> __device__ __forceinline__ void planes_emit(LdsBits& w, const typename FT<T>::U u[64], int p) {
+template <class T>
+__device__ __forceinline__ void planes_emit(LdsBits& w, const typename FT<T>::U u[64], int p, uint32_t* pw) {
   constexpr int P = FT<T>::P;
   uint32_t n = 0;
   for (int g = 0; 16 * g < p; ++g) {
-    uint32_t Tw[32];
-    plane_group(u, P - 16 * (g + 1), Tw);
-#pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      if (16 * g + t < p) {
-        uint64_t wd = (uint64_t)Tw[15 - t] | ((uint64_t)Tw[31 - t] << 32);
-        plane_emit(w, wd, n);
-      }
-    }
+    group_to_lds(u, P - 16 * (g + 1), pw);
+    const int tmax = p - 16 * g < 16 ? p - 16 * g : 16;
+    for (int t = 0; t < tmax; ++t) plane_emit(w, lds_plane(pw, t), n);
   }
 }
 
 // read p planes from the top into u (zero below)
-template <class T> __device__ __forceinline__ void planes_read(GBits& r, typename FT<T>::U u[64], int p) {
+template <class T>
+__device__ __forceinline__ void planes_read(GBits& r, typename FT<T>::U u[64], int p, uint32_t* pw) {
   typedef typename FT<T>::U U;
   constexpr int P = FT<T>::P;
 #pragma unroll
   for (int j = 0; j < 64; ++j) u[j] = 0;
   uint32_t n = 0;
   for (int g = 0; 16 * g < p; ++g) {
+    const int tmax = p - 16 * g < 16 ? p - 16 * g : 16;
+    for (int t = 0; t < 16; ++t) {
+      uint64_t wd = t < tmax ? plane_read(r, n) : 0ull;
+      pw[(15 - t) * 64] = (uint32_t)wd;
+      pw[(31 - t) * 64] = (uint32_t)(wd >> 32);
+    }
     uint32_t Tw[32];
 #pragma unroll
-    for (int j = 0; j < 32; ++j) Tw[j] = 0;
-#pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      if (16 * g + t < p) {
-        uint64_t wd = plane_read(r, n);
-        Tw[15 - t] = (uint32_t)wd;
-        Tw[31 - t] = (uint32_t)(wd >> 32);
-      }
-    }
+    for (int j = 0; j < 32; ++j) Tw[j] = pw[j * 64];
     transpose32(Tw);  // back to 16-bit slices of coefficients j and j+32
     const int base = P - 16 * (g + 1);
 #pragma unroll

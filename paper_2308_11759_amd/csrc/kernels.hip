@@ -48,14 +48,21 @@ __device__ __forceinline__ bool lvalid(const BlockPos& b, int l) {
   return (uint32_t)(l & 3) < b.vx && (uint32_t)((l >> 2) & 3) < b.vy && (uint32_t)(l >> 4) < b.vz;
 }
 
+// one block row (ly, lz): 4 consecutive x values; rows of partial blocks
+// repeat their last valid sample (edge replication on load)
+template <class T>
+__device__ __forceinline__ const T* row_ptr(const T* f, const Geo& g, const BlockPos& b, int r) {
+  const uint32_t ly = min<uint32_t>(r & 3, b.vy - 1), lz = min<uint32_t>(r >> 2, b.vz - 1);
+  return f + b.x0 + g.nx * ((b.y0 + ly) + g.ny * (b.z0 + lz));
+}
+
 template <class T>
 __device__ __forceinline__ void load_block(const T* __restrict__ f, const Geo& g, const BlockPos& b, T v[64]) {
-  const bool full = b.vx == 4 && b.vy == 4 && b.vz == 4;
-  if (full && g.rows_aligned) {
+  const bool vec = b.vx == 4 && g.rows_aligned;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const uint64_t y = b.y0 + (r & 3), z = b.z0 + (r >> 2);
-      const T* row = f + b.x0 + g.nx * (y + g.ny * z);
+  for (int r = 0; r < 16; ++r) {
+    const T* row = row_ptr(f, g, b, r);
+    if (vec) {
       if constexpr (sizeof(T) == 4) {
         float4 q = *reinterpret_cast<const float4*>(row);
         v[4 * r] = q.x; v[4 * r + 1] = q.y; v[4 * r + 2] = q.z; v[4 * r + 3] = q.w;
@@ -64,39 +71,45 @@ __device__ __forceinline__ void load_block(const T* __restrict__ f, const Geo& g
         double2 q1 = *reinterpret_cast<const double2*>(row + 2);
         v[4 * r] = q0.x; v[4 * r + 1] = q0.y; v[4 * r + 2] = q1.x; v[4 * r + 3] = q1.y;
       }
-    }
-  } else {
-#pragma unroll
-    for (int l = 0; l < 64; ++l) {
-      const uint64_t x = b.x0 + min<uint32_t>(l & 3, b.vx - 1);
-      const uint64_t y = b.y0 + min<uint32_t>((l >> 2) & 3, b.vy - 1);
-      const uint64_t z = b.z0 + min<uint32_t>(l >> 4, b.vz - 1);
-      v[l] = f[x + g.nx * (y + g.ny * z)];
+    } else {
+      const uint32_t m = b.vx - 1;
+      v[4 * r] = row[0];
+      v[4 * r + 1] = row[min<uint32_t>(1, m)];
+      v[4 * r + 2] = row[min<uint32_t>(2, m)];
+      v[4 * r + 3] = row[min<uint32_t>(3, m)];
     }
   }
 }
 
 template <class T>
 __device__ __forceinline__ void store_block(T* __restrict__ f, const Geo& g, const BlockPos& b, const T v[64]) {
-  const bool full = b.vx == 4 && b.vy == 4 && b.vz == 4;
-  if (full && g.rows_aligned) {
+  const bool vec = b.vx == 4 && g.rows_aligned;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const uint64_t y = b.y0 + (r & 3), z = b.z0 + (r >> 2);
-      T* row = f + b.x0 + g.nx * (y + g.ny * z);
+  for (int r = 0; r < 16; ++r) {
+    if ((uint32_t)(r & 3) >= b.vy || (uint32_t)(r >> 2) >= b.vz) continue;
+    T* row = const_cast<T*>(row_ptr((const T*)f, g, b, r));
+    if (vec) {
       if constexpr (sizeof(T) == 4) {
         *reinterpret_cast<float4*>(row) = make_float4(v[4 * r], v[4 * r + 1], v[4 * r + 2], v[4 * r + 3]);
       } else {
         *reinterpret_cast<double2*>(row) = make_double2(v[4 * r], v[4 * r + 1]);
         *reinterpret_cast<double2*>(row + 2) = make_double2(v[4 * r + 2], v[4 * r + 3]);
       }
-    }
-  } else {
-#pragma unroll
-    for (int l = 0; l < 64; ++l) {
-      if (lvalid(b, l)) f[b.x0 + (l & 3) + g.nx * (b.y0 + ((l >> 2) & 3) + g.ny * (b.z0 + (l >> 4)))] = v[l];
+    } else {
+      row[0] = v[4 * r];
+      if (b.vx > 1) row[1] = v[4 * r + 1];
+      if (b.vx > 2) row[2] = v[4 * r + 2];
+      if (b.vx > 3) row[3] = v[4 * r + 3];
     }
   }
+}
+
+// a copy the compiler cannot prove equal to the original: recomputing the
+// residual from such copies stops common-subexpression elimination from
+// keeping a 64-value array alive across the whole kernel
+template <class T> __device__ __forceinline__ T opaque(T v) {
+  __asm__ volatile("" : "+v"(v));
+  return v;
 }
 
 // NaN-propagating max, matching "take a if not a <= m"
@@ -110,22 +123,25 @@ __device__ __forceinline__ double wave_max(double v) {
 
 // ---------------------------------------------------------------------------
 // encode one component
+constexpr uint32_t kEmitWords = 256;  // LDS window per chunk, in 32-bit words
+
 template <class T>
 __global__ __launch_bounds__(64) void k_encode(EncArgs<T> a) {
   typedef typename FT<T>::U U;
   constexpr int P = FT<T>::P;
   constexpr int CAP = chunk_cap_words<T>();
-  __shared__ uint32_t lds[4 * CAP];
+  __shared__ uint32_t s_planes[32 * 64];
+  __shared__ uint32_t s_emit[4 * kEmitWords];
+  __shared__ T s_x[64 * 64];  // the block's x values, column per lane
 
   const uint32_t lane = threadIdx.x;
+  uint32_t* pw = s_planes + lane;
+  T* sx = s_x + lane;  // x value l of this lane's block at sx[l * 64]
   const uint64_t blk = (uint64_t)blockIdx.x * 64 + lane;
   const bool active = blk < a.g.nblocks;
 
-  for (uint32_t i = lane; i < 4 * CAP; i += 64) lds[i] = 0;
-
   BlockPos bp = block_pos(a.g, active ? blk : 0);
-  T xv[64], tv[64];
-  load_block(a.x, a.g, bp, xv);
+  T tv[64];
   if (a.first) {
 #pragma unroll
     for (int l = 0; l < 64; ++l) tv[l] = (T)0;
@@ -137,13 +153,18 @@ __global__ __launch_bounds__(64) void k_encode(EncArgs<T> a) {
   U maxabs = 0;
   double eb = 0.0;
   bool nonfinite = false;
+  {
+    T xv[64];
+    load_block(a.x, a.g, bp, xv);
 #pragma unroll
-  for (int l = 0; l < 64; ++l) {
-    T ev = xv[l] - tv[l];
-    U ab = abs_bits(ev);
-    maxabs = ab > maxabs ? ab : maxabs;
-    if (lvalid(bp, l)) eb = nmax(eb, fabs((double)xv[l] - (double)tv[l]));
-    nonfinite |= !isfinite(xv[l]);
+    for (int l = 0; l < 64; ++l) {
+      sx[l * 64] = xv[l];
+      T ev = xv[l] - tv[l];
+      U ab = abs_bits(ev);
+      maxabs = ab > maxabs ? ab : maxabs;
+      if (lvalid(bp, l)) eb = nmax(eb, fabs((double)xv[l] - (double)tv[l]));
+      nonfinite |= !isfinite(xv[l]);
+    }
   }
   const int emax = block_emax<T>(maxabs);
   int p = emax - a.minexp + kGuard;
@@ -152,19 +173,21 @@ __global__ __launch_bounds__(64) void k_encode(EncArgs<T> a) {
   uint32_t nbits = 1;
   double err = eb;
 
+  // acceptance: smallest plane count p >= p0 whose block meets tau without
+  // raising the error; else empty (already within tau) or raw
   if (active && maxabs != 0) {
     for (;;) {
       U u[64];
       {
         T e[64];
 #pragma unroll
-        for (int l = 0; l < 64; ++l) e[l] = xv[l] - tv[l];
+        for (int l = 0; l < 64; ++l) e[l] = sx[l * 64] - opaque(tv[l]);
         forward_coeffs<T>(e, emax, u);
       }
       bool feasible = false;
       uint32_t cb = 0;
       if (p >= 1 && p <= P) {
-        cb = 2u + (uint32_t)(delta + 1) + (uint32_t)FT<T>::EBITS + planes_cost<T>(u, p);
+        cb = 2u + (uint32_t)(delta + 1) + (uint32_t)FT<T>::EBITS + planes_cost<T>(u, p, pw);
         feasible = cb <= (uint32_t)FT<T>::RAW_BITS;
       }
       if (feasible) {
@@ -177,7 +200,7 @@ __global__ __launch_bounds__(64) void k_encode(EncArgs<T> a) {
 #pragma unroll
         for (int l = 0; l < 64; ++l) {
           d[l] = tv[l] + d[l];  // x~_{i-1} + x_i in the field precision
-          if (lvalid(bp, l)) ea = nmax(ea, fabs((double)xv[l] - (double)d[l]));
+          if (lvalid(bp, l)) ea = nmax(ea, fabs((double)sx[l * 64] - (double)d[l]));
         }
         if (ea <= a.tau && ea <= eb) {
           mode = MODE_CODED;
@@ -208,8 +231,9 @@ __global__ __launch_bounds__(64) void k_encode(EncArgs<T> a) {
     double ea = 0.0;
 #pragma unroll
     for (int l = 0; l < 64; ++l) {
-      d[l] = tv[l] + (xv[l] - tv[l]);
-      if (lvalid(bp, l)) ea = nmax(ea, fabs((double)xv[l] - (double)d[l]));
+      const T xl = sx[l * 64];
+      d[l] = tv[l] + (xl - tv[l]);
+      if (lvalid(bp, l)) ea = nmax(ea, fabs((double)xl - (double)d[l]));
     }
     err = ea;
     miss = !(ea <= a.tau && ea <= eb);
@@ -250,6 +274,18 @@ __global__ __launch_bounds__(64) void k_encode(EncArgs<T> a) {
     }
   }
 
+  // what the block emits: coefficients (coded) or the residual's bits (raw)
+  U u[64];
+  if (mode == MODE_CODED) {
+    T e[64];
+#pragma unroll
+    for (int l = 0; l < 64; ++l) e[l] = sx[l * 64] - opaque(tv[l]);
+    forward_coeffs<T>(e, emax, u);
+  } else {
+#pragma unroll
+    for (int l = 0; l < 64; ++l) u[l] = (U)raw_bits_lo((T)(sx[l * 64] - opaque(tv[l])));
+  }
+
   // offsets of the blocks inside their chunk (16 lanes = one chunk)
   uint32_t incl = nbits;
 #pragma unroll
@@ -259,49 +295,52 @@ __global__ __launch_bounds__(64) void k_encode(EncArgs<T> a) {
   }
   const uint32_t off = incl - nbits;
   if (active) a.aux[blk] = off;
-  __syncthreads();  // zeroed LDS visible to every lane
-
-  if (active) {
-    LdsBits w;
-    w.init(&lds[(lane >> 4) * CAP], off);
-    if (mode == MODE_EMPTY) {
-      w.put(0, 1);
-    } else if (mode == MODE_RAW) {
-      w.put(3, 2);
-#pragma unroll
-      for (int l = 0; l < 64; ++l) {
-        T ev = xv[l] - tv[l];
-        w.put64((uint64_t)raw_bits_lo(ev), (uint32_t)P);
-      }
-    } else {
-      w.put(1, 2);  // nonempty, coded
-      for (int t = 0; t < delta; ++t) w.put(1, 1);
-      w.put(0, 1);
-      w.put((uint64_t)(emax + FT<T>::BIAS), (uint32_t)FT<T>::EBITS);
-      U u[64];
-      {
-        T e[64];
-#pragma unroll
-        for (int l = 0; l < 64; ++l) e[l] = xv[l] - tv[l];
-        forward_coeffs<T>(e, emax, u);
-      }
-      planes_emit<T>(w, u, p);
-    }
-    w.flush();
-  }
-  __syncthreads();
-
-  // copy the four chunk bitstreams to their staging slots
+  uint32_t cwords[4];
+  uint32_t maxw = 0;
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    const uint32_t bits = __shfl(incl, 16 * c + 15, 64);
-    const uint64_t chunk = (uint64_t)blockIdx.x * 4 + c;
-    if (chunk < a.g.nchunks) {
-      const uint32_t words = (bits + 31) / 32;
-      uint32_t* dst = a.staging + chunk * (uint64_t)CAP;
-      for (uint32_t i = lane; i < words; i += 64) dst[i] = lds[c * CAP + i];
-      if (lane == 0) a.chunk_words[chunk] = words;
+    cwords[c] = (__shfl(incl, 16 * c + 15, 64) + 31) / 32;
+    maxw = cwords[c] > maxw ? cwords[c] : maxw;
+  }
+
+  // emit the four chunk bitstreams through LDS windows of kEmitWords words
+  for (uint32_t w0 = 0; w0 < maxw; w0 += kEmitWords) {
+    for (uint32_t i = lane; i < 4 * kEmitWords; i += 64) s_emit[i] = 0;
+    __syncthreads();
+    const uint64_t lo_bit = (uint64_t)w0 * 32, hi_bit = (uint64_t)(w0 + kEmitWords) * 32;
+    if (active && (uint64_t)off < hi_bit && (uint64_t)off + nbits > lo_bit) {
+      LdsBits w;
+      w.init(&s_emit[(lane >> 4) * kEmitWords], off, w0, kEmitWords);
+      if (mode == MODE_EMPTY) {
+        w.put(0, 1);
+      } else if (mode == MODE_RAW) {
+        w.put(3, 2);
+        for (int l = 0; l < 64; ++l) w.put64((uint64_t)u[l], (uint32_t)P);
+      } else {
+        w.put(1, 2);  // nonempty, coded
+        for (int t = 0; t < delta; ++t) w.put(1, 1);
+        w.put(0, 1);
+        w.put((uint64_t)(emax + FT<T>::BIAS), (uint32_t)FT<T>::EBITS);
+        planes_emit<T>(w, u, p, pw);
+      }
+      w.flush();
     }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const uint64_t chunk = (uint64_t)blockIdx.x * 4 + c;
+      if (chunk < a.g.nchunks && cwords[c] > w0) {
+        const uint32_t nw = cwords[c] - w0 < kEmitWords ? cwords[c] - w0 : kEmitWords;
+        uint32_t* dst = a.staging + chunk * (uint64_t)CAP + w0;
+        for (uint32_t i = lane; i < nw; i += 64) dst[i] = s_emit[c * kEmitWords + i];
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const uint64_t chunk = (uint64_t)blockIdx.x * 4 + c;
+    if (lane == 0 && chunk < a.g.nchunks) a.chunk_words[chunk] = cwords[c];
   }
 }
 
@@ -427,7 +466,7 @@ __global__ __launch_bounds__(64) void k_pack(PackArgs a) {
 // the field precision; the block's bits start at its chunk's word offset plus
 // the block's bit offset from the per-block index
 template <class T>
-__device__ __forceinline__ bool decode_block_add(GBits& r, int minexp, T acc[64]) {
+__device__ __forceinline__ bool decode_block_add(GBits& r, int minexp, T acc[64], uint32_t* pw) {
   typedef typename FT<T>::U U;
   constexpr int P = FT<T>::P;
   if (!r.get(1)) return true;  // empty: x_i = 0 leaves x~ unchanged
@@ -448,7 +487,7 @@ __device__ __forceinline__ bool decode_block_add(GBits& r, int minexp, T acc[64]
   p = (p < 0 ? 0 : (p > P ? P : p)) + delta;
   if (emax < 2 - FT<T>::BIAS || p < 1 || p > P) return false;
   U u[64];
-  planes_read<T>(r, u, p);
+  planes_read<T>(r, u, p, pw);
   T dv[64];
   inverse_values<T>(u, emax, dv);
 #pragma unroll
@@ -458,6 +497,8 @@ __device__ __forceinline__ bool decode_block_add(GBits& r, int minexp, T acc[64]
 
 template <class T>
 __global__ __launch_bounds__(64) void k_decode(DecArgs<T> a) {
+  __shared__ uint32_t s_planes[32 * 64];
+  uint32_t* pw = s_planes + threadIdx.x;
   const uint64_t blk = (uint64_t)blockIdx.x * 64 + threadIdx.x;
   if (blk >= a.g.nblocks) return;
   const BlockPos bp = block_pos(a.g, blk);
@@ -483,7 +524,7 @@ __global__ __launch_bounds__(64) void k_decode(DecArgs<T> a) {
     GBits r;
     r.init(payload + start + (off >> 5), payload + stop);
     r.skip((uint32_t)(off & 31));
-    ok = decode_block_add<T>(r, a.minexp[i], acc) && !r.bad();
+    ok = decode_block_add<T>(r, a.minexp[i], acc, pw) && !r.bad();
   }
   if (ok) store_block(a.out, a.g, bp, acc);
   else atomicOr(a.status, 1u);
