@@ -462,6 +462,31 @@ __device__ __forceinline__ void inverse_values(const typename FT<T>::U u[64], in
   for (int l = 0; l < 64; ++l) d[l] = dequantize(q[l], emax);
 }
 
+// the inverse split so that its last (x) pass can run one block row at a time:
+// coefficients -> integers after the z and y passes ...
+template <class T>
+__device__ __forceinline__ void inverse_zy(const typename FT<T>::U u[64], typename FT<T>::S q[64]) {
+#pragma unroll
+  for (int r = 0; r < 64; ++r) q[kOrder.at[r]] = from_nb<T>(u[r]);
+#pragma unroll
+  for (int l = 0; l < 16; ++l) {
+    const int b = l;
+    lift_inv(q[b], q[b + 16], q[b + 32], q[b + 48]);
+  }
+#pragma unroll
+  for (int l = 0; l < 16; ++l) {
+    const int b = 16 * (l >> 2) + (l & 3);
+    lift_inv(q[b], q[b + 4], q[b + 8], q[b + 12]);
+  }
+}
+// ... then row r (ly = r & 3, lz = r >> 2): x pass and dequantisation
+template <class T>
+__device__ __forceinline__ void inverse_row(typename FT<T>::S q[64], int r, int emax, T out[4]) {
+  lift_inv(q[4 * r], q[4 * r + 1], q[4 * r + 2], q[4 * r + 3]);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) out[t] = dequantize(q[4 * r + t], emax);
+}
+
 template <class U> __device__ __forceinline__ U plane_mask(int P, int p) {
   return p >= P ? ~(U)0 : ~(((U)1 << (P - p)) - (U)1);
 }
@@ -479,6 +504,23 @@ template <class U> __device__ __forceinline__ void group_to_lds(const U u[64], i
 // t-th plane from the top of the group
 __device__ __forceinline__ uint64_t lds_plane(const uint32_t* pw, int t) {
   return (uint64_t)pw[(15 - t) * 64] | ((uint64_t)pw[(31 - t) * 64] << 32);
+}
+
+// bits of p planes from the top, plane words in registers (the closed-form
+// cost is short, so the 16-plane loop can be unrolled)
+template <class T> __device__ __forceinline__ uint32_t planes_cost_reg(const typename FT<T>::U u[64], int p) {
+  constexpr int P = FT<T>::P;
+  uint32_t n = 0, bits = 0;
+  for (int g = 0; 16 * g < p; ++g) {
+    uint32_t Tw[32];
+    plane_group(u, P - 16 * (g + 1), Tw);
+    const int tmax = p - 16 * g;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      if (t < tmax) bits += plane_cost((uint64_t)Tw[15 - t] | ((uint64_t)Tw[31 - t] << 32), n);
+    }
+  }
+  return bits;
 }
 
 // bits of p planes from the top

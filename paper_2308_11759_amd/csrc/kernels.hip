@@ -104,12 +104,36 @@ __device__ __forceinline__ void store_block(T* __restrict__ f, const Geo& g, con
   }
 }
 
+// store row r of a block (valid samples only)
+template <class T>
+__device__ __forceinline__ void store_row(T* __restrict__ f, const Geo& g, const BlockPos& b, int r, const T v[4]) {
+  if ((uint32_t)(r & 3) >= b.vy || (uint32_t)(r >> 2) >= b.vz) return;
+  T* row = const_cast<T*>(row_ptr((const T*)f, g, b, r));
+  if (b.vx == 4 && g.rows_aligned) {
+    if constexpr (sizeof(T) == 4) {
+      *reinterpret_cast<float4*>(row) = make_float4(v[0], v[1], v[2], v[3]);
+    } else {
+      *reinterpret_cast<double2*>(row) = make_double2(v[0], v[1]);
+      *reinterpret_cast<double2*>(row + 2) = make_double2(v[2], v[3]);
+    }
+  } else {
+    row[0] = v[0];
+    if (b.vx > 1) row[1] = v[1];
+    if (b.vx > 2) row[2] = v[2];
+    if (b.vx > 3) row[3] = v[3];
+  }
+}
+
 // a copy the compiler cannot prove equal to the original: recomputing the
 // residual from such copies stops common-subexpression elimination from
 // keeping a 64-value array alive across the whole kernel
 template <class T> __device__ __forceinline__ T opaque(T v) {
   __asm__ volatile("" : "+v"(v));
   return v;
+}
+template <class T> __device__ __forceinline__ T* opaque(T* p) {
+  __asm__ volatile("" : "+v"(p));
+  return p;
 }
 
 // NaN-propagating max, matching "take a if not a <= m"
@@ -125,22 +149,68 @@ __device__ __forceinline__ double wave_max(double v) {
 // encode one component
 constexpr uint32_t kEmitWords = 256;  // LDS window per chunk, in 32-bit words
 
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) const void gmem_void_t;
+
+// the block's x values in LDS, [row r][lane][4 values] (f32) or
+// [row r][half h][lane][2 values] (f64): each 16-byte piece of a row is one
+// direct global->LDS load (global_load_lds_dwordx4), so x never occupies
+// VGPRs; partial or unaligned rows are written by plain loads
+template <class T> struct XLds {
+  T* base;  // s_x
+  uint32_t lane;
+  __device__ __forceinline__ T* slot(int r, int t) const {
+    if constexpr (sizeof(T) == 4) return base + ((uint32_t)r * 64 + lane) * 4 + t;
+    else return base + (((uint32_t)r * 2 + (t >> 1)) * 64 + lane) * 2 + (t & 1);
+  }
+  __device__ __forceinline__ T at(int l) const { return *slot(l >> 2, l & 3); }
+};
+
+template <class T>
+__device__ __forceinline__ void load_block_lds(const T* __restrict__ f, const Geo& g, const BlockPos& b, T* s_x,
+                                               uint32_t lane) {
+  const bool vec = b.vx == 4 && g.rows_aligned;
+  XLds<T> X{s_x, lane};
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const T* row = row_ptr(f, g, b, r);
+    if (vec) {
+      if constexpr (sizeof(T) == 4) {
+        __builtin_amdgcn_global_load_lds((gmem_void_t*)row, (lds_void_t*)(s_x + r * 256), 16, 0, 0);
+      } else {
+        __builtin_amdgcn_global_load_lds((gmem_void_t*)row, (lds_void_t*)(s_x + (r * 2) * 128), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((gmem_void_t*)(row + 2), (lds_void_t*)(s_x + (r * 2 + 1) * 128), 16, 0,
+                                         0);
+      }
+    } else {
+      const uint32_t m = b.vx - 1;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) *X.slot(r, t) = row[min<uint32_t>(t, m)];
+    }
+  }
+  __builtin_amdgcn_s_waitcnt(0);  // direct loads and LDS writes complete
+}
+
 template <class T>
 __global__ __launch_bounds__(64) void k_encode(EncArgs<T> a) {
   typedef typename FT<T>::U U;
   constexpr int P = FT<T>::P;
   constexpr int CAP = chunk_cap_words<T>();
-  __shared__ uint32_t s_planes[32 * 64];
-  __shared__ uint32_t s_emit[4 * kEmitWords];
-  __shared__ T s_x[64 * 64];  // the block's x values, column per lane
+  // LDS: the block's x values while deciding; once x is dead the same bytes
+  // hold the emission windows and the plane words
+  __shared__ T s_x[64 * 64];
+  static_assert(sizeof(s_x) >= 4 * (4 * kEmitWords + 32 * 64), "LDS reuse");
+  uint32_t* const s_emit = reinterpret_cast<uint32_t*>(s_x);
+  uint32_t* const s_planes = s_emit + 4 * kEmitWords;
 
   const uint32_t lane = threadIdx.x;
   uint32_t* pw = s_planes + lane;
-  T* sx = s_x + lane;  // x value l of this lane's block at sx[l * 64]
   const uint64_t blk = (uint64_t)blockIdx.x * 64 + lane;
   const bool active = blk < a.g.nblocks;
 
   BlockPos bp = block_pos(a.g, active ? blk : 0);
+  load_block_lds(a.x, a.g, bp, s_x, lane);
+  const XLds<T> X{s_x, lane};
   T tv[64];
   if (a.first) {
 #pragma unroll
@@ -153,18 +223,14 @@ __global__ __launch_bounds__(64) void k_encode(EncArgs<T> a) {
   U maxabs = 0;
   double eb = 0.0;
   bool nonfinite = false;
-  {
-    T xv[64];
-    load_block(a.x, a.g, bp, xv);
 #pragma unroll
-    for (int l = 0; l < 64; ++l) {
-      sx[l * 64] = xv[l];
-      T ev = xv[l] - tv[l];
-      U ab = abs_bits(ev);
-      maxabs = ab > maxabs ? ab : maxabs;
-      if (lvalid(bp, l)) eb = nmax(eb, fabs((double)xv[l] - (double)tv[l]));
-      nonfinite |= !isfinite(xv[l]);
-    }
+  for (int l = 0; l < 64; ++l) {
+    const T xl = X.at(l);
+    T ev = xl - tv[l];
+    U ab = abs_bits(ev);
+    maxabs = ab > maxabs ? ab : maxabs;
+    if (lvalid(bp, l)) eb = nmax(eb, fabs((double)xl - (double)tv[l]));
+    nonfinite |= !isfinite(xl);
   }
   const int emax = block_emax<T>(maxabs);
   int p = emax - a.minexp + kGuard;
@@ -172,41 +238,54 @@ __global__ __launch_bounds__(64) void k_encode(EncArgs<T> a) {
   int mode = MODE_EMPTY, delta = 0;
   uint32_t nbits = 1;
   double err = eb;
+  bool dirty = false;  // x~ rows of a rejected candidate were stored
 
   // acceptance: smallest plane count p >= p0 whose block meets tau without
   // raising the error; else empty (already within tau) or raw
   if (active && maxabs != 0) {
     for (;;) {
+      // re-derived each iteration so the LDS reads below are not hoisted
+      // out of the loop into 64 registers
+      const XLds<T> XL{opaque(s_x), lane};
       U u[64];
       {
         T e[64];
 #pragma unroll
-        for (int l = 0; l < 64; ++l) e[l] = sx[l * 64] - opaque(tv[l]);
+        for (int l = 0; l < 64; ++l) e[l] = XL.at(l) - opaque(tv[l]);
         forward_coeffs<T>(e, emax, u);
       }
       bool feasible = false;
       uint32_t cb = 0;
       if (p >= 1 && p <= P) {
-        cb = 2u + (uint32_t)(delta + 1) + (uint32_t)FT<T>::EBITS + planes_cost<T>(u, p, pw);
+        cb = 2u + (uint32_t)(delta + 1) + (uint32_t)FT<T>::EBITS + planes_cost_reg<T>(u, p);
         feasible = cb <= (uint32_t)FT<T>::RAW_BITS;
       }
       if (feasible) {
         const U m = plane_mask<U>(P, p);
 #pragma unroll
         for (int r = 0; r < 64; ++r) u[r] &= m;
-        T d[64];
-        inverse_values<T>(u, emax, d);
+        // decode, add and check one row at a time; x~_i rows are stored as
+        // they come (a rejected candidate is overwritten below)
+        typename FT<T>::S q[64];
+        inverse_zy<T>(u, q);
         double ea = 0.0;
 #pragma unroll
-        for (int l = 0; l < 64; ++l) {
-          d[l] = tv[l] + d[l];  // x~_{i-1} + x_i in the field precision
-          if (lvalid(bp, l)) ea = nmax(ea, fabs((double)sx[l * 64] - (double)d[l]));
+        for (int r = 0; r < 16; ++r) {
+          T row[4];
+          inverse_row<T>(q, r, emax, row);
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int l = 4 * r + t;
+            row[t] = tv[l] + row[t];  // x~_{i-1} + x_i in the field precision
+            if (lvalid(bp, l)) ea = nmax(ea, fabs((double)XL.at(l) - (double)row[t]));
+          }
+          if (!a.last) store_row(a.xt, a.g, bp, r, row);
         }
+        dirty = !a.last;
         if (ea <= a.tau && ea <= eb) {
           mode = MODE_CODED;
           nbits = cb;
           err = ea;
-          if (!a.last) store_block(a.xt, a.g, bp, d);
           break;
         }
       }
@@ -231,7 +310,7 @@ __global__ __launch_bounds__(64) void k_encode(EncArgs<T> a) {
     double ea = 0.0;
 #pragma unroll
     for (int l = 0; l < 64; ++l) {
-      const T xl = sx[l * 64];
+      const T xl = X.at(l);
       d[l] = tv[l] + (xl - tv[l]);
       if (lvalid(bp, l)) ea = nmax(ea, fabs((double)xl - (double)d[l]));
     }
@@ -240,8 +319,9 @@ __global__ __launch_bounds__(64) void k_encode(EncArgs<T> a) {
     if (!a.last) store_block(a.xt, a.g, bp, d);
   } else if (active && mode == MODE_EMPTY) {
     miss = !(eb <= a.tau);
-    // x~_i = x~_{i-1} + 0: only a fresh x~ (first component) needs writing
-    if (a.first && !a.last) {
+    // x~_i = x~_{i-1} + 0: written when x~ is fresh (first component) or a
+    // rejected candidate overwrote it
+    if (!a.last && (a.first || dirty)) {
       T d[64];
 #pragma unroll
       for (int l = 0; l < 64; ++l) d[l] = tv[l] + (T)0;
@@ -279,12 +359,14 @@ __global__ __launch_bounds__(64) void k_encode(EncArgs<T> a) {
   if (mode == MODE_CODED) {
     T e[64];
 #pragma unroll
-    for (int l = 0; l < 64; ++l) e[l] = sx[l * 64] - opaque(tv[l]);
+    for (int l = 0; l < 64; ++l) e[l] = X.at(l) - opaque(tv[l]);
     forward_coeffs<T>(e, emax, u);
   } else {
 #pragma unroll
-    for (int l = 0; l < 64; ++l) u[l] = (U)raw_bits_lo((T)(sx[l * 64] - opaque(tv[l])));
+    for (int l = 0; l < 64; ++l) u[l] = (U)raw_bits_lo((T)(X.at(l) - opaque(tv[l])));
   }
+
+  __syncthreads();  // every lane is done with x: its LDS is reused below
 
   // offsets of the blocks inside their chunk (16 lanes = one chunk)
   uint32_t incl = nbits;
@@ -488,10 +570,15 @@ __device__ __forceinline__ bool decode_block_add(GBits& r, int minexp, T acc[64]
   if (emax < 2 - FT<T>::BIAS || p < 1 || p > P) return false;
   U u[64];
   planes_read<T>(r, u, p, pw);
-  T dv[64];
-  inverse_values<T>(u, emax, dv);
+  typename FT<T>::S q[64];
+  inverse_zy<T>(u, q);
 #pragma unroll
-  for (int l = 0; l < 64; ++l) acc[l] = acc[l] + dv[l];
+  for (int row = 0; row < 16; ++row) {
+    T v[4];
+    inverse_row<T>(q, row, emax, v);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[4 * row + t] = acc[4 * row + t] + v[t];
+  }
   return true;
 }
 
