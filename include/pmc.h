@@ -147,6 +147,35 @@ pmc_status pmc_store_deserialize(pmc_ctx* ctx, const void* host_buf, size_t size
                                  pmc_store** out);
 void pmc_store_free(pmc_store* s);
 
+/* ---- batches: many fields of uneven size and mixed type ---------------
+ * Alg. 1 for nf fields at once.  All components of all fields run as one
+ * captured HIP graph, replayed on every pmc_batch_compress: per component a
+ * persistent encode kernel per element type walks a list of (field, 64-block
+ * group) items, then a segmented chunk scan and a batched pack run.  The
+ * schedule (persistent grid = grid_mult x compute units; item order 0 =
+ * field-major, 1 = interleaved across fields, 2 = largest field first) never
+ * changes the output bytes.  n[i] components for field i with tolerances
+ * tau[i][0] > ... > tau[i][n[i]-1] > 0.  With the environment variable
+ * PMC_TUNE_CACHE naming a file, plans reuse and pmc_batch_tune records the
+ * schedule chosen for the same size class. */
+typedef struct pmc_batch pmc_batch;
+pmc_status pmc_batch_plan(pmc_ctx* ctx, int nf, const pmc_field* fields, const int* n, const double* const* tau,
+                          pmc_batch** out);
+/* device workspace and stream-buffer bytes a batch needs */
+pmc_status pmc_batch_sizes(const pmc_batch* b, size_t* ws_bytes, size_t* streams_bytes);
+pmc_status pmc_batch_schedule(pmc_batch* b, int grid_mult, int order);
+pmc_status pmc_batch_get_schedule(const pmc_batch* b, int* grid_mult, int* order);
+/* d_x[i]: field i on the device.  out[i] receives a store per field whose
+ * streams live in d_streams.  Synchronises once to read the sizes. */
+pmc_status pmc_batch_compress(pmc_batch* b, const void* const* d_x, void* d_ws, size_t ws_bytes, void* d_streams,
+                              size_t streams_cap, pmc_store** out);
+/* Autotuner: times every schedule (grid_mult 1, 2, 4, 8 x 3 orders) on these
+ * inputs with HIP events, keeps the fastest and reports its graph time. */
+pmc_status pmc_batch_tune(pmc_batch* b, const void* const* d_x, void* d_ws, size_t ws_bytes, void* d_streams,
+                          size_t streams_cap, float* best_ms);
+const char* pmc_batch_order_name(int order);
+void pmc_batch_free(pmc_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

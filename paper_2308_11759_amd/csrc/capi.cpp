@@ -11,88 +11,12 @@
 #include <string>
 #include <vector>
 
-#include "../../include/pmc.h"
-#include "launch.hpp"
+#include "internal.hpp"
 
 using namespace pmc;
+using namespace pmc_host;
 
-struct ProfRec {
-  int kernel;
-  hipEvent_t start, stop;
-};
-
-struct pmc_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  std::string err;
-  int fused_decode = 1;
-  int sync_check = 0;
-  int profile = 0;
-  std::vector<std::string> prof_names;
-  std::vector<uint64_t> prof_launches;
-  std::vector<double> prof_ms;
-  std::vector<ProfRec> prof_pending;
-  std::vector<hipEvent_t> prof_pool;
-};
-
-namespace {
-
-hipEvent_t prof_event(pmc_ctx* c) {
-  if (!c->prof_pool.empty()) {
-    hipEvent_t e = c->prof_pool.back();
-    c->prof_pool.pop_back();
-    return e;
-  }
-  hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
-  return e;
-}
-
-int prof_kernel_id(pmc_ctx* c, const char* name) {
-  for (size_t i = 0; i < c->prof_names.size(); ++i)
-    if (c->prof_names[i] == name) return (int)i;
-  c->prof_names.push_back(name);
-  c->prof_launches.push_back(0);
-  c->prof_ms.push_back(0.0);
-  return (int)c->prof_names.size() - 1;
-}
-
-// brackets one kernel launch with events on the context stream when enabled
-struct ProfScope {
-  pmc_ctx* c;
-  ProfRec r{};
-  bool on;
-  ProfScope(pmc_ctx* ctx, const char* name) : c(ctx), on(ctx->profile != 0) {
-    if (!on) return;
-    r.kernel = prof_kernel_id(c, name);
-    r.start = prof_event(c);
-    r.stop = prof_event(c);
-    if (!r.start || !r.stop) {
-      on = false;
-      return;
-    }
-    (void)hipEventRecord(r.start, c->stream);
-  }
-  ~ProfScope() {
-    if (!on) return;
-    (void)hipEventRecord(r.stop, c->stream);
-    c->prof_pending.push_back(r);
-  }
-};
-
-}  // namespace
-
-struct pmc_store {
-  pmc_field f{};
-  Geo g{};
-  int n = 0;
-  std::vector<double> tau, linf;
-  std::vector<int> minexp;
-  std::vector<uint64_t> bytes, offset, aux_offset, words, nempty, ncoded, nraw, nesc, nmiss;
-  const uint8_t* d_base = nullptr;  // caller-owned device memory holding the streams
-};
-
-namespace {
+namespace pmc_host {
 
 pmc_status fail(pmc_ctx* ctx, pmc_status st, const char* fmt, ...) {
   if (ctx) {
@@ -175,7 +99,34 @@ uint64_t stream_cap_one(const Geo& g, int dtype) {
 // streams, each on a 256-byte boundary
 uint64_t aux_bytes(const Geo& g) { return align256(4 * g.nblocks); }
 
-}  // namespace
+pmc_store* store_from_meta(const pmc_field* f, const Geo& g, int n, const double* tau, const int* minexp,
+                           const CompMeta* hm, const uint8_t* d_base) {
+  pmc_store* s = new pmc_store();
+  s->f = *f;
+  s->g = g;
+  s->n = n;
+  s->d_base = d_base;
+  const uint64_t auxb = aux_bytes(g);
+  for (int i = 0; i < n; ++i) {
+    double l;
+    std::memcpy(&l, &hm[i].linf_bits, 8);
+    s->tau.push_back(tau[i]);
+    s->linf.push_back(l);
+    s->minexp.push_back(minexp[i]);
+    s->bytes.push_back(hm[i].stream_bytes);
+    s->offset.push_back(hm[i].stream_offset);
+    s->aux_offset.push_back(i * auxb);
+    s->words.push_back(hm[i].payload_words);
+    s->nempty.push_back(hm[i].nempty);
+    s->ncoded.push_back(hm[i].ncoded);
+    s->nraw.push_back(hm[i].nraw);
+    s->nesc.push_back(hm[i].nesc);
+    s->nmiss.push_back(hm[i].nmiss);
+  }
+  return s;
+}
+
+}  // namespace pmc_host
 
 extern "C" {
 
@@ -425,27 +376,7 @@ pmc_status pmc_compress(pmc_ctx* ctx, const pmc_field* f, const void* d_x, int n
     for (int i = 0; i < n; ++i) need = align256(need) + hm[i].stream_bytes;
     return fail(ctx, PMC_E_NOMEM, "stream capacity too small: need %llu bytes", need);
   }
-  pmc_store* s = new pmc_store();
-  s->f = *f;
-  s->g = g;
-  s->n = n;
-  s->d_base = (const uint8_t*)d_streams;
-  for (int i = 0; i < n; ++i) {
-    double l;
-    std::memcpy(&l, &hm[i].linf_bits, 8);
-    s->tau.push_back(tau[i]);
-    s->linf.push_back(l);
-    s->minexp.push_back(minexp[i]);
-    s->bytes.push_back(hm[i].stream_bytes);
-    s->offset.push_back(hm[i].stream_offset);
-    s->aux_offset.push_back(i * auxb);
-    s->words.push_back(hm[i].payload_words);
-    s->nempty.push_back(hm[i].nempty);
-    s->ncoded.push_back(hm[i].ncoded);
-    s->nraw.push_back(hm[i].nraw);
-    s->nesc.push_back(hm[i].nesc);
-    s->nmiss.push_back(hm[i].nmiss);
-  }
+  pmc_store* s = store_from_meta(f, g, n, tau, minexp.data(), hm.data(), (const uint8_t*)d_streams);
   *out = s;
   if (misses) return fail(ctx, PMC_E_BOUND, "%llu blocks missed their tolerance", misses);
   return PMC_OK;

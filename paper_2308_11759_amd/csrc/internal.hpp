@@ -1,0 +1,100 @@
+// internal.hpp -- host-side objects shared by the C-ABI translation units
+// (capi.cpp: single fields and stores; batch.cpp: batches of fields).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/pmc.h"
+#include "launch.hpp"
+
+struct ProfRec {
+  int kernel;
+  hipEvent_t start, stop;
+};
+
+struct pmc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  int fused_decode = 1;
+  int sync_check = 0;
+  int profile = 0;
+  std::vector<std::string> prof_names;
+  std::vector<uint64_t> prof_launches;
+  std::vector<double> prof_ms;
+  std::vector<ProfRec> prof_pending;
+  std::vector<hipEvent_t> prof_pool;
+};
+
+struct pmc_store {
+  pmc_field f{};
+  pmc::Geo g{};
+  int n = 0;
+  std::vector<double> tau, linf;
+  std::vector<int> minexp;
+  std::vector<uint64_t> bytes, offset, aux_offset, words, nempty, ncoded, nraw, nesc, nmiss;
+  const uint8_t* d_base = nullptr;  // caller-owned device memory holding the streams
+};
+
+namespace pmc_host {
+
+pmc_status fail(pmc_ctx* ctx, pmc_status st, const char* fmt, ...);
+pmc_status hipfail(pmc_ctx* ctx, hipError_t e, const char* what);
+bool make_geo(const pmc_field* f, pmc::Geo* g);
+uint64_t elem_size(const pmc_field* f);
+uint64_t align256(uint64_t v);
+int floor_log2(double tau);
+uint64_t stream_cap_one(const pmc::Geo& g, int dtype);
+uint64_t aux_bytes(const pmc::Geo& g);
+// a store from per-component device results (offsets relative to d_base)
+pmc_store* store_from_meta(const pmc_field* f, const pmc::Geo& g, int n, const double* tau, const int* minexp,
+                           const pmc::CompMeta* hm, const uint8_t* d_base);
+
+inline hipEvent_t prof_event(pmc_ctx* c) {
+  if (!c->prof_pool.empty()) {
+    hipEvent_t e = c->prof_pool.back();
+    c->prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+inline int prof_kernel_id(pmc_ctx* c, const char* name) {
+  for (size_t i = 0; i < c->prof_names.size(); ++i)
+    if (c->prof_names[i] == name) return (int)i;
+  c->prof_names.push_back(name);
+  c->prof_launches.push_back(0);
+  c->prof_ms.push_back(0.0);
+  return (int)c->prof_names.size() - 1;
+}
+
+// brackets one kernel launch (or graph launch) with events on the context
+// stream when profiling is enabled
+struct ProfScope {
+  pmc_ctx* c;
+  ProfRec r{};
+  bool on;
+  ProfScope(pmc_ctx* ctx, const char* name) : c(ctx), on(ctx->profile != 0) {
+    if (!on) return;
+    r.kernel = prof_kernel_id(c, name);
+    r.start = prof_event(c);
+    r.stop = prof_event(c);
+    if (!r.start || !r.stop) {
+      on = false;
+      return;
+    }
+    (void)hipEventRecord(r.start, c->stream);
+  }
+  ~ProfScope() {
+    if (!on) return;
+    (void)hipEventRecord(r.stop, c->stream);
+    c->prof_pending.push_back(r);
+  }
+};
+
+}  // namespace pmc_host

@@ -191,21 +191,22 @@ __device__ __forceinline__ void load_block_lds(const T* __restrict__ f, const Ge
   __builtin_amdgcn_s_waitcnt(0);  // direct loads and LDS writes complete
 }
 
+// one wave = 64 consecutive blocks = 4 chunks; `wave` numbers these groups
+// within the field.  s_x: 64 * 64 values of LDS owned by this wave.
 template <class T>
-__global__ __launch_bounds__(64) void k_encode(EncArgs<T> a) {
+__device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T* s_x) {
   typedef typename FT<T>::U U;
   constexpr int P = FT<T>::P;
   constexpr int CAP = chunk_cap_words<T>();
   // LDS: the block's x values while deciding; once x is dead the same bytes
   // hold the emission windows and the plane words
-  __shared__ T s_x[64 * 64];
-  static_assert(sizeof(s_x) >= 4 * (4 * kEmitWords + 32 * 64), "LDS reuse");
+  static_assert(64 * 64 * sizeof(T) >= 4 * (4 * kEmitWords + 32 * 64), "LDS reuse");
   uint32_t* const s_emit = reinterpret_cast<uint32_t*>(s_x);
   uint32_t* const s_planes = s_emit + 4 * kEmitWords;
 
   const uint32_t lane = threadIdx.x;
   uint32_t* pw = s_planes + lane;
-  const uint64_t blk = (uint64_t)blockIdx.x * 64 + lane;
+  const uint64_t blk = (uint64_t)wave * 64 + lane;
   const bool active = blk < a.g.nblocks;
 
   BlockPos bp = block_pos(a.g, active ? blk : 0);
@@ -410,7 +411,7 @@ __global__ __launch_bounds__(64) void k_encode(EncArgs<T> a) {
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const uint64_t chunk = (uint64_t)blockIdx.x * 4 + c;
+      const uint64_t chunk = (uint64_t)wave * 4 + c;
       if (chunk < a.g.nchunks && cwords[c] > w0) {
         const uint32_t nw = cwords[c] - w0 < kEmitWords ? cwords[c] - w0 : kEmitWords;
         uint32_t* dst = a.staging + chunk * (uint64_t)CAP + w0;
@@ -421,9 +422,15 @@ __global__ __launch_bounds__(64) void k_encode(EncArgs<T> a) {
   }
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    const uint64_t chunk = (uint64_t)blockIdx.x * 4 + c;
+    const uint64_t chunk = (uint64_t)wave * 4 + c;
     if (lane == 0 && chunk < a.g.nchunks) a.chunk_words[chunk] = cwords[c];
   }
+}
+
+template <class T>
+__global__ __launch_bounds__(64) void k_encode(EncArgs<T> a) {
+  __shared__ T s_x[64 * 64];
+  encode_wave<T>(a, blockIdx.x, s_x);
 }
 
 // ---------------------------------------------------------------------------
@@ -679,6 +686,145 @@ __global__ void k_fill64(unsigned long long* p, uint64_t n, unsigned long long v
 }
 
 // ---------------------------------------------------------------------------
+// batches: many fields of mixed size and type in persistent launches.  Work
+// is listed as items; each workgroup walks the list with a static stride, so
+// a field's bytes depend only on its own blocks, never on the schedule.
+template <class T> __device__ __forceinline__ EncArgs<T> field_enc_args(const FieldDev& f, int comp) {
+  EncArgs<T> a;
+  a.x = reinterpret_cast<const T*>(f.x);
+  a.xt = reinterpret_cast<T*>(f.xt);
+  a.g = f.g;
+  a.tau = f.tau[comp];
+  a.minexp = f.minexp[comp];
+  a.first = comp == 0;
+  a.last = comp == f.ncomp - 1;
+  a.staging = f.staging;
+  a.chunk_words = f.chunk_words;
+  a.aux = f.aux0 + (uint64_t)comp * f.aux_stride;
+  a.meta = f.meta0 + comp;
+  return a;
+}
+
+template <class T>
+__global__ __launch_bounds__(64) void k_encode_batch(BatchArgs b) {
+  __shared__ T s_x[64 * 64];
+  for (uint32_t it = blockIdx.x; it < b.nitems; it += gridDim.x) {
+    const Item w = b.items[it];
+    const FieldDev* f = b.fields + w.field;
+    if (b.comp < f->ncomp) encode_wave<T>(field_enc_args<T>(*f, b.comp), w.index, s_x);
+    __syncthreads();  // the next item reuses s_x
+  }
+}
+
+// stream bookkeeping at the start: component 0's stream follows the field's
+// block indexes
+__global__ void k_batch_init(const FieldDev* fields, uint32_t nfields) {
+  const uint32_t f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nfields) return;
+  const FieldDev& d = fields[f];
+  for (int i = 0; i < d.ncomp; ++i) {
+    unsigned long long* m = reinterpret_cast<unsigned long long*>(d.meta0 + i);
+    for (int w = 0; w < (int)(sizeof(CompMeta) / 8); ++w) m[w] = 0ull;
+  }
+  d.meta0[0].stream_offset = (unsigned long long)d.ncomp * d.aux_stride * 4ull;
+}
+
+__global__ __launch_bounds__(1024) void k_btile_sums(BatchArgs b) {
+  __shared__ unsigned long long sh[16];
+  const Item t = b.items[blockIdx.x];
+  const FieldDev& f = b.fields[t.field];
+  if (b.comp >= f.ncomp) return;  // uniform across the workgroup
+  const uint64_t i = (uint64_t)t.index * kScanTile + threadIdx.x;
+  unsigned long long v = i < f.g.nchunks ? f.chunk_words[i] : 0ull;
+  v = block_incl_scan(v, sh);
+  if (threadIdx.x == kScanTile - 1) f.tile_sums[t.index] = v;
+}
+
+__global__ __launch_bounds__(1024) void k_btile_scan(BatchArgs b) {
+  __shared__ unsigned long long sh[16];
+  const FieldDev& f = b.fields[blockIdx.x];
+  if (b.comp >= f.ncomp) return;
+  unsigned long long carry = 0;
+  for (uint64_t base = 0; base < f.ntiles; base += 1024) {
+    const uint64_t i = base + threadIdx.x;
+    unsigned long long v = i < f.ntiles ? f.tile_sums[i] : 0ull;
+    unsigned long long inc = block_incl_scan(v, sh);
+    if (i < f.ntiles) f.tile_sums[i] = carry + inc - v;
+    carry += sh[15];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    CompMeta* m = f.meta0 + b.comp;
+    const unsigned long long words = carry;
+    const unsigned long long bytes = (unsigned long long)kHeaderBytes + 4ull * f.g.nchunks + 4ull * words;
+    m->payload_words = words;
+    m->stream_bytes = bytes;
+    const unsigned long long end = m->stream_offset + bytes;
+    if (end > f.region_cap) m->flags |= FLAG_OVERFLOW;
+    if (words > 0xFFFFFFFFull) m->flags |= FLAG_INDEX;
+    if (b.comp + 1 < f.ncomp) f.meta0[b.comp + 1].stream_offset = (end + 255ull) & ~255ull;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_btile_offsets(BatchArgs b) {
+  __shared__ unsigned long long sh[16];
+  const Item t = b.items[blockIdx.x];
+  const FieldDev& f = b.fields[t.field];
+  if (b.comp >= f.ncomp) return;
+  const uint64_t i = (uint64_t)t.index * kScanTile + threadIdx.x;
+  unsigned long long v = i < f.g.nchunks ? f.chunk_words[i] : 0ull;
+  unsigned long long inc = block_incl_scan(v, sh);
+  if (i < f.g.nchunks) f.offsets[i] = (uint32_t)(f.tile_sums[t.index] + inc - v);
+}
+
+__global__ __launch_bounds__(64) void k_bpack(BatchArgs b) {
+  const Item q = b.items[blockIdx.x];
+  const FieldDev& f = b.fields[q.field];
+  if (b.comp >= f.ncomp) return;
+  const CompMeta* m = f.meta0 + b.comp;
+  if (m->flags & (FLAG_OVERFLOW | FLAG_INDEX)) return;
+  const uint64_t cap = f.dtype == 1 ? (uint64_t)chunk_cap_words<float>() : (uint64_t)chunk_cap_words<double>();
+  uint8_t* base = f.region + m->stream_offset;
+  uint32_t* index = reinterpret_cast<uint32_t*>(base + kHeaderBytes);
+  uint32_t* payload = index + f.g.nchunks;
+  const uint32_t lane = threadIdx.x;
+  const uint64_t chunk = (uint64_t)q.index * 4 + (lane >> 4);
+  const uint32_t sub = lane & 15;
+  if (chunk < f.g.nchunks) {
+    const uint32_t words = f.chunk_words[chunk];
+    const uint32_t o = f.offsets[chunk];
+    const uint32_t* src = f.staging + chunk * cap;
+    for (uint32_t i = sub; i < words; i += 16) payload[o + i] = src[i];
+    if (sub == 0) index[chunk] = o;
+  }
+  if (q.index == 0 && lane < 16) {
+    uint32_t* h = reinterpret_cast<uint32_t*>(base);
+    const double tau = f.tau[b.comp];
+    const uint64_t taub = (uint64_t)__double_as_longlong(tau);
+    uint32_t v = 0;
+    switch (lane) {
+      case 0: v = kMagic; break;
+      case 1: v = (uint32_t)kVersion | ((uint32_t)f.dtype << 16) | (3u << 24); break;
+      case 2: v = (uint32_t)f.g.nx; break;
+      case 3: v = (uint32_t)(f.g.nx >> 32); break;
+      case 4: v = (uint32_t)f.g.ny; break;
+      case 5: v = (uint32_t)(f.g.ny >> 32); break;
+      case 6: v = (uint32_t)f.g.nz; break;
+      case 7: v = (uint32_t)(f.g.nz >> 32); break;
+      case 8: v = (uint32_t)taub; break;
+      case 9: v = (uint32_t)(taub >> 32); break;
+      case 10: v = (uint32_t)f.minexp[b.comp]; break;
+      case 11: v = (uint32_t)kChunkBlocks; break;
+      case 12: v = (uint32_t)f.g.nchunks; break;
+      case 13: v = (uint32_t)(f.g.nchunks >> 32); break;
+      case 14: v = (uint32_t)m->payload_words; break;
+      case 15: v = (uint32_t)(m->payload_words >> 32); break;
+    }
+    h[lane] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // host launchers
 template <class T> hipError_t launch_encode(const EncArgs<T>& a, hipStream_t s) {
   const uint64_t wgs = (a.g.nblocks + 63) / 64;
@@ -714,12 +860,33 @@ template <class T> hipError_t launch_range(const T* x, uint64_t n, unsigned long
   hipLaunchKernelGGL(k_range<T>, dim3((uint32_t)wgs), dim3(256), 0, s, x, n, out);
   return hipGetLastError();
 }
+template <class T> hipError_t launch_encode_batch(const BatchArgs& a, uint32_t grid, hipStream_t s) {
+  if (a.nitems == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_encode_batch<T>, dim3(grid), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_batch_scan(const BatchArgs& tiles, uint32_t nfields, hipStream_t s) {
+  hipLaunchKernelGGL(k_btile_sums, dim3(tiles.nitems), dim3(kScanTile), 0, s, tiles);
+  hipLaunchKernelGGL(k_btile_scan, dim3(nfields), dim3(1024), 0, s, tiles);
+  hipLaunchKernelGGL(k_btile_offsets, dim3(tiles.nitems), dim3(kScanTile), 0, s, tiles);
+  return hipGetLastError();
+}
+hipError_t launch_batch_pack(const BatchArgs& quads, hipStream_t s) {
+  hipLaunchKernelGGL(k_bpack, dim3(quads.nitems), dim3(64), 0, s, quads);
+  return hipGetLastError();
+}
+hipError_t launch_batch_init(const FieldDev* fields, uint32_t nfields, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_init, dim3((nfields + 63) / 64), dim3(64), 0, s, fields, nfields);
+  return hipGetLastError();
+}
 hipError_t launch_fill64(unsigned long long* p, uint64_t n, unsigned long long v, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill64, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
   return hipGetLastError();
 }
 
+template hipError_t launch_encode_batch<float>(const BatchArgs&, uint32_t, hipStream_t);
+template hipError_t launch_encode_batch<double>(const BatchArgs&, uint32_t, hipStream_t);
 template hipError_t launch_encode<float>(const EncArgs<float>&, hipStream_t);
 template hipError_t launch_encode<double>(const EncArgs<double>&, hipStream_t);
 template hipError_t launch_pack<float>(const PackArgs&, hipStream_t);

@@ -104,6 +104,45 @@ struct AuxArgs {
   unsigned int* status;  // optional (NULL): set when a chunk fails to parse
 };
 
+// ---- batches of fields (one table entry per field) -----------------------
+struct FieldDev {
+  const void* x;
+  void* xt;
+  Geo g;
+  uint32_t* staging;
+  uint32_t* chunk_words;
+  uint32_t* offsets;
+  unsigned long long* tile_sums;
+  uint32_t* aux0;           // block index of component 0; component i at aux0 + i * aux_stride
+  uint64_t aux_stride;      // in 32-bit words
+  CompMeta* meta0;          // meta of component 0; component i at meta0 + i
+  uint8_t* region;          // the field's stream region: block indexes, then streams
+  unsigned long long region_cap;
+  int ncomp;
+  int dtype;                // 1 = f32, 2 = f64
+  uint32_t ntiles;          // scan tiles of the field
+  uint32_t pad;
+  double tau[kMaxComps];
+  int minexp[kMaxComps];
+};
+
+struct Item {  // (field, group) : a wave of 64 blocks, a scan tile, or 4 chunks
+  uint32_t field, index;
+};
+
+struct BatchArgs {
+  const FieldDev* fields;
+  uint32_t nfields;
+  const Item* items;  // encode waves of one dtype, scan tiles or chunk quads
+  uint32_t nitems;
+  int comp;
+};
+
+template <class T> hipError_t launch_encode_batch(const BatchArgs& a, uint32_t grid, hipStream_t s);
+hipError_t launch_batch_scan(const BatchArgs& tiles, uint32_t nfields, hipStream_t s);
+hipError_t launch_batch_pack(const BatchArgs& quads, hipStream_t s);
+hipError_t launch_batch_init(const FieldDev* fields, uint32_t nfields, hipStream_t s);
+
 template <class T> hipError_t launch_encode(const EncArgs<T>& a, hipStream_t s);
 hipError_t launch_scan(const ScanArgs& a, hipStream_t s);
 template <class T> hipError_t launch_aux(const AuxArgs& a, hipStream_t s);

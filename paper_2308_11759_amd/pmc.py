@@ -65,6 +65,14 @@ SIGNATURES = {
     "pmc_store_deserialize": (_int, [_vp, _vp, _sz, _vp, _sz, _P(_vp)]),
     "pmc_store_free": (None, [_vp]),
     "pmc_prof_read": (_int, [_vp, _P(ProfEntry), _int, _P(_int), _int]),
+    "pmc_batch_plan": (_int, [_vp, _int, _P(Field), _P(_int), _P(_P(_dbl)), _P(_vp)]),
+    "pmc_batch_sizes": (_int, [_vp, _P(_sz), _P(_sz)]),
+    "pmc_batch_schedule": (_int, [_vp, _int, _int]),
+    "pmc_batch_get_schedule": (_int, [_vp, _P(_int), _P(_int)]),
+    "pmc_batch_compress": (_int, [_vp, _P(_vp), _vp, _sz, _vp, _sz, _P(_vp)]),
+    "pmc_batch_tune": (_int, [_vp, _P(_vp), _vp, _sz, _vp, _sz, _P(ctypes.c_float)]),
+    "pmc_batch_order_name": (ctypes.c_char_p, [_int]),
+    "pmc_batch_free": (None, [_vp]),
 }
 
 
@@ -219,6 +227,10 @@ class Context:
                                         self._dec_ws.numel()))
         return xt
 
+    def batch(self, shapes_dtypes, taus):
+        """Plan a batch: shapes_dtypes = [(shape, torch dtype)], taus = [[tau...]]."""
+        return Batch(self, shapes_dtypes, taus)
+
     def deserialize(self, blob, streams=None):
         """Rebuild a store from bytes written by Store.serialize (or any valid blob)."""
         blob = bytes(blob)
@@ -231,6 +243,85 @@ class Context:
         self._check(self.lib.pmc_store_deserialize(self.handle, buf, len(blob), ctypes.c_void_p(streams.data_ptr()),
                                                    streams.numel(), ctypes.byref(h)))
         return Store(self, h, streams)
+
+
+class Batch:
+    """Many fields compressed together (one captured HIP graph per call)."""
+
+    def __init__(self, ctx, shapes_dtypes, taus):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        nf = len(shapes_dtypes)
+        assert len(taus) == nf
+        self.fields = (Field * nf)()
+        for i, (shape, dt) in enumerate(shapes_dtypes):
+            dims = list(reversed(list(shape))) + [1] * (3 - len(shape))
+            self.fields[i].nx, self.fields[i].ny, self.fields[i].nz = dims
+            self.fields[i].dtype = _dtype_code(dt)
+        self.shapes = [tuple(s) for s, _ in shapes_dtypes]
+        self.n = (ctypes.c_int * nf)(*[len(t) for t in taus])
+        self._tau_arrays = [(ctypes.c_double * len(t))(*[float(v) for v in t]) for t in taus]
+        tau_ptrs = (_P(_dbl) * nf)(*[ctypes.cast(a, _P(_dbl)) for a in self._tau_arrays])
+        h = ctypes.c_void_p()
+        ctx._check(self.lib.pmc_batch_plan(ctx.handle, nf, self.fields, self.n, tau_ptrs, ctypes.byref(h)))
+        self.handle = h
+        ws, st = ctypes.c_size_t(), ctypes.c_size_t()
+        self.lib.pmc_batch_sizes(h, ctypes.byref(ws), ctypes.byref(st))
+        self.ws = torch.empty(max(ws.value, 256), dtype=torch.uint8, device=ctx.device)
+        self.streams = torch.empty(max(st.value, 256), dtype=torch.uint8, device=ctx.device)
+        self.nf = nf
+
+    def _ptrs(self, xs):
+        assert len(xs) == self.nf
+        for i, x in enumerate(xs):
+            f = field_of(x)
+            g = self.fields[i]
+            if (f.nx, f.ny, f.nz, f.dtype) != (g.nx, g.ny, g.nz, g.dtype):
+                raise ValueError("field %d does not match the plan" % i)
+        return (_vp * self.nf)(*[x.data_ptr() for x in xs])
+
+    def schedule(self, grid_mult=None, order=None):
+        gm, od = ctypes.c_int(), ctypes.c_int()
+        self.lib.pmc_batch_get_schedule(self.handle, ctypes.byref(gm), ctypes.byref(od))
+        if grid_mult is not None or order is not None:
+            gm.value = gm.value if grid_mult is None else grid_mult
+            od.value = od.value if order is None else order
+            self.ctx._check(self.lib.pmc_batch_schedule(self.handle, gm.value, od.value))
+        return gm.value, od.value
+
+    def tune(self, xs):
+        ms = ctypes.c_float()
+        self.ctx._check(self.lib.pmc_batch_tune(self.handle, self._ptrs(xs), ctypes.c_void_p(self.ws.data_ptr()),
+                                                self.ws.numel(), ctypes.c_void_p(self.streams.data_ptr()),
+                                                self.streams.numel(), ctypes.byref(ms)))
+        return self.schedule() + (ms.value,)
+
+    def compress(self, xs, streams=None):
+        """Returns one Store per field; their streams share one device buffer
+        (a fresh one per call unless `streams` is given)."""
+        if streams is None:
+            streams = torch.empty_like(self.streams)
+        outs = (_vp * self.nf)()
+        st = self.lib.pmc_batch_compress(self.handle, self._ptrs(xs), ctypes.c_void_p(self.ws.data_ptr()),
+                                         self.ws.numel(), ctypes.c_void_p(streams.data_ptr()), streams.numel(),
+                                         outs)
+        if st != OK:
+            for o in outs:
+                if o:
+                    self.lib.pmc_store_free(ctypes.c_void_p(o))
+            self.ctx._check(st)
+        return [Store(self.ctx, ctypes.c_void_p(o), streams) for o in outs]
+
+    def free(self):
+        if getattr(self, "handle", None):
+            self.lib.pmc_batch_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 class Store:

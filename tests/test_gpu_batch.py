@@ -1,0 +1,108 @@
+"""Batched compression (many fields of uneven size and mixed type in one
+captured HIP graph) against the oracle and against itself under every
+schedule.  The graph is replayed several times with eager work in between and
+every replay is checked."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import driver
+from paper_2308_11759_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def make_fields(count=10, seed=300, lo=5, hi=40):
+    rng = np.random.default_rng(seed)
+    out = []
+    for f in range(count):
+        dims = tuple(int(round(np.exp(rng.uniform(np.log(lo), np.log(hi))))) for _ in range(3))
+        dt = np.float32 if f % 2 == 0 else np.float64
+        out.append(inputs.spectral_field(dims, seed=seed + f, dtype=dt))
+    return out
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+    from paper_2308_11759_amd import pmc
+    ctx = pmc.Context(0)
+    ctx.set_option(pmc.OPT_SYNC_CHECK, 1)
+    xs = make_fields()
+    taus = []
+    for x in xs:
+        r = float(x.max() - x.min())
+        taus.append([r * 4.0 ** -(i + 1) for i in range(4 if x.dtype == np.float32 else 5)])
+    say("batch of %d fields: %s" % (len(xs), [x.shape for x in xs]))
+    oracle = [driver.compress(x, t) for x, t in zip(xs, taus)]
+    dev = [torch.from_numpy(x).to("cuda:0") for x in xs]
+    batch = ctx.batch([(x.shape, d.dtype) for x, d in zip(xs, dev)], taus)
+    yield ctx, xs, taus, oracle, dev, batch
+    torch.cuda.synchronize()
+
+
+def streams_of(stores):
+    return [[s.stream(i).cpu().numpy() for i in range(s.n)] for s in stores]
+
+
+def test_batch_matches_oracle(setup):
+    ctx, xs, taus, oracle, dev, batch = setup
+    stores = batch.compress(dev)
+    for f, (x, st) in enumerate(zip(xs, stores)):
+        comps, meta = oracle[f]
+        for i in range(len(comps)):
+            assert np.array_equal(st.stream(i).cpu().numpy(), comps[i]), (f, i)
+            assert st.info[i]["linf"] == meta[i]["linf"] <= taus[f][i]
+        k = len(comps)
+        want = driver.reconstruct(comps, k, x.shape, x.dtype)
+        assert np.array_equal(ctx.retrieve(st, k).cpu().numpy(), want), f
+
+
+def test_graph_replays_with_eager_work_between(setup):
+    ctx, xs, taus, oracle, dev, batch = setup
+    first = streams_of(batch.compress(dev))
+    for rep in range(3):
+        # eager work on the same stream between replays
+        single = ctx.compress(dev[0], taus[0])
+        assert np.array_equal(single.stream(0).cpu().numpy(), oracle[0][0][0])
+        again = streams_of(batch.compress(dev))
+        for f in range(len(xs)):
+            for i in range(len(first[f])):
+                assert np.array_equal(again[f][i], first[f][i]), (rep, f, i)
+
+
+def test_every_schedule_gives_the_same_bytes(setup):
+    ctx, xs, taus, oracle, dev, batch = setup
+    ref = [[c for c in comps] for comps, _ in oracle]
+    for gm in (1, 2, 4, 8):
+        for order in (0, 1, 2):
+            batch.schedule(gm, order)
+            got = streams_of(batch.compress(dev))
+            for f in range(len(xs)):
+                for i in range(len(ref[f])):
+                    assert np.array_equal(got[f][i], ref[f][i]), (gm, order, f, i)
+    gm, order, ms = batch.tune(dev)
+    say("tuned schedule: grid x%d order %d, %.3f ms" % (gm, order, ms))
+    got = streams_of(batch.compress(dev))
+    for f in range(len(xs)):
+        for i in range(len(ref[f])):
+            assert np.array_equal(got[f][i], ref[f][i])
+
+
+def test_batch_inputs_can_change(setup):
+    """The graph stays valid when the inputs move: the field table is refreshed."""
+    import torch
+    ctx, xs, taus, oracle, dev, batch = setup
+    moved = [d.clone() for d in dev]
+    got = streams_of(batch.compress(moved))
+    for f in range(len(xs)):
+        for i in range(len(oracle[f][0])):
+            assert np.array_equal(got[f][i], oracle[f][0][i])
+    del moved
+    torch.cuda.synchronize()
