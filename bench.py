@@ -36,6 +36,8 @@ WORKLOADS = {
     "bulk_256_f64": ((256, 256, 256), np.float64, 2, 8, lambda i, r: 2.0 ** (-3 * i), 0.0),
     "small_64_f64": (None, np.float64, 0, 4, lambda i, r: r * 10.0 ** -i, 0.0),
     "largest_1024_f32": ((1024, 1024, 1024), np.float32, 3, 12, lambda i, r: 2.0 ** (-2 * i), 1e-4),
+    "batched_256": None,
+    "served_64": None,
 }
 
 
@@ -88,6 +90,161 @@ def cpu_baseline(x, taus, planes):
                       "k=1..%d, %.1f s" % (xs.shape[0], xs.shape[1], xs.shape[2], xs.size, n, n, dt)}
 
 
+def bench_batched(args):
+    """256 fields, edges log-uniform in [16, 256] per axis, f32/f64 alternating,
+    6 components, tau_i = range_f * 4^-i: one tuned graph per call vs a loop
+    of single-field compressions."""
+    import torch
+    from paper_2308_11759_amd import inputs, pmc
+    dev = torch.device("cuda", 0)
+    shapes = inputs.batched_shapes(args.fields)
+    log("generating %d fields on the device" % len(shapes))
+    xs, taus = [], []
+    for f, (shape, is32) in enumerate(shapes):
+        x = inputs.spectral_field_torch(shape, seed=100 + f, dtype=torch.float32 if is32 else torch.float64,
+                                        device=dev)
+        r = float(x.max() - x.min())
+        xs.append(x)
+        taus.append([r * 4.0 ** -i for i in range(1, 7)])
+    total = sum(x.numel() * x.element_size() for x in xs)
+    nval = sum(x.numel() for x in xs)
+    ctx = pmc.Context(0)
+    batch = ctx.batch([(tuple(x.shape), x.dtype) for x in xs], taus)
+    streams = torch.empty_like(batch.streams)
+    log("tuning (%d schedules)" % 12)
+    gm, order, tms = batch.tune(xs)
+    log("tuned: grid x%d, order %d, graph %.3f ms" % (gm, order, tms))
+    for _ in range(args.warmup):
+        batch.compress(xs, streams=streams)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        stores = batch.compress(xs, streams=streams)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / args.steps
+    # baseline: one pmc_compress per field
+    outs = [torch.empty(ctx.compress_sizes(x, 6)[1] * 6, dtype=torch.uint8, device=dev) for x in xs]
+    for x, t, o in zip(xs, taus, outs):
+        ctx.compress(x, t, streams=o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        singles = [ctx.compress(x, t, streams=o) for x, t, o in zip(xs, taus, outs)]
+    torch.cuda.synchronize()
+    t_loop = (time.perf_counter() - t0) / args.steps
+    same = all(bool(torch.equal(a.stream(i), b.stream(i))) for a, b in zip(stores, singles) for i in range(6))
+    sbytes = sum(m["bytes"] for st in stores for m in st.info)
+    rec = {"metric": "batched compress GB/s (256 mixed fields, 6 comps)", "value": total / t_batch / 1e9,
+           "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": t_batch * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32+f64", "data": "synthetic",
+           "config": {"workload": "batched_256", "fields": len(xs), "values": nval, "components": 6,
+                      "schedule": {"grid_mult": gm, "order": order}},
+           "per_field_loop_gbs": total / t_loop / 1e9, "speedup_vs_loop": t_loop / t_batch,
+           "identical_to_single_field": same, "rate_bits_per_value": 8.0 * sbytes / nval}
+    print(json.dumps(rec))
+
+
+def bench_served(args):
+    """64 stored fields (edge log-uniform 64..384, f32/f64 alternating, 10
+    components, tau_i = range * 10^(-i/2)); open-loop Poisson queries (field
+    uniform, tolerance log-uniform in [1e-5, 1e-1] * range).  Served form:
+    the library's request loop (continuous batching, device partial-sum cache,
+    64 GB budget).  Plain form: the same trace, first come first served, one
+    Alg. 2 retrieval from scratch per query."""
+    import threading
+    import torch
+    from paper_2308_11759_amd import inputs, pmc
+    dev = torch.device("cuda", 0)
+    ctx = pmc.Context(0)
+    shapes = inputs.served_shapes(64)
+    stores, ranges, nbytes = [], [], []
+    log("building the store: %d fields" % len(shapes))
+    for f, (shape, is32) in enumerate(shapes):
+        x = inputs.spectral_field_torch(shape, seed=200 + f, dtype=torch.float32 if is32 else torch.float64,
+                                        device=dev)
+        r = float(x.max() - x.min())
+        taus = [r * 10.0 ** (-i / 2.0) for i in range(1, 11)]
+        stores.append(ctx.compress(x, taus))
+        ranges.append(r)
+        nbytes.append(x.numel() * x.element_size())
+        del x
+    torch.cuda.synchronize()
+    results = {}
+    rates = [int(v) for v in args.rates.split(",")]
+    for lam in rates:
+        trace = inputs.query_trace(len(stores), lam, args.queries, seed=7 + lam)
+        trace = [(t, f, rel * ranges[f]) for t, f, rel in trace]
+        # served
+        srv = pmc.Server(ctx, arena_bytes=args.arena_gb << 30, budget_bytes=args.arena_gb << 30, max_batch=64)
+        for st in stores:
+            srv.add(st)
+        tickets = [None] * len(trace)
+        lat = [None] * len(trace)
+        t0 = time.perf_counter()
+
+        def submitter():
+            for i, (ta, f, tol) in enumerate(trace):
+                d = t0 + ta - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                tickets[i] = srv.submit(f, tol)
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        done = 0
+        while done < len(trace):
+            progressed = False
+            for i in range(len(trace)):
+                if lat[i] is None and tickets[i] is not None:
+                    d, st, l = srv.poll(tickets[i])
+                    if d:
+                        assert st == pmc.OK, st
+                        lat[i] = l
+                        srv.release(tickets[i])
+                        done += 1
+                        progressed = True
+            if not progressed:
+                time.sleep(0.0002)
+        th.join()
+        makespan = time.perf_counter() - t0
+        sstats = srv.stats()
+        srv.close()
+        out_bytes = sum(nbytes[f] for _, f, _ in trace)
+        served = {"p50_ms": 1e3 * float(np.percentile(lat, 50)), "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+                  "gbs": out_bytes / makespan / 1e9, "makespan_s": makespan,
+                  "hits": sstats["hits"], "partial": sstats["partial"], "misses": sstats["misses"],
+                  "steps": sstats["steps"], "max_queue": sstats["max_queue"]}
+        # plain: FIFO, one retrieval from scratch per query
+        outs = [torch.empty(st.shape, dtype=st.dtype, device=dev) for st in stores]
+        plat = []
+        t0 = time.perf_counter()
+        for ta, f, tol in trace:
+            d = t0 + ta - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            k = stores[f].select_k(tol)
+            ctx.retrieve(stores[f], k, out=outs[f])
+            torch.cuda.synchronize()
+            plat.append(time.perf_counter() - (t0 + ta))
+        pmake = time.perf_counter() - t0
+        plain = {"p50_ms": 1e3 * float(np.percentile(plat, 50)), "p99_ms": 1e3 * float(np.percentile(plat, 99)),
+                 "gbs": out_bytes / pmake / 1e9, "makespan_s": pmake}
+        del outs
+        results[str(lam)] = {"served": served, "plain": plain}
+        log("lambda %d: served p50 %.2f ms p99 %.2f ms | plain p50 %.2f ms p99 %.2f ms" %
+            (lam, served["p50_ms"], served["p99_ms"], plain["p50_ms"], plain["p99_ms"]))
+    top = results[str(rates[-1])]
+    rec = {"metric": "query p99 latency, served vs plain (64 fields, 10 comps)",
+           "value": top["served"]["p99_ms"], "unit": "ms", "n_gpus": 1, "steps": args.queries, "warmup": 0,
+           "ms_per_step": None, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32+f64", "data": "synthetic",
+           "config": {"workload": "served_64", "queries_per_rate": args.queries, "rates_qps": rates,
+                      "budget_gb": args.arena_gb},
+           "plain_p99_ms": top["plain"]["p99_ms"], "per_rate": results}
+    print(json.dumps(rec))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,11 +253,20 @@ def main():
     ap.add_argument("--workload", default="bulk_512_f32", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-planes", type=int, default=8, help="z-planes of the oracle sample (0 = skip)")
     ap.add_argument("--literal", action="store_true", help="one decode pass per component (literal Alg. 2)")
+    ap.add_argument("--fields", type=int, default=256, help="batched workload: number of fields")
+    ap.add_argument("--queries", type=int, default=2000, help="served workload: queries per arrival rate")
+    ap.add_argument("--rates", default="200,500,1000,2000", help="served workload: arrival rates (QPS)")
+    ap.add_argument("--arena-gb", type=int, default=64, help="served workload: cache arena and budget")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (the field would be split "
               "into z-slabs, one per GPU; see DESIGN.md).", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batched_256":
+        return bench_batched(args)
+    if args.workload == "served_64":
+        return bench_served(args)
 
     import torch
     from paper_2308_11759_amd import pmc

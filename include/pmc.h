@@ -176,6 +176,42 @@ pmc_status pmc_batch_tune(pmc_batch* b, const void* const* d_x, void* d_ws, size
 const char* pmc_batch_order_name(int order);
 void pmc_batch_free(pmc_batch* b);
 
+/* ---- serving progressive-retrieval queries ---------------------------
+ * A request loop on a host thread serves queries "field f at tolerance tau"
+ * with k = the smallest component count whose prescribed tolerance is <= tau
+ * (Sec. 6.2).  Decoded partial sums x~_k stay resident on the device in a
+ * (field, k) cache inside the caller's arena, so a query is served by copying
+ * a cached x~_k, by refining the cached x~_j with the largest j < k
+ * (components j+1..k, Sec. 4.2), or by decoding from scratch.  Continuous
+ * batching: every step admits waiting queries in arrival order while batch
+ * slots (max_batch) and the HBM budget allow and decodes all of them in one
+ * launch per element type; steps are enqueued while earlier steps run.  The
+ * budget bounds the arena bytes in use (cache entries and result slots) plus
+ * the caller outputs of running queries; least-recently-used cache entries
+ * that no running step touches are evicted to admit a query.  Results are
+ * bit-identical alone or in a mix.  The stores added must outlive the server.
+ * A query with d_out == NULL gets a result slot in the arena, readable via
+ * pmc_server_result until pmc_server_release.  Internally synchronised. */
+typedef struct pmc_server pmc_server;
+typedef struct {
+  uint64_t submitted, completed, hits, partial, misses, steps, batched_queries, max_queue;
+  uint64_t cache_entries, cache_bytes, arena_peak, pending, running;
+} pmc_server_stats;
+pmc_status pmc_server_create(pmc_ctx* ctx, size_t hbm_budget, void* d_arena, size_t arena_bytes, int max_batch,
+                             pmc_server** out);
+pmc_status pmc_server_add(pmc_server* s, const pmc_store* store, int* field_id);
+/* PMC_E_UNREACHABLE when tol is below the field's last tolerance */
+pmc_status pmc_server_submit(pmc_server* s, int field_id, double tol, void* d_out, uint64_t* ticket);
+/* latency_s = completion - submission in seconds (-1 while running) */
+pmc_status pmc_server_poll(pmc_server* s, uint64_t ticket, int* done, pmc_status* st, double* latency_s);
+/* device address of a finished query's x~_k; source: 0 decoded from scratch,
+ * 1 refined from a cached partial sum, 2 copied from the cache */
+pmc_status pmc_server_result(pmc_server* s, uint64_t ticket, const void** d_result, int* k, int* source);
+pmc_status pmc_server_release(pmc_server* s, uint64_t ticket);
+pmc_status pmc_server_get_stats(pmc_server* s, pmc_server_stats* out);
+/* finishes every submitted query, then stops the request loop */
+void pmc_server_destroy(pmc_server* s);
+
 #ifdef __cplusplus
 }
 #endif

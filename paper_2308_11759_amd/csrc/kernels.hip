@@ -589,39 +589,70 @@ __device__ __forceinline__ bool decode_block_add(GBits& r, int minexp, T acc[64]
   return true;
 }
 
+// decode block `blk` of a field: x~ = in (or +0) plus components [0, ncomp)
+// of the given streams, left to right; false on a malformed stream
 template <class T>
-__global__ __launch_bounds__(64) void k_decode(DecArgs<T> a) {
-  __shared__ uint32_t s_planes[32 * 64];
-  uint32_t* pw = s_planes + threadIdx.x;
-  const uint64_t blk = (uint64_t)blockIdx.x * 64 + threadIdx.x;
-  if (blk >= a.g.nblocks) return;
-  const BlockPos bp = block_pos(a.g, blk);
+__device__ __forceinline__ bool decode_block_sum(const Geo& g, const uint8_t* const* s, const uint32_t* const* aux,
+                                                 const uint64_t* words, const int* minexp, int ncomp, const T* in,
+                                                 T* out, uint64_t blk, uint32_t* pw) {
+  const BlockPos bp = block_pos(g, blk);
   const uint64_t chunk = blk / kChunkBlocks;
   T acc[64];
-  if (a.in) {
-    load_block(a.in, a.g, bp, acc);
+  if (in) {
+    load_block(in, g, bp, acc);
   } else {
 #pragma unroll
     for (int l = 0; l < 64; ++l) acc[l] = (T)0;
   }
   bool ok = true;
-  for (int i = 0; i < a.ncomp && ok; ++i) {
-    const uint32_t* index = reinterpret_cast<const uint32_t*>(a.s[i] + kHeaderBytes);
-    const uint32_t* payload = index + a.g.nchunks;
+  for (int i = 0; i < ncomp && ok; ++i) {
+    const uint32_t* index = reinterpret_cast<const uint32_t*>(s[i] + kHeaderBytes);
+    const uint32_t* payload = index + g.nchunks;
     const uint64_t start = index[chunk];
-    const uint64_t stop = chunk + 1 < a.g.nchunks ? (uint64_t)index[chunk + 1] : a.words[i];
-    const uint64_t off = a.aux[i][blk];
-    if (start > stop || stop > a.words[i] || off >= (stop - start) * 32) {
+    const uint64_t stop = chunk + 1 < g.nchunks ? (uint64_t)index[chunk + 1] : words[i];
+    const uint64_t off = aux[i][blk];
+    if (start > stop || stop > words[i] || off >= (stop - start) * 32) {
       ok = false;
       break;
     }
     GBits r;
     r.init(payload + start + (off >> 5), payload + stop);
     r.skip((uint32_t)(off & 31));
-    ok = decode_block_add<T>(r, a.minexp[i], acc, pw) && !r.bad();
+    ok = decode_block_add<T>(r, minexp[i], acc, pw) && !r.bad();
   }
-  if (ok) store_block(a.out, a.g, bp, acc);
-  else atomicOr(a.status, 1u);
+  if (ok) store_block(out, g, bp, acc);
+  return ok;
+}
+
+template <class T>
+__global__ __launch_bounds__(64) void k_decode(DecArgs<T> a) {
+  __shared__ uint32_t s_planes[32 * 64];
+  uint32_t* pw = s_planes + threadIdx.x;
+  const uint64_t blk = (uint64_t)blockIdx.x * 64 + threadIdx.x;
+  if (blk >= a.g.nblocks) return;
+  if (!decode_block_sum<T>(a.g, a.s, a.aux, a.words, a.minexp, a.ncomp, a.in, a.out, blk, pw))
+    atomicOr(a.status, 1u);
+}
+
+// many retrieval queries in one launch: wave w belongs to the query q with
+// wave_prefix[q] <= w < wave_prefix[q + 1]
+template <class T>
+__global__ __launch_bounds__(64) void k_decode_queries(ServeArgs a) {
+  __shared__ uint32_t s_planes[32 * 64];
+  uint32_t* pw = s_planes + threadIdx.x;
+  const uint32_t w = blockIdx.x;
+  uint32_t lo = 0, hi = a.nq;  // largest q with wave_prefix[q] <= w
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (a.wave_prefix[mid] <= w) lo = mid;
+    else hi = mid;
+  }
+  const QueryDev& q = a.q[lo];
+  const uint64_t blk = (uint64_t)(w - a.wave_prefix[lo]) * 64 + threadIdx.x;
+  if (blk >= q.g.nblocks) return;
+  if (!decode_block_sum<T>(q.g, q.s, q.aux, q.words, q.minexp, q.ncomp, reinterpret_cast<const T*>(q.in),
+                           reinterpret_cast<T*>(q.out), blk, pw))
+    atomicOr(a.status, 1u);
 }
 
 // per-block bit offsets of a stream written elsewhere: parse each chunk
@@ -848,6 +879,11 @@ template <class T> hipError_t launch_decode(const DecArgs<T>& a, hipStream_t s) 
   hipLaunchKernelGGL(k_decode<T>, dim3((uint32_t)wgs), dim3(64), 0, s, a);
   return hipGetLastError();
 }
+template <class T> hipError_t launch_decode_queries(const ServeArgs& a, hipStream_t s) {
+  if (a.nwaves == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_decode_queries<T>, dim3(a.nwaves), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
 template <class T> hipError_t launch_aux(const AuxArgs& a, hipStream_t s) {
   const uint64_t wgs = (a.g.nchunks + 63) / 64;
   hipLaunchKernelGGL(k_aux<T>, dim3((uint32_t)wgs), dim3(64), 0, s, a);
@@ -893,6 +929,8 @@ template hipError_t launch_pack<float>(const PackArgs&, hipStream_t);
 template hipError_t launch_pack<double>(const PackArgs&, hipStream_t);
 template hipError_t launch_decode<float>(const DecArgs<float>&, hipStream_t);
 template hipError_t launch_decode<double>(const DecArgs<double>&, hipStream_t);
+template hipError_t launch_decode_queries<float>(const ServeArgs&, hipStream_t);
+template hipError_t launch_decode_queries<double>(const ServeArgs&, hipStream_t);
 template hipError_t launch_aux<float>(const AuxArgs&, hipStream_t);
 template hipError_t launch_aux<double>(const AuxArgs&, hipStream_t);
 template hipError_t launch_range<float>(const float*, uint64_t, unsigned long long*, hipStream_t);

@@ -94,6 +94,28 @@ template <class T> struct DecArgs {
   unsigned int* status;  // bit 0: malformed stream
 };
 
+// one retrieval query of a server step: out = in (or +0) + components
+// [0, ncomp) of the listed streams
+struct QueryDev {
+  const uint8_t* s[kMaxComps];
+  const uint32_t* aux[kMaxComps];
+  uint64_t words[kMaxComps];
+  int minexp[kMaxComps];
+  int ncomp;
+  int dtype;
+  const void* in;
+  void* out;
+  Geo g;
+};
+
+struct ServeArgs {
+  const QueryDev* q;
+  const uint32_t* wave_prefix;  // nq + 1 entries
+  uint32_t nq;
+  uint32_t nwaves;
+  unsigned int* status;
+};
+
 // rebuild the per-block bit offsets of one stream (one lane per chunk)
 struct AuxArgs {
   const uint8_t* s;
@@ -146,6 +168,7 @@ hipError_t launch_batch_init(const FieldDev* fields, uint32_t nfields, hipStream
 template <class T> hipError_t launch_encode(const EncArgs<T>& a, hipStream_t s);
 hipError_t launch_scan(const ScanArgs& a, hipStream_t s);
 template <class T> hipError_t launch_aux(const AuxArgs& a, hipStream_t s);
+template <class T> hipError_t launch_decode_queries(const ServeArgs& a, hipStream_t s);
 template <class T> hipError_t launch_pack(const PackArgs& a, hipStream_t s);
 template <class T> hipError_t launch_decode(const DecArgs<T>& a, hipStream_t s);
 template <class T> hipError_t launch_range(const T* x, uint64_t n, unsigned long long* out, hipStream_t s);

@@ -39,6 +39,12 @@ class ProfEntry(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_uint64), ("ms", ctypes.c_double)]
 
 
+class ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in ("submitted", "completed", "hits", "partial", "misses", "steps",
+                                                "batched_queries", "max_queue", "cache_entries", "cache_bytes",
+                                                "arena_peak", "pending", "running")]
+
+
 _lib = None
 
 # every exported symbol of include/pmc.h with (restype, argtypes)
@@ -73,6 +79,14 @@ SIGNATURES = {
     "pmc_batch_tune": (_int, [_vp, _P(_vp), _vp, _sz, _vp, _sz, _P(ctypes.c_float)]),
     "pmc_batch_order_name": (ctypes.c_char_p, [_int]),
     "pmc_batch_free": (None, [_vp]),
+    "pmc_server_create": (_int, [_vp, _sz, _vp, _sz, _int, _P(_vp)]),
+    "pmc_server_add": (_int, [_vp, _vp, _P(_int)]),
+    "pmc_server_submit": (_int, [_vp, _int, _dbl, _vp, _P(_u64)]),
+    "pmc_server_poll": (_int, [_vp, _u64, _P(_int), _P(_int), _P(_dbl)]),
+    "pmc_server_result": (_int, [_vp, _u64, _P(_vp), _P(_int), _P(_int)]),
+    "pmc_server_release": (_int, [_vp, _u64]),
+    "pmc_server_get_stats": (_int, [_vp, _P(ServerStats)]),
+    "pmc_server_destroy": (None, [_vp]),
 }
 
 
@@ -322,6 +336,81 @@ class Batch:
             self.free()
         except Exception:
             pass
+
+
+class Server:
+    """Progressive-retrieval server with a device-resident partial-sum cache
+    and continuous batching (request loop on a library thread)."""
+
+    def __init__(self, ctx, arena_bytes, budget_bytes=None, max_batch=64):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=ctx.device)
+        budget = int(budget_bytes if budget_bytes is not None else arena_bytes)
+        h = ctypes.c_void_p()
+        ctx._check(self.lib.pmc_server_create(ctx.handle, budget, ctypes.c_void_p(self.arena.data_ptr()),
+                                              self.arena.numel(), int(max_batch), ctypes.byref(h)))
+        self.handle = h
+        self.stores = []
+
+    def add(self, store):
+        fid = ctypes.c_int()
+        self.ctx._check(self.lib.pmc_server_add(self.handle, store.handle, ctypes.byref(fid)))
+        self.stores.append(store)
+        return fid.value
+
+    def submit(self, field, tol, out=None):
+        t = ctypes.c_uint64()
+        ptr = ctypes.c_void_p(out.data_ptr()) if out is not None else None
+        self.ctx._check(self.lib.pmc_server_submit(self.handle, int(field), float(tol), ptr, ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket):
+        """(done, status, latency_s)"""
+        d, st, lat = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        self.ctx._check(self.lib.pmc_server_poll(self.handle, int(ticket), ctypes.byref(d), ctypes.byref(st),
+                                                 ctypes.byref(lat)))
+        return bool(d.value), st.value, lat.value
+
+    def result(self, ticket, field):
+        """(x~_k as a device tensor view, k, source); valid until release()."""
+        p, k, src = ctypes.c_void_p(), ctypes.c_int(), ctypes.c_int()
+        self.ctx._check(self.lib.pmc_server_result(self.handle, int(ticket), ctypes.byref(p), ctypes.byref(k),
+                                                   ctypes.byref(src)))
+        st = self.stores[field]
+        nbytes = int(np_prod(st.shape)) * (4 if st.dtype == torch.float32 else 8)
+        off = p.value - self.arena.data_ptr()
+        if 0 <= off < self.arena.numel():
+            view = self.arena[off:off + nbytes].view(st.dtype).view(st.shape)
+        else:
+            view = None  # caller-owned output
+        return view, k.value, src.value
+
+    def release(self, ticket):
+        self.ctx._check(self.lib.pmc_server_release(self.handle, int(ticket)))
+
+    def stats(self):
+        s = ServerStats()
+        self.lib.pmc_server_get_stats(self.handle, ctypes.byref(s))
+        return {n: getattr(s, n) for n, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.pmc_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def np_prod(shape):
+    p = 1
+    for v in shape:
+        p *= int(v)
+    return p
 
 
 class Store:

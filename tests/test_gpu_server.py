@@ -1,0 +1,132 @@
+"""Serving: continuous batching with a device-resident partial-sum cache.
+Every result must equal the isolated retrieval (and the oracle) bit for bit,
+whatever mix of queries it was served in."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from oracle import driver
+from paper_2308_11759_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def served():
+    import torch
+    from paper_2308_11759_amd import pmc
+    ctx = pmc.Context(0)
+    ctx.set_option(pmc.OPT_SYNC_CHECK, 1)
+    xs = [inputs.spectral_field((n, n + 3, n + 1), seed=400 + i, dtype=np.float32 if i % 2 == 0 else np.float64)
+          for i, n in enumerate((12, 30, 21, 40, 17, 26))]
+    stores, taus, refs = [], [], []
+    for x in xs:
+        r = float(x.max() - x.min())
+        t = [r * 10.0 ** (-(i + 1) / 2.0) for i in range(6)]
+        st = ctx.compress(torch.from_numpy(x).to("cuda:0"), t)
+        stores.append(st)
+        taus.append(t)
+        refs.append([ctx.retrieve(st, k).cpu().numpy() for k in range(1, 7)])
+    # the isolated retrievals themselves are the oracle's Alg. 2
+    comps, _ = driver.compress(xs[1], taus[1])
+    for k in range(1, 7):
+        assert np.array_equal(refs[1][k - 1], driver.reconstruct(comps, k, xs[1].shape, xs[1].dtype))
+    yield ctx, xs, stores, taus, refs
+    torch.cuda.synchronize()
+
+
+def wait_all(srv, tickets, timeout=60.0):
+    t0 = time.time()
+    for t in tickets:
+        while True:
+            done, st, lat = srv.poll(t)
+            if done:
+                break
+            assert time.time() - t0 < timeout, "query %d not done" % t
+            time.sleep(0.0005)
+
+
+def test_mixed_queries_match_isolated_retrieval(served):
+    from paper_2308_11759_amd import pmc
+    ctx, xs, stores, taus, refs = served
+    srv = pmc.Server(ctx, arena_bytes=256 << 20, max_batch=8)
+    fids = [srv.add(s) for s in stores]
+    rng = np.random.default_rng(1)
+    tickets = []
+    for q in range(120):
+        f = int(rng.integers(0, len(fids)))
+        k = int(rng.integers(1, 7))
+        tol = taus[f][k - 1] * (1.0 + 0.5 * rng.random())  # selects exactly k
+        tickets.append((srv.submit(fids[f], tol), f, k))
+        if q % 17 == 0:
+            time.sleep(0.002)  # arrivals while steps run
+    wait_all(srv, [t for t, _, _ in tickets])
+    for t, f, k in tickets:
+        done, st, lat = srv.poll(t)
+        assert done and st == pmc.OK and lat >= 0.0
+        view, kk, src = srv.result(t, f)
+        assert kk == k
+        assert np.array_equal(view.cpu().numpy(), refs[f][k - 1]), (t, f, k, src)
+        srv.release(t)
+    s = srv.stats()
+    say("server stats: %s" % s)
+    assert s["completed"] == len(tickets)
+    assert s["hits"] + s["partial"] + s["misses"] == len(tickets)
+    assert s["hits"] > 0 and s["steps"] < len(tickets)
+    srv.close()
+
+
+def test_tight_budget_still_serves_everything(served):
+    from paper_2308_11759_amd import pmc
+    ctx, xs, stores, taus, refs = served
+    biggest = max(x.nbytes for x in xs)
+    srv = pmc.Server(ctx, arena_bytes=64 << 20, budget_bytes=2 * biggest + 4096, max_batch=4)
+    fids = [srv.add(s) for s in stores]
+    tickets = []
+    for q in range(40):
+        f = q % len(fids)
+        k = 1 + (q * 7) % 6
+        tickets.append((srv.submit(fids[f], taus[f][k - 1]), f, k))
+    # release results as they complete so that memory frees up
+    t0 = time.time()
+    left = list(tickets)
+    while left:
+        nxt = []
+        for t, f, k in left:
+            done, st, _ = srv.poll(t)
+            if done:
+                assert st == pmc.OK
+                view, kk, _ = srv.result(t, f)
+                assert np.array_equal(view.cpu().numpy(), refs[f][k - 1])
+                srv.release(t)
+            else:
+                nxt.append((t, f, k))
+        left = nxt
+        assert time.time() - t0 < 60.0
+        time.sleep(0.0005)
+    assert srv.stats()["arena_peak"] <= 2 * biggest + 4096 + 4 * 256
+    srv.close()
+
+
+def test_caller_outputs_and_unreachable(served):
+    import torch
+    from paper_2308_11759_amd import pmc
+    ctx, xs, stores, taus, refs = served
+    srv = pmc.Server(ctx, arena_bytes=128 << 20, max_batch=16)
+    fids = [srv.add(s) for s in stores]
+    outs = [torch.empty(s.shape, dtype=s.dtype, device="cuda:0") for s in stores]
+    tickets = [srv.submit(fids[f], taus[f][3], out=outs[f]) for f in range(len(fids))]
+    wait_all(srv, tickets)
+    for f in range(len(fids)):
+        assert np.array_equal(outs[f].cpu().numpy(), refs[f][3])
+    with pytest.raises(pmc.PmcError) as ei:
+        srv.submit(fids[0], taus[0][-1] * 0.5)
+    assert ei.value.status == pmc.E_UNREACHABLE
+    srv.close()
