@@ -98,14 +98,15 @@ def bench_batched(args):
     from paper_2308_11759_amd import inputs, pmc
     dev = torch.device("cuda", 0)
     shapes = inputs.batched_shapes(args.fields)
-    log("generating %d fields on the device" % len(shapes))
+    log("generating %d fields" % len(shapes))
     xs, taus = [], []
     for f, (shape, is32) in enumerate(shapes):
-        x = inputs.spectral_field_torch(shape, seed=100 + f, dtype=torch.float32 if is32 else torch.float64,
-                                        device=dev)
-        r = float(x.max() - x.min())
-        xs.append(x)
+        xh = inputs.spectral_field(shape, seed=100 + f, dtype=np.float32 if is32 else np.float64)
+        r = float(xh.max()) - float(xh.min())
+        xs.append(torch.from_numpy(xh).to(dev))
         taus.append([r * 4.0 ** -i for i in range(1, 7)])
+        if f % 32 == 31:
+            log("  %d fields" % (f + 1))
     total = sum(x.numel() * x.element_size() for x in xs)
     nval = sum(x.numel() for x in xs)
     ctx = pmc.Context(0)
@@ -161,14 +162,16 @@ def bench_served(args):
     stores, ranges, nbytes = [], [], []
     log("building the store: %d fields" % len(shapes))
     for f, (shape, is32) in enumerate(shapes):
-        x = inputs.spectral_field_torch(shape, seed=200 + f, dtype=torch.float32 if is32 else torch.float64,
-                                        device=dev)
-        r = float(x.max() - x.min())
+        xh = inputs.spectral_field(shape, seed=200 + f, dtype=np.float32 if is32 else np.float64)
+        r = float(xh.max()) - float(xh.min())
+        x = torch.from_numpy(xh).to(dev)
         taus = [r * 10.0 ** (-i / 2.0) for i in range(1, 11)]
         stores.append(ctx.compress(x, taus))
         ranges.append(r)
         nbytes.append(x.numel() * x.element_size())
-        del x
+        del x, xh
+        if f % 8 == 7:
+            log("  %d fields stored" % (f + 1))
     torch.cuda.synchronize()
     results = {}
     rates = [int(v) for v in args.rates.split(",")]

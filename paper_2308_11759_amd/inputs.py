@@ -77,32 +77,6 @@ def spectral_field(shape, seed=1, dtype=np.float32, noise_rel=0.0):
     return f.astype(dtype)
 
 
-def spectral_field_torch(shape, seed=1, dtype=None, noise_rel=0.0, device="cuda"):
-    """The spectral recipe of spectral_field drawn with torch: phases from a
-    seeded CPU generator, inverse FFT in float64 on `device`.  Deterministic
-    for a given seed and device, but not bit-identical to spectral_field."""
-    import torch
-    dtype = dtype or torch.float32
-    shape = tuple(int(s) for s in shape)
-    nz, ny, nx = shape
-    gen = torch.Generator(device="cpu").manual_seed(int(seed))
-    kz = torch.fft.fftfreq(nz, device=device, dtype=torch.float64) * nz
-    ky = torch.fft.fftfreq(ny, device=device, dtype=torch.float64) * ny
-    kx = torch.fft.rfftfreq(nx, device=device, dtype=torch.float64) * nx
-    k2 = kz[:, None, None] ** 2 + ky[None, :, None] ** 2 + kx[None, None, :] ** 2
-    amp = torch.where(k2 > 0, k2.clamp_min(1e-300) ** (-11.0 / 12.0), torch.zeros_like(k2))
-    phase = torch.rand(tuple(amp.shape), generator=gen, dtype=torch.float64).to(device) * (2.0 * math.pi)
-    spec = torch.polar(amp, phase)
-    f = torch.fft.irfftn(spec, s=shape)
-    del spec, amp, phase, k2
-    lo, hi = f.min(), f.max()
-    f = ((f - lo) * (2.0 / (hi - lo)) - 1.0).clamp_(-1.0, 1.0)
-    if noise_rel > 0.0:
-        noise = torch.randn(shape, generator=gen, dtype=torch.float64).to(device)
-        f += noise * (noise_rel * 2.0)
-    return f.to(dtype).contiguous()
-
-
 def batched_shapes(count=256, base_seed=100, lo=16, hi=256):
     """(shape, is_float32) of the batched workload's fields."""
     out = []
