@@ -260,6 +260,8 @@ def main():
     ap.add_argument("--queries", type=int, default=2000, help="served workload: queries per arrival rate")
     ap.add_argument("--rates", default="200,500,1000,2000", help="served workload: arrival rates (QPS)")
     ap.add_argument("--arena-gb", type=int, default=64, help="served workload: cache arena and budget")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run three 512 MiB device-to-device copies (scale for rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (the field would be split "
@@ -359,6 +361,14 @@ def main():
                   ("k_encode_" + tname, "k_scan", "k_pack_" + tname))
     dec_ms = kern.get("k_decode_" + tname, {}).get("ms_per_step", 0.0)
     value = N * s * (1 + n) / (ms_step / 1e3) / 1e9
+
+    if args.copy_calibration:
+        src = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     cpu = None
     if args.cpu_planes > 0:
