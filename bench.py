@@ -300,10 +300,13 @@ def main():
             ctx.retrieve(st, k, out=out)
         return st
 
+    store = None
     for w in range(args.warmup):
         store = step()
         torch.cuda.synchronize()
         log("warmup %d done" % w)
+    if store is None:
+        store = ctx.compress(xd, taus, streams=streams)
     # parity probe at full size: Eq. (1) for every k, on the device
     for k in range(1, n + 1):
         ctx.retrieve(store, k, out=out)
