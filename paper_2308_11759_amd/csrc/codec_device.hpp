@@ -264,29 +264,36 @@ __device__ __forceinline__ void plane_emit(LdsBits& w, uint64_t wd, uint32_t& n)
 }
 
 // ---------------------------------------------------------------------------
-// global-memory bit reader over one chunk [p, end) (never reads past end)
+// global-memory bit reader over the words [first, end) of a payload.  Word
+// indices are 32-bit (the stream index limits a payload to 2^32 words) and the
+// payload base is usually wave-uniform, which keeps the reader in few vector
+// registers.  The word after the buffered ones is loaded one refill ahead
+// (from the last word of the range once the range is exhausted, so every load
+// stays inside it and its latency overlaps the decoding of the bits already
+// buffered).  Bits past `end` are therefore unspecified; bad() reports any
+// use of them.  A reader is refilled only when first < end.
 struct GBits {
-  const uint32_t* p;
-  const uint32_t* end;
+  const uint32_t* base;
+  uint32_t p;  // index of the next word to load
+  uint32_t end;
   uint64_t buf;
   uint32_t nbuf;
-  uint32_t overrun;  // words requested past the end
-  __device__ __forceinline__ void init(const uint32_t* begin, const uint32_t* e) {
-    p = begin;
+  uint32_t nxt;  // word p - 1, loaded ahead
+  __device__ __forceinline__ void init(const uint32_t* b, uint32_t first, uint32_t e) {
+    base = b;
     end = e;
     buf = 0;
     nbuf = 0;
-    overrun = 0;
+    nxt = first < e ? b[first] : 0u;
+    p = first + 1;
   }
   // afterwards at least 32 bits are buffered
   __device__ __forceinline__ void refill() {
     if (nbuf <= 32) {
-      uint32_t v = 0;
-      if (p < end) v = *p;
-      else overrun = 1;
-      ++p;
-      buf |= (uint64_t)v << nbuf;
+      buf |= (uint64_t)nxt << nbuf;
       nbuf += 32;
+      nxt = base[p < end ? p : end - 1];
+      ++p;
     }
   }
   __device__ __forceinline__ void drop(uint32_t count) {  // count <= buffered bits
@@ -311,20 +318,29 @@ struct GBits {
     refill();
     drop(count);
   }
-  // bits consumed past the end of the chunk (fetched-but-unused zero words
-  // beyond `end` are fine)
+  // bits consumed since word `from`: words moved into the buffer minus those held
+  __device__ __forceinline__ uint64_t consumed(uint32_t from) const {
+    return (uint64_t)(p - 1 - from) * 32 - nbuf;
+  }
+  // bits consumed past `end` (zero words fetched beyond it and not used are fine)
   __device__ __forceinline__ bool bad() const {
-    if (!overrun) return false;
-    int64_t past_bits = (int64_t)(p - end) * 32 - (int64_t)nbuf;
-    return past_bits > 0;
+    return (int64_t)((int64_t)p - 1 - (int64_t)end) * 32 > (int64_t)nbuf;
   }
 };
 
-// read one plane: n verbatim bits, then group tests; each positive test and
-// its run "0...01" is taken in one step from a 32-bit peek of the buffer
-__device__ __forceinline__ uint64_t plane_read(GBits& r, uint32_t& n) {
-  uint64_t wd = 0;
-  if (n > 0) wd = r.get64(n);
+// prefix parity: bit j of the result is the XOR of bits 0..j of s
+__device__ __forceinline__ uint32_t prefix_xor(uint32_t s) {
+  s ^= s << 1;
+  s ^= s << 2;
+  s ^= s << 4;
+  s ^= s << 8;
+  s ^= s << 16;
+  return s;
+}
+
+// the group tests of one plane one token at a time: a positive test and its
+// run "0...01" are taken in one step from a 32-bit peek of the buffer
+__device__ __forceinline__ void plane_tokens(GBits& r, uint32_t& n, uint64_t& wd) {
   while (n < 64) {
     r.refill();
     const uint32_t lo = (uint32_t)r.buf;
@@ -369,6 +385,52 @@ __device__ __forceinline__ uint64_t plane_read(GBits& r, uint32_t& n) {
         n += 32;
       }
     }
+  }
+}
+
+// read one plane: n verbatim bits, then the group tests, taken 32 bits at a
+// time without a loop over tokens.  In the section "1 0^r1 1  1 0^r2 1 ... 0"
+// the ones alternate between positive tests and run terminators, so within a
+// window that starts at a test the terminators are the ones with an even
+// inclusive prefix count.  The section ends at the first terminator followed
+// by a 0; otherwise every token whose terminator lies in the window is
+// complete and the next window starts right after the last of them.  The i-th
+// terminator of a window at bit t marks coefficient n + t - i.  Whenever that
+// reading could differ from the coder's (no terminator in the window, or a
+// run reaching the last coefficient, whose one is implied), the token loop
+// finishes the plane instead.
+__device__ __forceinline__ uint64_t plane_read(GBits& r, uint32_t& n) {
+  uint64_t wd = 0;
+  if (n > 0) wd = r.get64(n);
+  while (n < 64) {
+    r.refill();
+    const uint32_t s = (uint32_t)r.buf;
+    if ((s & 1u) == 0u) {  // negative test: the plane ends
+      r.drop(1);
+      break;
+    }
+    const uint32_t term = s & ~prefix_xor(s);
+    const uint32_t ends = term & ~(s >> 1) & 0x7FFFFFFFu;
+    const uint32_t last =
+        ends != 0u ? (uint32_t)__builtin_ctz(ends) : 31u - (uint32_t)__builtin_clz(term | 1u);
+    const uint32_t tm = term & ((2u << last) - 1u);
+    const uint32_t cnt = (uint32_t)__builtin_popcount(tm);
+    if (term == 0u || n + last - cnt > 62u) {
+      plane_tokens(r, n, wd);
+      break;
+    }
+    uint32_t rel = 0, left = tm;
+    for (uint32_t i = 1; left != 0u; ++i) {
+      rel |= 1u << ((uint32_t)__builtin_ctz(left) - i);
+      left &= left - 1u;
+    }
+    wd |= (uint64_t)rel << n;
+    n += last - cnt + 1;
+    if (ends != 0u) {
+      r.drop(last + 2);  // through the terminator and the negative test after it
+      break;
+    }
+    r.drop(last + 1);
   }
   return wd;
 }
@@ -451,17 +513,6 @@ __device__ __forceinline__ void forward_coeffs(const T e[64], int emax, typename
 }
 
 // coefficients truncated to p planes -> decoded block values (in d[l])
-template <class T>
-__device__ __forceinline__ void inverse_values(const typename FT<T>::U u[64], int emax, T d[64]) {
-  typedef typename FT<T>::S S;
-  S q[64];
-#pragma unroll
-  for (int r = 0; r < 64; ++r) q[kOrder.at[r]] = from_nb<T>(u[r]);
-  xform_inv(q);
-#pragma unroll
-  for (int l = 0; l < 64; ++l) d[l] = dequantize(q[l], emax);
-}
-
 // the inverse split so that its last (x) pass can run one block row at a time:
 // coefficients -> integers after the z and y passes ...
 template <class T>
@@ -485,6 +536,30 @@ __device__ __forceinline__ void inverse_row(typename FT<T>::S q[64], int r, int 
   lift_inv(q[4 * r], q[4 * r + 1], q[4 * r + 2], q[4 * r + 3]);
 #pragma unroll
   for (int t = 0; t < 4; ++t) out[t] = dequantize(q[4 * r + t], emax);
+}
+
+// whole-block form for the decoder: the x pass of every row, then
+// acc += dequantised values in the field precision
+template <class T> __device__ __forceinline__ void inverse_x(typename FT<T>::S q[64]) {
+#pragma unroll
+  for (int r = 0; r < 16; ++r) lift_inv(q[4 * r], q[4 * r + 1], q[4 * r + 2], q[4 * r + 3]);
+}
+// While every nonzero q * 2^(emax-30) is a normal float (emax >= -96), the
+// int -> float conversion performs the one rounding and the power-of-two
+// scale is exact, so the result equals dequantize() without double precision.
+__device__ __forceinline__ void dequant_add(const int32_t q[64], int emax, float acc[64]) {
+  if (emax >= -96) {
+    const float scale = __uint_as_float((uint32_t)(emax - 30 + 127) << 23);
+#pragma unroll
+    for (int l = 0; l < 64; ++l) acc[l] = acc[l] + (float)q[l] * scale;
+  } else {
+#pragma unroll
+    for (int l = 0; l < 64; ++l) acc[l] = acc[l] + dequantize(q[l], emax);
+  }
+}
+__device__ __forceinline__ void dequant_add(const int64_t q[64], int emax, double acc[64]) {
+#pragma unroll
+  for (int l = 0; l < 64; ++l) acc[l] = acc[l] + dequantize(q[l], emax);
 }
 
 template <class U> __device__ __forceinline__ U plane_mask(int P, int p) {

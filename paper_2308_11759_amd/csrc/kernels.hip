@@ -579,13 +579,8 @@ __device__ __forceinline__ bool decode_block_add(GBits& r, int minexp, T acc[64]
   planes_read<T>(r, u, p, pw);
   typename FT<T>::S q[64];
   inverse_zy<T>(u, q);
-#pragma unroll
-  for (int row = 0; row < 16; ++row) {
-    T v[4];
-    inverse_row<T>(q, row, emax, v);
-#pragma unroll
-    for (int t = 0; t < 4; ++t) acc[4 * row + t] = acc[4 * row + t] + v[t];
-  }
+  inverse_x<T>(q);
+  dequant_add(q, emax, acc);
   return true;
 }
 
@@ -611,12 +606,12 @@ __device__ __forceinline__ bool decode_block_sum(const Geo& g, const uint8_t* co
     const uint64_t start = index[chunk];
     const uint64_t stop = chunk + 1 < g.nchunks ? (uint64_t)index[chunk + 1] : words[i];
     const uint64_t off = aux[i][blk];
-    if (start > stop || stop > words[i] || off >= (stop - start) * 32) {
+    if (start > stop || stop > words[i] || stop > 0xFFFFFFFFull || off >= (stop - start) * 32) {
       ok = false;
       break;
     }
     GBits r;
-    r.init(payload + start + (off >> 5), payload + stop);
+    r.init(payload, (uint32_t)(start + (off >> 5)), (uint32_t)stop);
     r.skip((uint32_t)(off & 31));
     ok = decode_block_add<T>(r, minexp[i], acc, pw) && !r.bad();
   }
@@ -625,7 +620,7 @@ __device__ __forceinline__ bool decode_block_sum(const Geo& g, const uint8_t* co
 }
 
 template <class T>
-__global__ __launch_bounds__(64) void k_decode(DecArgs<T> a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1))) void k_decode(DecArgs<T> a) {
   __shared__ uint32_t s_planes[32 * 64];
   uint32_t* pw = s_planes + threadIdx.x;
   const uint64_t blk = (uint64_t)blockIdx.x * 64 + threadIdx.x;
@@ -637,7 +632,7 @@ __global__ __launch_bounds__(64) void k_decode(DecArgs<T> a) {
 // many retrieval queries in one launch: wave w belongs to the query q with
 // wave_prefix[q] <= w < wave_prefix[q + 1]
 template <class T>
-__global__ __launch_bounds__(64) void k_decode_queries(ServeArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1))) void k_decode_queries(ServeArgs a) {
   __shared__ uint32_t s_planes[32 * 64];
   uint32_t* pw = s_planes + threadIdx.x;
   const uint32_t w = blockIdx.x;
@@ -664,15 +659,13 @@ __global__ __launch_bounds__(64) void k_aux(AuxArgs a) {
   const uint32_t* payload = index + a.g.nchunks;
   const uint64_t start = index[chunk];
   const uint64_t stop = chunk + 1 < a.g.nchunks ? (uint64_t)index[chunk + 1] : a.words;
-  bool ok = start <= stop && stop <= a.words;
+  // a chunk holds at least one block, hence at least one bit
+  bool ok = start < stop && stop <= a.words && stop <= 0xFFFFFFFFull;
   GBits r;
-  r.init(payload + start, payload + (ok ? stop : start));
-  uint64_t consumed = 0;
+  r.init(payload, (uint32_t)start, (uint32_t)(ok ? stop : start));
   const uint64_t b0 = chunk * kChunkBlocks, b1 = min<uint64_t>(a.g.nblocks, b0 + kChunkBlocks);
   for (uint64_t blk = b0; blk < b1; ++blk) {
-    // bits consumed so far = words fetched * 32 - bits still buffered
-    consumed = (uint64_t)(r.p - (payload + start)) * 32 - r.nbuf;
-    a.aux[blk] = ok ? (uint32_t)consumed : 0u;
+    a.aux[blk] = ok ? (uint32_t)r.consumed((uint32_t)start) : 0u;
     if (ok) ok = block_skip<T>(r, a.minexp) && !r.bad();
   }
   if (!ok && a.status) atomicOr(a.status, 1u);
