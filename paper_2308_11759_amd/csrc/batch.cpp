@@ -30,7 +30,7 @@ struct pmc_batch {
   std::vector<std::vector<double>> tau;
   std::vector<std::vector<int>> minexp;
   // workspace layout (byte offsets into d_ws)
-  std::vector<uint64_t> off_xt, off_staging, off_cw, off_offs, off_tiles;
+  std::vector<uint64_t> off_xt0, off_xt1, off_staging, off_cw, off_offs, off_tiles;
   std::vector<uint64_t> meta_first;  // index of the field's first CompMeta
   uint64_t off_table = 0, off_items = 0, off_meta = 0, ws_total = 0;
   // stream regions (byte offsets into d_streams)
@@ -189,8 +189,11 @@ pmc_status pmc_batch_plan(pmc_ctx* ctx, int nf, const pmc_field* fields, const i
     b->minexp.push_back(me);
     b->maxn = std::max(b->maxn, n[i]);
     const uint64_t N = g.nx * g.ny * g.nz;
-    b->off_xt.push_back(ws);
+    // x~ ping-pong buffers (component i reads buffer (i-1)&1, writes i&1)
+    b->off_xt0.push_back(ws);
     if (n[i] > 1) ws += align256(N * elem_size(&fields[i]));
+    b->off_xt1.push_back(ws);
+    if (n[i] > 2) ws += align256(N * elem_size(&fields[i]));
     b->off_staging.push_back(ws);
     ws += align256(g.nchunks * chunk_cap_words_host(fields[i].dtype) * 4);
     b->off_cw.push_back(ws);
@@ -297,7 +300,8 @@ static pmc_status batch_launch(pmc_batch* b, const void* const* d_x, uint8_t* ws
     FieldDev& d = tab[i];
     std::memset(&d, 0, sizeof(d));
     d.x = d_x[i];
-    d.xt = ws + b->off_xt[i];
+    d.xt[0] = ws + b->off_xt0[i];
+    d.xt[1] = ws + b->off_xt1[i];
     d.g = b->g[i];
     d.staging = (uint32_t*)(ws + b->off_staging[i]);
     d.chunk_words = (uint32_t*)(ws + b->off_cw[i]);

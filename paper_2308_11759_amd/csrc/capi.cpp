@@ -68,14 +68,19 @@ int floor_log2(double tau) {
 }
 
 struct WsLayout {
-  uint64_t xt, staging, chunk_words, offsets, tile_sums, meta, total;
+  uint64_t xt[2], staging, chunk_words, offsets, tile_sums, meta, total;
 };
 
+// x~ is double-buffered: component i reads x~_{i-1} from xt[(i-1) & 1] and
+// writes x~_i to xt[i & 1] (the first reads nothing, the last writes nothing)
 WsLayout ws_layout(const pmc_field* f, const Geo& g, int n) {
   WsLayout w{};
   uint64_t o = 0;
-  w.xt = o;
-  if (n > 1) o += align256(g.nx * g.ny * g.nz * elem_size(f));
+  const uint64_t field = align256(g.nx * g.ny * g.nz * elem_size(f));
+  w.xt[0] = o;
+  if (n > 1) o += field;
+  w.xt[1] = o;
+  if (n > 2) o += field;
   w.staging = o;
   o += align256(g.nchunks * chunk_cap_words_host(f->dtype) * 4);
   w.chunk_words = o;
@@ -302,7 +307,8 @@ pmc_status pmc_compress(pmc_ctx* ctx, const pmc_field* f, const void* d_x, int n
     if (f->dtype == PMC_F32) {
       EncArgs<float> a{};
       a.x = (const float*)d_x;
-      a.xt = (float*)(ws + w.xt);
+      a.xt_in = i > 0 ? (const float*)(ws + w.xt[(i - 1) & 1]) : nullptr;
+      a.xt_out = (float*)(ws + w.xt[i & 1]);
       a.g = g;
       a.tau = tau[i];
       a.minexp = minexp[i];
@@ -330,7 +336,8 @@ pmc_status pmc_compress(pmc_ctx* ctx, const pmc_field* f, const void* d_x, int n
     } else {
       EncArgs<double> a{};
       a.x = (const double*)d_x;
-      a.xt = (double*)(ws + w.xt);
+      a.xt_in = i > 0 ? (const double*)(ws + w.xt[(i - 1) & 1]) : nullptr;
+      a.xt_out = (double*)(ws + w.xt[i & 1]);
       a.g = g;
       a.tau = tau[i];
       a.minexp = minexp[i];

@@ -124,6 +124,34 @@ __device__ __forceinline__ void store_row(T* __restrict__ f, const Geo& g, const
   }
 }
 
+// load row r of a block (edge replication as in load_block); a null field
+// reads as +0
+template <class T>
+__device__ __forceinline__ void load_row(const T* f, const Geo& g, const BlockPos& b, int r, T v[4]) {
+  if (!f) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) v[t] = (T)0;
+    return;
+  }
+  const T* row = row_ptr(f, g, b, r);
+  if (b.vx == 4 && g.rows_aligned) {
+    if constexpr (sizeof(T) == 4) {
+      float4 q = *reinterpret_cast<const float4*>(row);
+      v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    } else {
+      double2 q0 = *reinterpret_cast<const double2*>(row);
+      double2 q1 = *reinterpret_cast<const double2*>(row + 2);
+      v[0] = q0.x; v[1] = q0.y; v[2] = q1.x; v[3] = q1.y;
+    }
+  } else {
+    const uint32_t m = b.vx - 1;
+    v[0] = row[0];
+    v[1] = row[min<uint32_t>(1, m)];
+    v[2] = row[min<uint32_t>(2, m)];
+    v[3] = row[min<uint32_t>(3, m)];
+  }
+}
+
 // a copy the compiler cannot prove equal to the original: recomputing the
 // residual from such copies stops common-subexpression elimination from
 // keeping a 64-value array alive across the whole kernel
@@ -134,6 +162,13 @@ template <class T> __device__ __forceinline__ T opaque(T v) {
 template <class T> __device__ __forceinline__ T* opaque(T* p) {
   __asm__ volatile("" : "+v"(p));
   return p;
+}
+
+__device__ __forceinline__ BlockPos opaque_pos(BlockPos b) {
+  b.x0 = opaque(b.x0);
+  b.y0 = opaque(b.y0);
+  b.z0 = opaque(b.z0);
+  return b;
 }
 
 // NaN-propagating max, matching "take a if not a <= m"
@@ -212,26 +247,28 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
   BlockPos bp = block_pos(a.g, active ? blk : 0);
   load_block_lds(a.x, a.g, bp, s_x, lane);
   const XLds<T> X{s_x, lane};
-  T tv[64];
-  if (a.first) {
-#pragma unroll
-    for (int l = 0; l < 64; ++l) tv[l] = (T)0;
-  } else {
-    load_block(a.xt, a.g, bp, tv);
-  }
+  // row addresses are recomputed where used instead of kept in registers
+  bp = opaque_pos(bp);
 
-  // residual statistics: exponent, all-zero test, error before this component
+  // residual statistics: exponent, all-zero test, error before this component.
+  // x~_{i-1} is re-read row by row wherever it is needed (it stays in the
+  // caches), so it never occupies 64 registers.
   U maxabs = 0;
   double eb = 0.0;
   bool nonfinite = false;
+#pragma unroll 1
+  for (int r = 0; r < 16; ++r) {
+    T tr[4];
+    load_row(a.first ? nullptr : a.xt_in, a.g, bp, r, tr);
 #pragma unroll
-  for (int l = 0; l < 64; ++l) {
-    const T xl = X.at(l);
-    T ev = xl - tv[l];
-    U ab = abs_bits(ev);
-    maxabs = ab > maxabs ? ab : maxabs;
-    if (lvalid(bp, l)) eb = nmax(eb, fabs((double)xl - (double)tv[l]));
-    nonfinite |= !isfinite(xl);
+    for (int t = 0; t < 4; ++t) {
+      const int l = 4 * r + t;
+      const T xl = X.at(l);
+      U ab = abs_bits((T)(xl - tr[t]));
+      maxabs = ab > maxabs ? ab : maxabs;
+      if (lvalid(bp, l)) eb = nmax(eb, fabs((double)xl - (double)tr[t]));
+      nonfinite |= !isfinite(xl);
+    }
   }
   const int emax = block_emax<T>(maxabs);
   int p = emax - a.minexp + kGuard;
@@ -239,20 +276,26 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
   int mode = MODE_EMPTY, delta = 0;
   uint32_t nbits = 1;
   double err = eb;
-  bool dirty = false;  // x~ rows of a rejected candidate were stored
 
   // acceptance: smallest plane count p >= p0 whose block meets tau without
   // raising the error; else empty (already within tau) or raw
   if (active && maxabs != 0) {
     for (;;) {
-      // re-derived each iteration so the LDS reads below are not hoisted
-      // out of the loop into 64 registers
+      // re-derived each iteration so the loads below are not hoisted out of
+      // the loop into 64 registers
       const XLds<T> XL{opaque(s_x), lane};
+      const T* const tin = a.first ? nullptr : opaque(a.xt_in);
+      const BlockPos bq = opaque_pos(bp);  // row addresses are recomputed, not held
       U u[64];
       {
         T e[64];
 #pragma unroll
-        for (int l = 0; l < 64; ++l) e[l] = XL.at(l) - opaque(tv[l]);
+        for (int r = 0; r < 16; ++r) {
+          T tr[4];
+          load_row(tin, a.g, bq, r, tr);
+#pragma unroll
+          for (int t = 0; t < 4; ++t) e[4 * r + t] = XL.at(4 * r + t) - tr[t];
+        }
         forward_coeffs<T>(e, emax, u);
       }
       bool feasible = false;
@@ -272,17 +315,17 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
         double ea = 0.0;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          T row[4];
+          T row[4], tr[4];
           inverse_row<T>(q, r, emax, row);
+          load_row(tin, a.g, bq, r, tr);
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
             const int l = 4 * r + t;
-            row[t] = tv[l] + row[t];  // x~_{i-1} + x_i in the field precision
+            row[t] = tr[t] + row[t];  // x~_{i-1} + x_i in the field precision
             if (lvalid(bp, l)) ea = nmax(ea, fabs((double)XL.at(l) - (double)row[t]));
           }
-          if (!a.last) store_row(a.xt, a.g, bp, r, row);
+          if (!a.last) store_row(a.xt_out, a.g, bq, r, row);
         }
-        dirty = !a.last;
         if (ea <= a.tau && ea <= eb) {
           mode = MODE_CODED;
           nbits = cb;
@@ -307,26 +350,34 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
   }
   bool miss = false;
   if (active && mode == MODE_RAW) {
-    T d[64];
     double ea = 0.0;
+#pragma unroll 1
+    for (int r = 0; r < 16; ++r) {
+      T tr[4], d[4];
+      load_row(a.first ? nullptr : a.xt_in, a.g, bp, r, tr);
 #pragma unroll
-    for (int l = 0; l < 64; ++l) {
-      const T xl = X.at(l);
-      d[l] = tv[l] + (xl - tv[l]);
-      if (lvalid(bp, l)) ea = nmax(ea, fabs((double)xl - (double)d[l]));
+      for (int t = 0; t < 4; ++t) {
+        const int l = 4 * r + t;
+        const T xl = X.at(l);
+        d[t] = tr[t] + (xl - tr[t]);
+        if (lvalid(bp, l)) ea = nmax(ea, fabs((double)xl - (double)d[t]));
+      }
+      if (!a.last) store_row(a.xt_out, a.g, bp, r, d);
     }
     err = ea;
     miss = !(ea <= a.tau && ea <= eb);
-    if (!a.last) store_block(a.xt, a.g, bp, d);
   } else if (active && mode == MODE_EMPTY) {
     miss = !(eb <= a.tau);
-    // x~_i = x~_{i-1} + 0: written when x~ is fresh (first component) or a
-    // rejected candidate overwrote it
-    if (!a.last && (a.first || dirty)) {
-      T d[64];
+    // x~_i = x~_{i-1} + 0 (also over the rows of a rejected candidate)
+    if (!a.last) {
+#pragma unroll 1
+      for (int r = 0; r < 16; ++r) {
+        T tr[4], d[4];
+        load_row(a.first ? nullptr : a.xt_in, a.g, bp, r, tr);
 #pragma unroll
-      for (int l = 0; l < 64; ++l) d[l] = tv[l] + (T)0;
-      store_block(a.xt, a.g, bp, d);
+        for (int t = 0; t < 4; ++t) d[t] = tr[t] + (T)0;
+        store_row(a.xt_out, a.g, bp, r, d);
+      }
     }
   }
   if (!active) {
@@ -358,13 +409,16 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
   // what the block emits: coefficients (coded) or the residual's bits (raw)
   U u[64];
   if (mode == MODE_CODED) {
+    const T* const tin = a.first ? nullptr : opaque(a.xt_in);
     T e[64];
 #pragma unroll
-    for (int l = 0; l < 64; ++l) e[l] = X.at(l) - opaque(tv[l]);
-    forward_coeffs<T>(e, emax, u);
-  } else {
+    for (int r = 0; r < 16; ++r) {
+      T tr[4];
+      load_row(tin, a.g, bp, r, tr);
 #pragma unroll
-    for (int l = 0; l < 64; ++l) u[l] = (U)raw_bits_lo((T)(X.at(l) - opaque(tv[l])));
+      for (int t = 0; t < 4; ++t) e[4 * r + t] = X.at(4 * r + t) - tr[t];
+    }
+    forward_coeffs<T>(e, emax, u);
   }
 
   __syncthreads();  // every lane is done with x: its LDS is reused below
@@ -396,9 +450,16 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
       w.init(&s_emit[(lane >> 4) * kEmitWords], off, w0, kEmitWords);
       if (mode == MODE_EMPTY) {
         w.put(0, 1);
-      } else if (mode == MODE_RAW) {
+      } else if (mode == MODE_RAW) {  // the residual's bits, x and x~_{i-1} re-read
         w.put(3, 2);
-        for (int l = 0; l < 64; ++l) w.put64((uint64_t)u[l], (uint32_t)P);
+#pragma unroll 1
+        for (int r = 0; r < 16; ++r) {
+          T xr[4], tr[4];
+          load_row(a.x, a.g, bp, r, xr);
+          load_row(a.first ? nullptr : a.xt_in, a.g, bp, r, tr);
+#pragma unroll
+          for (int t = 0; t < 4; ++t) w.put64((uint64_t)raw_bits_lo((T)(xr[t] - tr[t])), (uint32_t)P);
+        }
       } else {
         w.put(1, 2);  // nonempty, coded
         for (int t = 0; t < delta; ++t) w.put(1, 1);
@@ -428,7 +489,7 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
 }
 
 template <class T>
-__global__ __launch_bounds__(64) void k_encode(EncArgs<T> a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1))) void k_encode(EncArgs<T> a) {
   __shared__ T s_x[64 * 64];
   encode_wave<T>(a, blockIdx.x, s_x);
 }
@@ -716,7 +777,8 @@ __global__ void k_fill64(unsigned long long* p, uint64_t n, unsigned long long v
 template <class T> __device__ __forceinline__ EncArgs<T> field_enc_args(const FieldDev& f, int comp) {
   EncArgs<T> a;
   a.x = reinterpret_cast<const T*>(f.x);
-  a.xt = reinterpret_cast<T*>(f.xt);
+  a.xt_in = reinterpret_cast<const T*>(comp > 0 ? f.xt[(comp - 1) & 1] : nullptr);
+  a.xt_out = reinterpret_cast<T*>(f.xt[comp & 1]);
   a.g = f.g;
   a.tau = f.tau[comp];
   a.minexp = f.minexp[comp];
@@ -730,7 +792,7 @@ template <class T> __device__ __forceinline__ EncArgs<T> field_enc_args(const Fi
 }
 
 template <class T>
-__global__ __launch_bounds__(64) void k_encode_batch(BatchArgs b) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1))) void k_encode_batch(BatchArgs b) {
   __shared__ T s_x[64 * 64];
   for (uint32_t it = blockIdx.x; it < b.nitems; it += gridDim.x) {
     const Item w = b.items[it];

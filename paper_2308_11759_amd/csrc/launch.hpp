@@ -42,7 +42,8 @@ static_assert(sizeof(CompMeta) == 128, "CompMeta layout");
 
 template <class T> struct EncArgs {
   const T* x;
-  T* xt;  // x~_{i-1} in, x~_i out (in place)
+  const T* xt_in;  // x~_{i-1} (not read for the first component)
+  T* xt_out;       // x~_i (not written for the last component); never xt_in
   Geo g;
   double tau;
   int minexp;
@@ -129,7 +130,7 @@ struct AuxArgs {
 // ---- batches of fields (one table entry per field) -----------------------
 struct FieldDev {
   const void* x;
-  void* xt;
+  void* xt[2];  // x~ ping-pong: component i reads xt[(i-1)&1], writes xt[i&1]
   Geo g;
   uint32_t* staging;
   uint32_t* chunk_words;
