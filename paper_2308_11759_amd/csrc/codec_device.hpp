@@ -274,13 +274,15 @@ __device__ __forceinline__ void plane_emit(LdsBits& w, uint64_t wd, uint32_t& n)
 // use of them.  A reader is refilled only when first < end.
 struct GBits {
   const uint32_t* base;
+  const uint8_t* squeeze;  // the byte table of squeeze_table() (in LDS)
   uint32_t p;  // index of the next word to load
   uint32_t end;
   uint64_t buf;
   uint32_t nbuf;
   uint32_t nxt;  // word p - 1, loaded ahead
-  __device__ __forceinline__ void init(const uint32_t* b, uint32_t first, uint32_t e) {
+  __device__ __forceinline__ void init(const uint32_t* b, uint32_t first, uint32_t e, const uint8_t* sq) {
     base = b;
+    squeeze = sq;
     end = e;
     buf = 0;
     nbuf = 0;
@@ -388,49 +390,89 @@ __device__ __forceinline__ void plane_tokens(GBits& r, uint32_t& n, uint64_t& wd
   }
 }
 
-// read one plane: n verbatim bits, then the group tests, taken 32 bits at a
-// time without a loop over tokens.  In the section "1 0^r1 1  1 0^r2 1 ... 0"
-// the ones alternate between positive tests and run terminators, so within a
-// window that starts at a test the terminators are the ones with an even
-// inclusive prefix count.  The section ends at the first terminator followed
-// by a 0; otherwise every token whose terminator lies in the window is
-// complete and the next window starts right after the last of them.  The i-th
-// terminator of a window at bit t marks coefficient n + t - i.  Whenever that
-// reading could differ from the coder's (no terminator in the window, or a
-// run reaching the last coefficient, whose one is implied), the token loop
-// finishes the plane instead.
+// squeeze: every set bit of m, at position t and i-th from the bottom
+// (i >= 1), moves to t - i.  Applied to the run terminators of a group-test
+// section (which are at least two bits apart and never at bit 0) this drops
+// the positive tests and leaves the plane bits.  The table holds, for each
+// byte, its own squeeze shifted up by one (a byte's lowest set bit may sit at
+// its bit 0); the bytes are joined with shifts given by the number of set
+// bits below them.
+__device__ __forceinline__ uint32_t squeeze_byte(uint32_t b) {
+  uint32_t r = 0, i = 0;
+  for (uint32_t t = 0; t < 8; ++t)
+    if ((b >> t) & 1u) r |= 1u << (t + 1 - ++i);
+  return r;
+}
+// fill the 256-entry table at tab (LDS) with all threads of the block
+__device__ __forceinline__ void squeeze_table(uint8_t* tab) {
+  for (uint32_t b = threadIdx.x; b < 256; b += blockDim.x) tab[b] = (uint8_t)squeeze_byte(b);
+  __syncthreads();
+}
+__device__ __forceinline__ uint32_t squeeze32(uint32_t m, const uint8_t* tab) {
+  const uint32_t b0 = m & 0xFFu, b1 = (m >> 8) & 0xFFu, b2 = (m >> 16) & 0xFFu, b3 = m >> 24;
+  const uint32_t c1 = (uint32_t)__builtin_popcount(b0);
+  const uint32_t c2 = c1 + (uint32_t)__builtin_popcount(b1);
+  const uint32_t c3 = c2 + (uint32_t)__builtin_popcount(b2);
+  return ((uint32_t)tab[b0] >> 1) | ((uint32_t)tab[b1] << (7 - c1)) | ((uint32_t)tab[b2] << (15 - c2)) |
+         ((uint32_t)tab[b3] << (23 - c3));
+}
+
+// read one plane: n verbatim bits, then the group tests, 32 bits at a time.
+// In the section "1 0^r1 1  1 0^r2 1 ... 0" the ones alternate between
+// positive tests and run terminators, so within a window that starts at a
+// test the terminators are the ones with an even inclusive prefix count; the
+// i-th terminator at bit t marks coefficient n + t - i (squeeze32).  The
+// section ends at the first terminator followed by a 0 (a negative test), or
+// where a run reaches the last coefficient, whose one is implied (no
+// terminator, no test after it).  A window that ends inside a run lets the
+// next window start inside it: a virtual positive test (vg = 1) is put in
+// front.
 __device__ __forceinline__ uint64_t plane_read(GBits& r, uint32_t& n) {
   uint64_t wd = 0;
   if (n > 0) wd = r.get64(n);
+  uint32_t vg = 0;
   while (n < 64) {
     r.refill();
-    const uint32_t s = (uint32_t)r.buf;
+    const uint32_t s = ((uint32_t)r.buf << vg) | vg;
     if ((s & 1u) == 0u) {  // negative test: the plane ends
       r.drop(1);
       break;
     }
     const uint32_t term = s & ~prefix_xor(s);
     const uint32_t ends = term & ~(s >> 1) & 0x7FFFFFFFu;
-    const uint32_t last =
-        ends != 0u ? (uint32_t)__builtin_ctz(ends) : 31u - (uint32_t)__builtin_clz(term | 1u);
+    const uint32_t last = (uint32_t)__builtin_ctz(ends | 0x80000000u);
     const uint32_t tm = term & ((2u << last) - 1u);
-    const uint32_t cnt = (uint32_t)__builtin_popcount(tm);
-    if (term == 0u || n + last - cnt > 62u) {
-      plane_tokens(r, n, wd);
+    // terminators whose coefficient stays below 63; the first beyond marks
+    // a run that reaches coefficient 63 instead
+    const uint32_t rel = squeeze32(tm, r.squeeze);
+    const uint32_t room = 63u - n;  // coefficients n..62 may carry a terminator
+    const uint32_t vrel = room >= 32u ? rel : rel & ((1u << room) - 1u);
+    const bool over = vrel != rel;
+    const uint32_t nn = vrel != 0u ? 32u - (uint32_t)__builtin_clz(vrel) : 0u;
+    const uint32_t g = nn + (uint32_t)__builtin_popcount(vrel);  // the bit after the last one taken
+    wd |= (uint64_t)vrel << n;
+    n += nn;
+    if (!over && tm != 0u) {
+      if (ends != 0u) {  // through the terminator and the negative test
+        r.drop(g + 1 - vg);
+        break;
+      }
+      r.drop(g - vg);  // complete tokens; the next window starts at a test
+      vg = 0;
+      continue;
+    }
+    // a positive test at bit g starts a run from coefficient n: either it
+    // reaches coefficient 63 inside the window (implied one), or it runs on
+    const uint32_t z = 63u - n;
+    if (z <= 31u - g) {
+      r.drop(g + 1 + z - vg);
+      wd |= 1ull << 63;
+      n = 64;
       break;
     }
-    uint32_t rel = 0, left = tm;
-    for (uint32_t i = 1; left != 0u; ++i) {
-      rel |= 1u << ((uint32_t)__builtin_ctz(left) - i);
-      left &= left - 1u;
-    }
-    wd |= (uint64_t)rel << n;
-    n += last - cnt + 1;
-    if (ends != 0u) {
-      r.drop(last + 2);  // through the terminator and the negative test after it
-      break;
-    }
-    r.drop(last + 1);
+    r.drop(32 - vg);
+    n += 31u - g;
+    vg = 1;
   }
   return wd;
 }

@@ -650,7 +650,7 @@ __device__ __forceinline__ bool decode_block_add(GBits& r, int minexp, T acc[64]
 template <class T>
 __device__ __forceinline__ bool decode_block_sum(const Geo& g, const uint8_t* const* s, const uint32_t* const* aux,
                                                  const uint64_t* words, const int* minexp, int ncomp, const T* in,
-                                                 T* out, uint64_t blk, uint32_t* pw) {
+                                                 T* out, uint64_t blk, uint32_t* pw, const uint8_t* sq) {
   const BlockPos bp = block_pos(g, blk);
   const uint64_t chunk = blk / kChunkBlocks;
   T acc[64];
@@ -672,7 +672,7 @@ __device__ __forceinline__ bool decode_block_sum(const Geo& g, const uint8_t* co
       break;
     }
     GBits r;
-    r.init(payload, (uint32_t)(start + (off >> 5)), (uint32_t)stop);
+    r.init(payload, (uint32_t)(start + (off >> 5)), (uint32_t)stop, sq);
     r.skip((uint32_t)(off & 31));
     ok = decode_block_add<T>(r, minexp[i], acc, pw) && !r.bad();
   }
@@ -683,10 +683,12 @@ __device__ __forceinline__ bool decode_block_sum(const Geo& g, const uint8_t* co
 template <class T>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1))) void k_decode(DecArgs<T> a) {
   __shared__ uint32_t s_planes[32 * 64];
+  __shared__ uint8_t s_squeeze[256];
+  squeeze_table(s_squeeze);
   uint32_t* pw = s_planes + threadIdx.x;
   const uint64_t blk = (uint64_t)blockIdx.x * 64 + threadIdx.x;
   if (blk >= a.g.nblocks) return;
-  if (!decode_block_sum<T>(a.g, a.s, a.aux, a.words, a.minexp, a.ncomp, a.in, a.out, blk, pw))
+  if (!decode_block_sum<T>(a.g, a.s, a.aux, a.words, a.minexp, a.ncomp, a.in, a.out, blk, pw, s_squeeze))
     atomicOr(a.status, 1u);
 }
 
@@ -695,6 +697,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
 template <class T>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1))) void k_decode_queries(ServeArgs a) {
   __shared__ uint32_t s_planes[32 * 64];
+  __shared__ uint8_t s_squeeze[256];
+  squeeze_table(s_squeeze);
   uint32_t* pw = s_planes + threadIdx.x;
   const uint32_t w = blockIdx.x;
   uint32_t lo = 0, hi = a.nq;  // largest q with wave_prefix[q] <= w
@@ -707,13 +711,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
   const uint64_t blk = (uint64_t)(w - a.wave_prefix[lo]) * 64 + threadIdx.x;
   if (blk >= q.g.nblocks) return;
   if (!decode_block_sum<T>(q.g, q.s, q.aux, q.words, q.minexp, q.ncomp, reinterpret_cast<const T*>(q.in),
-                           reinterpret_cast<T*>(q.out), blk, pw))
+                           reinterpret_cast<T*>(q.out), blk, pw, s_squeeze))
     atomicOr(a.status, 1u);
 }
 
 // per-block bit offsets of a stream written elsewhere: parse each chunk
 template <class T>
 __global__ __launch_bounds__(64) void k_aux(AuxArgs a) {
+  __shared__ uint8_t s_squeeze[256];
+  squeeze_table(s_squeeze);
   const uint64_t chunk = (uint64_t)blockIdx.x * 64 + threadIdx.x;
   if (chunk >= a.g.nchunks) return;
   const uint32_t* index = reinterpret_cast<const uint32_t*>(a.s + kHeaderBytes);
@@ -723,7 +729,7 @@ __global__ __launch_bounds__(64) void k_aux(AuxArgs a) {
   // a chunk holds at least one block, hence at least one bit
   bool ok = start < stop && stop <= a.words && stop <= 0xFFFFFFFFull;
   GBits r;
-  r.init(payload, (uint32_t)start, (uint32_t)(ok ? stop : start));
+  r.init(payload, (uint32_t)start, (uint32_t)(ok ? stop : start), s_squeeze);
   const uint64_t b0 = chunk * kChunkBlocks, b1 = min<uint64_t>(a.g.nblocks, b0 + kChunkBlocks);
   for (uint64_t blk = b0; blk < b1; ++blk) {
     a.aux[blk] = ok ? (uint32_t)r.consumed((uint32_t)start) : 0u;
