@@ -589,6 +589,20 @@ template <class T> __device__ __forceinline__ void inverse_x(typename FT<T>::S q
 // While every nonzero q * 2^(emax-30) is a normal float (emax >= -96), the
 // int -> float conversion performs the one rounding and the power-of-two
 // scale is exact, so the result equals dequantize() without double precision.
+__device__ __forceinline__ void dequantize_block(const int32_t q[64], int emax, float d[64]) {
+  if (emax >= -96) {
+    const float scale = __uint_as_float((uint32_t)(emax - 30 + 127) << 23);
+#pragma unroll
+    for (int l = 0; l < 64; ++l) d[l] = (float)q[l] * scale;
+  } else {
+#pragma unroll
+    for (int l = 0; l < 64; ++l) d[l] = dequantize(q[l], emax);
+  }
+}
+__device__ __forceinline__ void dequantize_block(const int64_t q[64], int emax, double d[64]) {
+#pragma unroll
+  for (int l = 0; l < 64; ++l) d[l] = dequantize(q[l], emax);
+}
 __device__ __forceinline__ void dequant_add(const int32_t q[64], int emax, float acc[64]) {
   if (emax >= -96) {
     const float scale = __uint_as_float((uint32_t)(emax - 30 + 127) << 23);

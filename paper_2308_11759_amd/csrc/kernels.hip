@@ -47,6 +47,20 @@ __device__ __forceinline__ BlockPos block_pos(const Geo& g, uint64_t blk) {
 __device__ __forceinline__ bool lvalid(const BlockPos& b, int l) {
   return (uint32_t)(l & 3) < b.vx && (uint32_t)((l >> 2) & 3) < b.vy && (uint32_t)(l >> 4) < b.vz;
 }
+// bit l set when sample l of the block lies inside the field
+__device__ __forceinline__ uint64_t valid_mask(const BlockPos& b) {
+  const uint64_t xm = (1ull << b.vx) - 1ull;                                               // a row
+  const uint64_t ym = (xm | xm << 4 | xm << 8 | xm << 12) & ((1ull << (4 * b.vy)) - 1ull);  // a z slice
+  const uint64_t zm = ym | ym << 16 | ym << 32 | ym << 48;
+  return b.vz == 4 ? zm : zm & ((1ull << (16 * b.vz)) - 1ull);
+}
+// |v| for sample l, or +0 where the sample lies outside the field: the mask
+// bit becomes an all-ones / all-zeros word applied to the double's bits, so
+// no per-sample condition (a lane mask) has to stay live
+__device__ __forceinline__ double masked_abs(uint64_t m, int l, double v) {
+  const uint64_t keep = 0ull - ((m >> l) & 1ull);
+  return __longlong_as_double((long long)((uint64_t)__double_as_longlong(v) & keep & 0x7FFFFFFFFFFFFFFFull));
+}
 
 // one block row (ly, lz): 4 consecutive x values; rows of partial blocks
 // repeat their last valid sample (edge replication on load)
@@ -249,14 +263,14 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
   const XLds<T> X{s_x, lane};
   // row addresses are recomputed where used instead of kept in registers
   bp = opaque_pos(bp);
+  const uint64_t vmask = valid_mask(bp);
 
   // residual statistics: exponent, all-zero test, error before this component.
   // x~_{i-1} is re-read row by row wherever it is needed (it stays in the
   // caches), so it never occupies 64 registers.
-  U maxabs = 0;
+  U maxabs = 0, xmax = 0;  // largest |residual| and |x| bit patterns
   double eb = 0.0;
-  bool nonfinite = false;
-#pragma unroll 1
+#pragma unroll 4
   for (int r = 0; r < 16; ++r) {
     T tr[4];
     load_row(a.first ? nullptr : a.xt_in, a.g, bp, r, tr);
@@ -266,8 +280,9 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
       const T xl = X.at(l);
       U ab = abs_bits((T)(xl - tr[t]));
       maxabs = ab > maxabs ? ab : maxabs;
-      if (lvalid(bp, l)) eb = nmax(eb, fabs((double)xl - (double)tr[t]));
-      nonfinite |= !isfinite(xl);
+      eb = nmax(eb, masked_abs(vmask, l, (double)xl - (double)tr[t]));
+      const U xb = abs_bits(xl);
+      xmax = xb > xmax ? xb : xmax;
     }
   }
   const int emax = block_emax<T>(maxabs);
@@ -284,7 +299,7 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
       // re-derived each iteration so the loads below are not hoisted out of
       // the loop into 64 registers
       const XLds<T> XL{opaque(s_x), lane};
-      const T* const tin = a.first ? nullptr : opaque(a.xt_in);
+      const T* const tin = a.first ? nullptr : a.xt_in;
       const BlockPos bq = opaque_pos(bp);  // row addresses are recomputed, not held
       U u[64];
       {
@@ -312,17 +327,19 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
         // they come (a rejected candidate is overwritten below)
         typename FT<T>::S q[64];
         inverse_zy<T>(u, q);
+        inverse_x<T>(q);
+        T d[64];
+        dequantize_block(q, emax, d);
         double ea = 0.0;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           T row[4], tr[4];
-          inverse_row<T>(q, r, emax, row);
           load_row(tin, a.g, bq, r, tr);
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
             const int l = 4 * r + t;
-            row[t] = tr[t] + row[t];  // x~_{i-1} + x_i in the field precision
-            if (lvalid(bp, l)) ea = nmax(ea, fabs((double)XL.at(l) - (double)row[t]));
+            row[t] = tr[t] + d[l];  // x~_{i-1} + x_i in the field precision
+            ea = nmax(ea, masked_abs(vmask, l, (double)XL.at(l) - (double)row[t]));
           }
           if (!a.last) store_row(a.xt_out, a.g, bq, r, row);
         }
@@ -360,7 +377,7 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
         const int l = 4 * r + t;
         const T xl = X.at(l);
         d[t] = tr[t] + (xl - tr[t]);
-        if (lvalid(bp, l)) ea = nmax(ea, fabs((double)xl - (double)d[t]));
+        ea = nmax(ea, masked_abs(vmask, l, (double)xl - (double)d[t]));
       }
       if (!a.last) store_row(a.xt_out, a.g, bp, r, d);
     }
@@ -393,6 +410,7 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
     const unsigned long long br = __ballot(active && mode == MODE_RAW);
     const unsigned long long bs = __ballot(active && mode == MODE_CODED && delta > 0);
     const unsigned long long bm = __ballot(miss);
+    const bool nonfinite = xmax >= abs_bits((T)__builtin_inf());  // an infinite or NaN sample
     const unsigned long long bn = __ballot(active && nonfinite);
     const double wm = wave_max(err);
     if (lane == 0) {
@@ -409,12 +427,13 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
   // what the block emits: coefficients (coded) or the residual's bits (raw)
   U u[64];
   if (mode == MODE_CODED) {
-    const T* const tin = a.first ? nullptr : opaque(a.xt_in);
+    const T* const tin = a.first ? nullptr : a.xt_in;
+    const BlockPos bq = opaque_pos(bp);
     T e[64];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       T tr[4];
-      load_row(tin, a.g, bp, r, tr);
+      load_row(tin, a.g, bq, r, tr);
 #pragma unroll
       for (int t = 0; t < 4; ++t) e[4 * r + t] = X.at(4 * r + t) - tr[t];
     }
