@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -127,6 +128,7 @@ pmc_store* store_from_meta(const pmc_field* f, const Geo& g, int n, const double
     s->nraw.push_back(hm[i].nraw);
     s->nesc.push_back(hm[i].nesc);
     s->nmiss.push_back(hm[i].nmiss);
+    s->max_span.push_back(hm[i].max_span);
   }
   return s;
 }
@@ -453,6 +455,8 @@ static pmc_status decode_range(pmc_ctx* ctx, const pmc_store* s, int k0, int k1,
   const void* in = d_in;
   for (int i0 = k0; i0 < k1; i0 += group) {
     const int i1 = i0 + group < k1 ? i0 + group : k1;
+    uint64_t span = 0;
+    for (int i = i0; i < i1; ++i) span = std::max(span, s->max_span[i]);
     if (s->f.dtype == PMC_F32) {
       DecArgs<float> a{};
       for (int i = i0; i < i1; ++i) {
@@ -467,7 +471,7 @@ static pmc_status decode_range(pmc_ctx* ctx, const pmc_store* s, int k0, int k1,
       a.g = s->g;
       a.status = status;
       ProfScope ps(ctx, "k_decode_f32");
-      e = launch_decode<float>(a, ctx->stream);
+      e = launch_decode<float>(a, span, ctx->stream);
     } else {
       DecArgs<double> a{};
       for (int i = i0; i < i1; ++i) {
@@ -482,7 +486,7 @@ static pmc_status decode_range(pmc_ctx* ctx, const pmc_store* s, int k0, int k1,
       a.g = s->g;
       a.status = status;
       ProfScope ps(ctx, "k_decode_f64");
-      e = launch_decode<double>(a, ctx->stream);
+      e = launch_decode<double>(a, span, ctx->stream);
     }
     if (e != hipSuccess) return hipfail(ctx, e, "decode");
     in = d_out;
@@ -601,7 +605,7 @@ static bool parse_blob(const void* host_buf, size_t size, BlobView* v) {
 
 // host-side validation of one stream (header fields and chunk index)
 static bool check_stream(const uint8_t* p, uint64_t bytes, const pmc_field* f, const Geo& g, double tau,
-                         uint64_t* words) {
+                         uint64_t* words, uint64_t* max_span) {
   if (bytes < 64) return false;
   uint32_t h[16];
   std::memcpy(h, p, 64);
@@ -623,7 +627,14 @@ static bool check_stream(const uint8_t* p, uint64_t bytes, const pmc_field* f, c
     if (idx[c] < prev || idx[c] > w) return false;
     prev = idx[c];
   }
+  // largest span of four consecutive chunks (the chunks of one decode wave)
+  uint64_t span = 0;
+  for (uint64_t c = 0; c < nch; c += 4) {
+    const uint64_t stop = c + 4 < nch ? idx[c + 4] : w;
+    span = std::max<uint64_t>(span, stop - idx[c]);
+  }
   *words = w;
+  *max_span = span;
   return true;
 }
 
@@ -660,9 +671,9 @@ pmc_status pmc_store_deserialize(pmc_ctx* ctx, const void* host_buf, size_t size
     std::memcpy(&tau, &r[0], 8);
     std::memcpy(&linf, &r[1], 8);
     off = align256(off);
-    uint64_t words = 0;
+    uint64_t words = 0, span = 0;
     if (!(tau > 0.0) || !std::isfinite(tau) || (i > 0 && !(tau < s->tau[i - 1])) ||
-        !check_stream(region + off, r[2], &v.f, g, tau, &words)) {
+        !check_stream(region + off, r[2], &v.f, g, tau, &words, &span)) {
       delete s;
       return fail(ctx, PMC_E_CORRUPT, "component %d: malformed stream", i);
     }
@@ -678,6 +689,7 @@ pmc_status pmc_store_deserialize(pmc_ctx* ctx, const void* host_buf, size_t size
     s->nraw.push_back(r[5]);
     s->nesc.push_back(r[6]);
     s->nmiss.push_back(r[7]);
+    s->max_span.push_back(span);
     off += r[2];
   }
   hipError_t e = hipSetDevice(ctx->device);

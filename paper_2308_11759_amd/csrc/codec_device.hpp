@@ -274,15 +274,13 @@ __device__ __forceinline__ void plane_emit(LdsBits& w, uint64_t wd, uint32_t& n)
 // use of them.  A reader is refilled only when first < end.
 struct GBits {
   const uint32_t* base;
-  const uint8_t* squeeze;  // the byte table of squeeze_table() (in LDS)
   uint32_t p;  // index of the next word to load
   uint32_t end;
   uint64_t buf;
   uint32_t nbuf;
   uint32_t nxt;  // word p - 1, loaded ahead
-  __device__ __forceinline__ void init(const uint32_t* b, uint32_t first, uint32_t e, const uint8_t* sq) {
+  __device__ __forceinline__ void init(const uint32_t* b, uint32_t first, uint32_t e) {
     base = b;
-    squeeze = sq;
     end = e;
     buf = 0;
     nbuf = 0;
@@ -320,6 +318,10 @@ struct GBits {
     refill();
     drop(count);
   }
+  __device__ __forceinline__ uint32_t peek32() {  // the next 32 bits
+    refill();
+    return (uint32_t)buf;
+  }
   // bits consumed since word `from`: words moved into the buffer minus those held
   __device__ __forceinline__ uint64_t consumed(uint32_t from) const {
     return (uint64_t)(p - 1 - from) * 32 - nbuf;
@@ -328,6 +330,50 @@ struct GBits {
   __device__ __forceinline__ bool bad() const {
     return (int64_t)((int64_t)p - 1 - (int64_t)end) * 32 > (int64_t)nbuf;
   }
+};
+
+// LDS bit reader over words staged in LDS (a wave's chunks): three words and
+// a bit offset; peeks are funnel shifts and every skip reloads the three
+// words at the new position, so there is no refill branch.  Words [0, CAPW)
+// exist; bits past `end` are unspecified and bad() reports any use of them.
+template <uint32_t CAPW> struct LBits {
+  const uint32_t* s;
+  uint32_t p, o, end;  // word of the next bit, its bit offset, end word
+  uint32_t w0, w1, w2;
+  __device__ __forceinline__ void load() {
+    w0 = s[p < CAPW ? p : CAPW - 1];
+    w1 = s[p + 1 < CAPW ? p + 1 : CAPW - 1];
+    w2 = s[p + 2 < CAPW ? p + 2 : CAPW - 1];
+  }
+  __device__ __forceinline__ void init(const uint32_t* st, uint32_t first, uint32_t e) {
+    s = st;
+    p = first;
+    o = 0;
+    end = e;
+    load();
+  }
+  __device__ __forceinline__ uint32_t peek32() const { return __builtin_amdgcn_alignbit(w1, w0, o); }
+  __device__ __forceinline__ uint64_t peek64() const {
+    return (uint64_t)__builtin_amdgcn_alignbit(w1, w0, o) | ((uint64_t)__builtin_amdgcn_alignbit(w2, w1, o) << 32);
+  }
+  __device__ __forceinline__ void skip(uint32_t count) {  // count <= 64
+    const uint32_t t = o + count;
+    p += t >> 5;
+    o = t & 31u;
+    load();
+  }
+  __device__ __forceinline__ uint32_t get(uint32_t count) {  // count <= 32
+    const uint32_t v = peek32();
+    skip(count);
+    return count >= 32 ? v : v & ((1u << count) - 1u);
+  }
+  __device__ __forceinline__ uint64_t get64(uint32_t count) {  // count <= 64
+    const uint64_t v = peek64();
+    skip(count);
+    return count >= 64 ? v : v & ((1ull << count) - 1ull);
+  }
+  __device__ __forceinline__ uint64_t consumed(uint32_t from) const { return (uint64_t)(p - from) * 32 + o; }
+  __device__ __forceinline__ bool bad() const { return (uint64_t)p * 32 + o > (uint64_t)end * 32; }
 };
 
 // prefix parity: bit j of the result is the XOR of bits 0..j of s
@@ -426,53 +472,42 @@ __device__ __forceinline__ uint32_t squeeze32(uint32_t m, const uint8_t* tab) {
 // where a run reaches the last coefficient, whose one is implied (no
 // terminator, no test after it).  A window that ends inside a run lets the
 // next window start inside it: a virtual positive test (vg = 1) is put in
-// front.
-__device__ __forceinline__ uint64_t plane_read(GBits& r, uint32_t& n) {
+// front.  Each window is decoded without branches; the loop runs once per
+// window.
+template <class R>
+__device__ __forceinline__ uint64_t plane_read(R& r, uint32_t& n, const uint8_t* sq) {
   uint64_t wd = 0;
   if (n > 0) wd = r.get64(n);
   uint32_t vg = 0;
   while (n < 64) {
-    r.refill();
-    const uint32_t s = ((uint32_t)r.buf << vg) | vg;
-    if ((s & 1u) == 0u) {  // negative test: the plane ends
-      r.drop(1);
-      break;
-    }
+    const uint32_t s = (r.peek32() << vg) | vg;
+    const bool neg = (s & 1u) == 0u;  // negative first test: the plane ends here
     const uint32_t term = s & ~prefix_xor(s);
     const uint32_t ends = term & ~(s >> 1) & 0x7FFFFFFFu;
     const uint32_t last = (uint32_t)__builtin_ctz(ends | 0x80000000u);
-    const uint32_t tm = term & ((2u << last) - 1u);
-    // terminators whose coefficient stays below 63; the first beyond marks
-    // a run that reaches coefficient 63 instead
-    const uint32_t rel = squeeze32(tm, r.squeeze);
+    const uint32_t tm = neg ? 0u : term & ((2u << last) - 1u);
+    // terminators whose coefficient stays below 63; one beyond marks a run
+    // that reaches coefficient 63 instead
+    const uint32_t rel = squeeze32(tm, sq);
     const uint32_t room = 63u - n;  // coefficients n..62 may carry a terminator
     const uint32_t vrel = room >= 32u ? rel : rel & ((1u << room) - 1u);
-    const bool over = vrel != rel;
+    const bool tokens = vrel == rel && tm != 0u;
     const uint32_t nn = vrel != 0u ? 32u - (uint32_t)__builtin_clz(vrel) : 0u;
     const uint32_t g = nn + (uint32_t)__builtin_popcount(vrel);  // the bit after the last one taken
     wd |= (uint64_t)vrel << n;
     n += nn;
-    if (!over && tm != 0u) {
-      if (ends != 0u) {  // through the terminator and the negative test
-        r.drop(g + 1 - vg);
-        break;
-      }
-      r.drop(g - vg);  // complete tokens; the next window starts at a test
-      vg = 0;
-      continue;
-    }
-    // a positive test at bit g starts a run from coefficient n: either it
-    // reaches coefficient 63 inside the window (implied one), or it runs on
+    // otherwise a positive test at bit g starts a run from coefficient n:
+    // it reaches coefficient 63 inside the window (implied one), or runs on
     const uint32_t z = 63u - n;
-    if (z <= 31u - g) {
-      r.drop(g + 1 + z - vg);
-      wd |= 1ull << 63;
-      n = 64;
-      break;
-    }
-    r.drop(32 - vg);
-    n += 31u - g;
-    vg = 1;
+    const bool run = !neg && !tokens;
+    const bool implied = run && z <= 31u - g;
+    const bool done = neg || implied || (tokens && ends != 0u);
+    const uint32_t c = neg ? 1u : tokens ? (ends != 0u ? g + 1u : g) : implied ? g + 1u + z : 32u;
+    r.skip(c - vg);
+    wd |= implied ? (1ull << 63) : 0ull;
+    n = implied ? 64u : run ? n + 31u - g : n;
+    vg = run ? 1u : 0u;
+    if (done) break;
   }
   return wd;
 }
@@ -679,24 +714,41 @@ __device__ __forceinline__ void planes_emit(LdsBits& w, const typename FT<T>::U 
 }
 
 // read p planes from the top into u (zero below)
-template <class T>
-__device__ __forceinline__ void planes_read(GBits& r, typename FT<T>::U u[64], int p, uint32_t* pw) {
+template <class T, class R>
+__device__ __forceinline__ void planes_read(R& r, typename FT<T>::U u[64], int p, uint32_t* pw, const uint8_t* sq) {
   typedef typename FT<T>::U U;
   constexpr int P = FT<T>::P;
-#pragma unroll
-  for (int j = 0; j < 64; ++j) u[j] = 0;
   uint32_t n = 0;
-  for (int g = 0; 16 * g < p; ++g) {
+  // the top 16 planes straight into registers (the plane loop is unrolled so
+  // every plane word has a fixed register), then one transpose
+  {
+    uint32_t Tw[32];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      uint64_t wd = 0;
+      if (t < p) wd = plane_read(r, n, sq);
+      Tw[15 - t] = (uint32_t)wd;
+      Tw[31 - t] = (uint32_t)(wd >> 32);
+    }
+    transpose32(Tw);  // back to 16-bit slices of coefficients j and j+32
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+      u[j] = (U)(Tw[j] & 0xFFFFu) << (P - 16);
+      u[j + 32] = (U)(Tw[j] >> 16) << (P - 16);
+    }
+  }
+  // deeper planes, 16 at a time through the lane's LDS column
+  for (int g = 1; 16 * g < p; ++g) {
     const int tmax = p - 16 * g < 16 ? p - 16 * g : 16;
     for (int t = 0; t < 16; ++t) {
-      uint64_t wd = t < tmax ? plane_read(r, n) : 0ull;
+      uint64_t wd = t < tmax ? plane_read(r, n, sq) : 0ull;
       pw[(15 - t) * 64] = (uint32_t)wd;
       pw[(31 - t) * 64] = (uint32_t)(wd >> 32);
     }
     uint32_t Tw[32];
 #pragma unroll
     for (int j = 0; j < 32; ++j) Tw[j] = pw[j * 64];
-    transpose32(Tw);  // back to 16-bit slices of coefficients j and j+32
+    transpose32(Tw);
     const int base = P - 16 * (g + 1);
 #pragma unroll
     for (int j = 0; j < 32; ++j) {
@@ -708,7 +760,7 @@ __device__ __forceinline__ void planes_read(GBits& r, typename FT<T>::U u[64], i
 
 // advance a reader over one block without reconstructing it; returns false
 // on a malformed header
-template <class T> __device__ __forceinline__ bool block_skip(GBits& r, int minexp) {
+template <class T, class R> __device__ __forceinline__ bool block_skip(R& r, int minexp, const uint8_t* sq) {
   constexpr int P = FT<T>::P;
   if (!r.get(1)) return true;  // empty
   if (r.get(1)) {              // raw
@@ -724,7 +776,7 @@ template <class T> __device__ __forceinline__ bool block_skip(GBits& r, int mine
   p = (p < 0 ? 0 : (p > P ? P : p)) + delta;
   if (emax < 2 - FT<T>::BIAS || p < 1 || p > P) return false;
   uint32_t n = 0;
-  for (int t = 0; t < p; ++t) (void)plane_read(r, n);
+  for (int t = 0; t < p; ++t) (void)plane_read(r, n, sq);
   return true;
 }
 

@@ -36,6 +36,7 @@ struct pmc_store {
   std::vector<double> tau, linf;
   std::vector<int> minexp;
   std::vector<uint64_t> bytes, offset, aux_offset, words, nempty, ncoded, nraw, nesc, nmiss;
+  std::vector<uint64_t> max_span;  // largest payload words of a decode wave's four chunks
   const uint8_t* d_base = nullptr;  // caller-owned device memory holding the streams
 };
 

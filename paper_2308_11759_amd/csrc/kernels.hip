@@ -597,13 +597,20 @@ __global__ __launch_bounds__(64) void k_pack(PackArgs a) {
   const uint32_t lane = threadIdx.x;
   const uint64_t chunk = (uint64_t)blockIdx.x * 4 + (lane >> 4);
   const uint32_t sub = lane & 15;
+  uint32_t span = 0;  // words of this wave's four chunks (one decode wave)
   if (chunk < a.nchunks) {
     const uint32_t words = a.chunk_words[chunk];
     const uint32_t o = a.offsets[chunk];
     const uint32_t* src = a.staging + chunk * (uint64_t)CAP;
     for (uint32_t i = sub; i < words; i += 16) payload[o + i] = src[i];
     if (sub == 0) index[chunk] = o;
+    span = sub == 0 ? words : 0u;
   }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) span += __shfl_xor(span, d, 64);
+  // most waves see a maximum already recorded: read before the atomic
+  if (lane == 0 && span > *(volatile unsigned long long*)&a.meta[a.comp].max_span)
+    atomicMax(&a.meta[a.comp].max_span, (unsigned long long)span);
   if (blockIdx.x == 0 && lane < 16) {
     uint32_t* h = reinterpret_cast<uint32_t*>(base);
     const uint64_t taub = (uint64_t)__double_as_longlong(a.tau);
@@ -634,12 +641,18 @@ __global__ __launch_bounds__(64) void k_pack(PackArgs a) {
 // Alg. 2 over one block per lane: x~ = (((x~_in or +0) + x_1) + x_2) ... in
 // the field precision; the block's bits start at its chunk's word offset plus
 // the block's bit offset from the per-block index
-template <class T>
-__device__ __forceinline__ bool decode_block_add(GBits& r, int minexp, T acc[64], uint32_t* pw) {
+template <class T, class R>
+__device__ __forceinline__ bool decode_block_add(R& r, int minexp, T acc[64], uint32_t* pw, const uint8_t* sq) {
   typedef typename FT<T>::U U;
   constexpr int P = FT<T>::P;
-  if (!r.get(1)) return true;  // empty: x_i = 0 leaves x~ unchanged
-  if (r.get(1)) {              // raw block
+  constexpr int EB = FT<T>::EBITS;
+  const uint32_t h = r.peek32();
+  if (!(h & 1u)) {  // empty: x_i = 0 leaves x~ unchanged
+    r.skip(1);
+    return true;
+  }
+  if (h & 2u) {  // raw block
+    r.skip(2);
 #pragma unroll
     for (int l = 0; l < 64; ++l) {
       T v = from_raw((U)r.get64((uint32_t)P), (T)0);
@@ -647,16 +660,25 @@ __device__ __forceinline__ bool decode_block_add(GBits& r, int minexp, T acc[64]
     }
     return true;
   }
-  int delta = 0;
-  while (r.get(1)) {
-    if (++delta > P) return false;
+  // unary escalation count, then the biased block exponent
+  int delta = (int)__builtin_ctz(~(h >> 2) | 0x40000000u);
+  int emax;
+  if (3 + delta + EB <= 32) {
+    emax = (int)((h >> (3 + delta)) & ((1u << EB) - 1u)) - FT<T>::BIAS;
+    r.skip((uint32_t)(3 + delta + EB));
+  } else {
+    r.skip(2);
+    delta = 0;
+    while (r.get(1)) {
+      if (++delta > P) return false;
+    }
+    emax = (int)r.get((uint32_t)EB) - FT<T>::BIAS;
   }
-  const int emax = (int)r.get((uint32_t)FT<T>::EBITS) - FT<T>::BIAS;
   int p = emax - minexp + kGuard;
   p = (p < 0 ? 0 : (p > P ? P : p)) + delta;
   if (emax < 2 - FT<T>::BIAS || p < 1 || p > P) return false;
   U u[64];
-  planes_read<T>(r, u, p, pw);
+  planes_read<T>(r, u, p, pw, sq);
   typename FT<T>::S q[64];
   inverse_zy<T>(u, q);
   inverse_x<T>(q);
@@ -664,59 +686,98 @@ __device__ __forceinline__ bool decode_block_add(GBits& r, int minexp, T acc[64]
   return true;
 }
 
-// decode block `blk` of a field: x~ = in (or +0) plus components [0, ncomp)
-// of the given streams, left to right; false on a malformed stream
-template <class T>
-__device__ __forceinline__ bool decode_block_sum(const Geo& g, const uint8_t* const* s, const uint32_t* const* aux,
-                                                 const uint64_t* words, const int* minexp, int ncomp, const T* in,
-                                                 T* out, uint64_t blk, uint32_t* pw, const uint8_t* sq) {
-  const BlockPos bp = block_pos(g, blk);
+// words of one wave's four chunks staged in LDS per component; spans larger
+// than this use the global-memory reader (the host picks the variant from
+// the largest span of the streams it decodes)
+constexpr uint32_t kStageWords = 2944;
+
+// decode the wave's 64 blocks [64 w, 64 w + 64) of a field: x~ = in (or +0)
+// plus components [0, ncomp) of the given streams, left to right.  Every lane
+// runs the component loop (the staging copies are shared); false on a
+// malformed stream.
+template <class T, bool kStaged>
+__device__ __forceinline__ bool decode_wave(const Geo& g, const uint8_t* const* s, const uint32_t* const* aux,
+                                            const uint64_t* words, const int* minexp, int ncomp, const T* in, T* out,
+                                            uint64_t w, uint32_t* pw, const uint8_t* sq, uint32_t* stage) {
+  const uint32_t lane = threadIdx.x;
+  const uint64_t blk = w * 64 + lane;
+  const bool active = blk < g.nblocks;
+  const BlockPos bp = block_pos(g, active ? blk : 0);
   const uint64_t chunk = blk / kChunkBlocks;
   T acc[64];
-  if (in) {
+  if (in && active) {
     load_block(in, g, bp, acc);
   } else {
 #pragma unroll
     for (int l = 0; l < 64; ++l) acc[l] = (T)0;
   }
   bool ok = true;
-  for (int i = 0; i < ncomp && ok; ++i) {
+  for (int i = 0; i < ncomp; ++i) {
     const uint32_t* index = reinterpret_cast<const uint32_t*>(s[i] + kHeaderBytes);
     const uint32_t* payload = index + g.nchunks;
+    uint64_t s0 = 0, s1 = 0;
+    bool span_ok = true;
+    if constexpr (kStaged) {
+      // the wave's chunks [4w, 4w + 4) are consecutive in the payload
+      const uint64_t c0 = w * 4, c1 = min<uint64_t>(c0 + 4, g.nchunks);
+      s0 = index[c0];
+      s1 = c1 < g.nchunks ? (uint64_t)index[c1] : words[i];
+      span_ok = s0 <= s1 && s1 <= words[i] && s1 - s0 <= kStageWords;
+      __syncthreads();  // the previous component's words are no longer read
+      if (span_ok) {
+        const uint32_t span = (uint32_t)(s1 - s0);
+        for (uint32_t k = 0; k < span; k += 64) {
+          const uint32_t j = k + lane < span ? k + lane : span - 1;
+          __builtin_amdgcn_global_load_lds((gmem_void_t*)(payload + s0 + j), (lds_void_t*)(stage + k), 4, 0, 0);
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+      }
+      __syncthreads();
+    }
+    if (!active || !ok) continue;
     const uint64_t start = index[chunk];
     const uint64_t stop = chunk + 1 < g.nchunks ? (uint64_t)index[chunk + 1] : words[i];
     const uint64_t off = aux[i][blk];
-    if (start > stop || stop > words[i] || stop > 0xFFFFFFFFull || off >= (stop - start) * 32) {
+    if (!span_ok || start > stop || stop > words[i] || stop > 0xFFFFFFFFull || off >= (stop - start) * 32 ||
+        (kStaged && (start < s0 || stop > s1))) {
       ok = false;
-      break;
+      continue;
     }
-    GBits r;
-    r.init(payload, (uint32_t)(start + (off >> 5)), (uint32_t)stop, sq);
-    r.skip((uint32_t)(off & 31));
-    ok = decode_block_add<T>(r, minexp[i], acc, pw) && !r.bad();
+    if constexpr (kStaged) {
+      LBits<kStageWords> r;
+      r.init(stage, (uint32_t)(start - s0 + (off >> 5)), (uint32_t)(stop - s0));
+      r.skip((uint32_t)(off & 31));
+      ok = decode_block_add<T>(r, minexp[i], acc, pw, sq) && !r.bad();
+    } else {
+      GBits r;
+      r.init(payload, (uint32_t)(start + (off >> 5)), (uint32_t)stop);
+      r.skip((uint32_t)(off & 31));
+      ok = decode_block_add<T>(r, minexp[i], acc, pw, sq) && !r.bad();
+    }
   }
-  if (ok) store_block(out, g, bp, acc);
-  return ok;
+  if (active && ok) store_block(out, g, bp, acc);
+  return ok || !active;
 }
 
-template <class T>
+template <class T, bool kStaged>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1))) void k_decode(DecArgs<T> a) {
   __shared__ uint32_t s_planes[32 * 64];
   __shared__ uint8_t s_squeeze[256];
+  __shared__ uint32_t s_stage[kStaged ? kStageWords : 1];
   squeeze_table(s_squeeze);
   uint32_t* pw = s_planes + threadIdx.x;
-  const uint64_t blk = (uint64_t)blockIdx.x * 64 + threadIdx.x;
-  if (blk >= a.g.nblocks) return;
-  if (!decode_block_sum<T>(a.g, a.s, a.aux, a.words, a.minexp, a.ncomp, a.in, a.out, blk, pw, s_squeeze))
+  if (!decode_wave<T, kStaged>(a.g, a.s, a.aux, a.words, a.minexp, a.ncomp, a.in, a.out, blockIdx.x, pw, s_squeeze,
+                               s_stage))
     atomicOr(a.status, 1u);
 }
 
 // many retrieval queries in one launch: wave w belongs to the query q with
 // wave_prefix[q] <= w < wave_prefix[q + 1]
-template <class T>
+template <class T, bool kStaged>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1))) void k_decode_queries(ServeArgs a) {
   __shared__ uint32_t s_planes[32 * 64];
   __shared__ uint8_t s_squeeze[256];
+  __shared__ uint32_t s_stage[kStaged ? kStageWords : 1];
   squeeze_table(s_squeeze);
   uint32_t* pw = s_planes + threadIdx.x;
   const uint32_t w = blockIdx.x;
@@ -727,10 +788,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     else hi = mid;
   }
   const QueryDev& q = a.q[lo];
-  const uint64_t blk = (uint64_t)(w - a.wave_prefix[lo]) * 64 + threadIdx.x;
-  if (blk >= q.g.nblocks) return;
-  if (!decode_block_sum<T>(q.g, q.s, q.aux, q.words, q.minexp, q.ncomp, reinterpret_cast<const T*>(q.in),
-                           reinterpret_cast<T*>(q.out), blk, pw, s_squeeze))
+  if (!decode_wave<T, kStaged>(q.g, q.s, q.aux, q.words, q.minexp, q.ncomp, reinterpret_cast<const T*>(q.in),
+                               reinterpret_cast<T*>(q.out), w - a.wave_prefix[lo], pw, s_squeeze, s_stage))
     atomicOr(a.status, 1u);
 }
 
@@ -748,11 +807,11 @@ __global__ __launch_bounds__(64) void k_aux(AuxArgs a) {
   // a chunk holds at least one block, hence at least one bit
   bool ok = start < stop && stop <= a.words && stop <= 0xFFFFFFFFull;
   GBits r;
-  r.init(payload, (uint32_t)start, (uint32_t)(ok ? stop : start), s_squeeze);
+  r.init(payload, (uint32_t)start, (uint32_t)(ok ? stop : start));
   const uint64_t b0 = chunk * kChunkBlocks, b1 = min<uint64_t>(a.g.nblocks, b0 + kChunkBlocks);
   for (uint64_t blk = b0; blk < b1; ++blk) {
     a.aux[blk] = ok ? (uint32_t)r.consumed((uint32_t)start) : 0u;
-    if (ok) ok = block_skip<T>(r, a.minexp) && !r.bad();
+    if (ok) ok = block_skip<T>(r, a.minexp, s_squeeze) && !r.bad();
   }
   if (!ok && a.status) atomicOr(a.status, 1u);
 }
@@ -901,13 +960,19 @@ __global__ __launch_bounds__(64) void k_bpack(BatchArgs b) {
   const uint32_t lane = threadIdx.x;
   const uint64_t chunk = (uint64_t)q.index * 4 + (lane >> 4);
   const uint32_t sub = lane & 15;
+  uint32_t span = 0;  // words of this wave's four chunks (one decode wave)
   if (chunk < f.g.nchunks) {
     const uint32_t words = f.chunk_words[chunk];
     const uint32_t o = f.offsets[chunk];
     const uint32_t* src = f.staging + chunk * cap;
     for (uint32_t i = sub; i < words; i += 16) payload[o + i] = src[i];
     if (sub == 0) index[chunk] = o;
+    span = sub == 0 ? words : 0u;
   }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) span += __shfl_xor(span, d, 64);
+  if (lane == 0 && span > *(volatile unsigned long long*)&f.meta0[b.comp].max_span)
+    atomicMax(&f.meta0[b.comp].max_span, (unsigned long long)span);
   if (q.index == 0 && lane < 16) {
     uint32_t* h = reinterpret_cast<uint32_t*>(base);
     const double tau = f.tau[b.comp];
@@ -954,14 +1019,16 @@ template <class T> hipError_t launch_pack(const PackArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_pack<T>, dim3((uint32_t)wgs), dim3(64), 0, s, a);
   return hipGetLastError();
 }
-template <class T> hipError_t launch_decode(const DecArgs<T>& a, hipStream_t s) {
+template <class T> hipError_t launch_decode(const DecArgs<T>& a, uint64_t max_span, hipStream_t s) {
   const uint64_t wgs = (a.g.nblocks + 63) / 64;
-  hipLaunchKernelGGL(k_decode<T>, dim3((uint32_t)wgs), dim3(64), 0, s, a);
+  if (max_span <= kStageWords) hipLaunchKernelGGL((k_decode<T, true>), dim3((uint32_t)wgs), dim3(64), 0, s, a);
+  else hipLaunchKernelGGL((k_decode<T, false>), dim3((uint32_t)wgs), dim3(64), 0, s, a);
   return hipGetLastError();
 }
-template <class T> hipError_t launch_decode_queries(const ServeArgs& a, hipStream_t s) {
+template <class T> hipError_t launch_decode_queries(const ServeArgs& a, uint64_t max_span, hipStream_t s) {
   if (a.nwaves == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_decode_queries<T>, dim3(a.nwaves), dim3(64), 0, s, a);
+  if (max_span <= kStageWords) hipLaunchKernelGGL((k_decode_queries<T, true>), dim3(a.nwaves), dim3(64), 0, s, a);
+  else hipLaunchKernelGGL((k_decode_queries<T, false>), dim3(a.nwaves), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 template <class T> hipError_t launch_aux(const AuxArgs& a, hipStream_t s) {
@@ -1007,10 +1074,10 @@ template hipError_t launch_encode<float>(const EncArgs<float>&, hipStream_t);
 template hipError_t launch_encode<double>(const EncArgs<double>&, hipStream_t);
 template hipError_t launch_pack<float>(const PackArgs&, hipStream_t);
 template hipError_t launch_pack<double>(const PackArgs&, hipStream_t);
-template hipError_t launch_decode<float>(const DecArgs<float>&, hipStream_t);
-template hipError_t launch_decode<double>(const DecArgs<double>&, hipStream_t);
-template hipError_t launch_decode_queries<float>(const ServeArgs&, hipStream_t);
-template hipError_t launch_decode_queries<double>(const ServeArgs&, hipStream_t);
+template hipError_t launch_decode<float>(const DecArgs<float>&, uint64_t, hipStream_t);
+template hipError_t launch_decode<double>(const DecArgs<double>&, uint64_t, hipStream_t);
+template hipError_t launch_decode_queries<float>(const ServeArgs&, uint64_t, hipStream_t);
+template hipError_t launch_decode_queries<double>(const ServeArgs&, uint64_t, hipStream_t);
 template hipError_t launch_aux<float>(const AuxArgs&, hipStream_t);
 template hipError_t launch_aux<double>(const AuxArgs&, hipStream_t);
 template hipError_t launch_range<float>(const float*, uint64_t, unsigned long long*, hipStream_t);

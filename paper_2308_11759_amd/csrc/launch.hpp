@@ -36,7 +36,8 @@ struct CompMeta {
   unsigned long long stream_bytes;
   unsigned int flags;
   unsigned int pad;
-  unsigned long long reserved[6];
+  unsigned long long max_span;  // largest payload words of four consecutive chunks (one decode wave)
+  unsigned long long reserved[5];
 };
 static_assert(sizeof(CompMeta) == 128, "CompMeta layout");
 
@@ -75,7 +76,7 @@ struct PackArgs {
   const uint32_t* chunk_words;
   const uint32_t* offsets;
   uint64_t nchunks;
-  const CompMeta* meta;
+  CompMeta* meta;  // the pack records each component's largest decode-wave span
   int comp;
   int minexp;
   uint8_t* streams;
@@ -169,9 +170,11 @@ hipError_t launch_batch_init(const FieldDev* fields, uint32_t nfields, hipStream
 template <class T> hipError_t launch_encode(const EncArgs<T>& a, hipStream_t s);
 hipError_t launch_scan(const ScanArgs& a, hipStream_t s);
 template <class T> hipError_t launch_aux(const AuxArgs& a, hipStream_t s);
-template <class T> hipError_t launch_decode_queries(const ServeArgs& a, hipStream_t s);
+// max_span: the largest word span of a wave's four chunks over the decoded
+// streams; spans up to the LDS staging capacity use the staged kernel
+template <class T> hipError_t launch_decode_queries(const ServeArgs& a, uint64_t max_span, hipStream_t s);
 template <class T> hipError_t launch_pack(const PackArgs& a, hipStream_t s);
-template <class T> hipError_t launch_decode(const DecArgs<T>& a, hipStream_t s);
+template <class T> hipError_t launch_decode(const DecArgs<T>& a, uint64_t max_span, hipStream_t s);
 template <class T> hipError_t launch_range(const T* x, uint64_t n, unsigned long long* out, hipStream_t s);
 hipError_t launch_fill64(unsigned long long* p, uint64_t n, unsigned long long v, hipStream_t s);
 

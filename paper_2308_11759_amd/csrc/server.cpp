@@ -229,6 +229,7 @@ bool launch_step(pmc_server* sv) {
   uint32_t* hpre[2] = {(uint32_t*)(htab + 2 * sv->max_batch * sizeof(QueryDev)),
                        (uint32_t*)(htab + 2 * sv->max_batch * sizeof(QueryDev)) + (sv->max_batch + 1)};
   uint32_t nq[2] = {0, 0}, nw[2] = {0, 0};
+  uint64_t span[2] = {0, 0};  // largest decode-wave span of the step's streams, per type
   hpre[0][0] = hpre[1][0] = 0;
   Step st{};
   st.id = step_id;
@@ -281,6 +282,7 @@ bool launch_step(pmc_server* sv) {
       d.aux[i] = (const uint32_t*)(s->d_base + s->aux_offset[c]);
       d.words[i] = s->words[c];
       d.minexp[i] = s->minexp[c];
+      span[t] = std::max(span[t], s->max_span[c]);
     }
     d.dtype = s->f.dtype;
     d.out = out;
@@ -319,7 +321,8 @@ bool launch_step(pmc_server* sv) {
     a.nq = nq[t];
     a.nwaves = nw[t];
     a.status = (unsigned int*)(dtab + sv->table_slot_bytes - 256);
-    e = t == 0 ? launch_decode_queries<float>(a, sv->stream) : launch_decode_queries<double>(a, sv->stream);
+    e = t == 0 ? launch_decode_queries<float>(a, span[t], sv->stream)
+               : launch_decode_queries<double>(a, span[t], sv->stream);
   }
   for (const CopyJob& c : copies)
     if (e == hipSuccess) e = hipMemcpyAsync(c.dst, c.src, c.bytes, hipMemcpyDeviceToDevice, sv->stream);
