@@ -115,6 +115,13 @@ pmc_status pmc_store_info(const pmc_store* s, int* n, double* tau, double* linf,
  * escalated (coded with more planes than the tolerance alone asks for) and
  * tolerance misses. */
 pmc_status pmc_store_counts(const pmc_store* s, int i, uint64_t counts[5]);
+/* Decode layout of component i (0-based): *max_span_words = the largest
+ * number of payload words in four consecutive chunks (the 64 blocks one
+ * decode wavefront handles), and *staged = 1 when that span fits the LDS
+ * staging buffer of the decoder (those components are read from LDS; larger
+ * spans, e.g. streams of mostly raw blocks, are read from device memory).
+ * Either pointer may be NULL.  PMC_E_ARG on a bad index. */
+pmc_status pmc_store_span(const pmc_store* s, int i, uint64_t* max_span_words, int* staged);
 /* Field of a store. */
 pmc_status pmc_store_field(const pmc_store* s, pmc_field* f);
 /* Device address and byte size of component i's stream (0-based). */

@@ -415,6 +415,13 @@ pmc_status pmc_store_counts(const pmc_store* s, int i, uint64_t counts[5]) {
   return PMC_OK;
 }
 
+pmc_status pmc_store_span(const pmc_store* s, int i, uint64_t* max_span_words, int* staged) {
+  if (!s || i < 0 || i >= s->n) return PMC_E_ARG;
+  if (max_span_words) *max_span_words = s->max_span[i];
+  if (staged) *staged = s->max_span[i] <= stage_words() ? 1 : 0;
+  return PMC_OK;
+}
+
 pmc_status pmc_store_field(const pmc_store* s, pmc_field* f) {
   if (!s || !f) return PMC_E_ARG;
   *f = s->f;

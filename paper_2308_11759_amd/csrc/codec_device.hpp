@@ -715,7 +715,7 @@ __device__ __forceinline__ void planes_emit(LdsBits& w, const typename FT<T>::U 
 
 // read p planes from the top into u (zero below)
 template <class T, class R>
-__device__ __forceinline__ void planes_read(R& r, typename FT<T>::U u[64], int p, uint32_t* pw, const uint8_t* sq) {
+__device__ __forceinline__ void planes_read(R& r, typename FT<T>::U u[64], int p, const uint8_t* sq) {
   typedef typename FT<T>::U U;
   constexpr int P = FT<T>::P;
   uint32_t n = 0;
@@ -737,23 +737,15 @@ __device__ __forceinline__ void planes_read(R& r, typename FT<T>::U u[64], int p
       u[j + 32] = (U)(Tw[j] >> 16) << (P - 16);
     }
   }
-  // deeper planes, 16 at a time through the lane's LDS column
-  for (int g = 1; 16 * g < p; ++g) {
-    const int tmax = p - 16 * g < 16 ? p - 16 * g : 16;
-    for (int t = 0; t < 16; ++t) {
-      uint64_t wd = t < tmax ? plane_read(r, n, sq) : 0ull;
-      pw[(15 - t) * 64] = (uint32_t)wd;
-      pw[(31 - t) * 64] = (uint32_t)(wd >> 32);
-    }
-    uint32_t Tw[32];
-#pragma unroll
-    for (int j = 0; j < 32; ++j) Tw[j] = pw[j * 64];
-    transpose32(Tw);
-    const int base = P - 16 * (g + 1);
+  // deeper planes (rare): each plane's bits are deposited directly
+  for (int t = 16; t < p; ++t) {
+    const uint64_t wd = plane_read(r, n, sq);
+    const uint32_t lo = (uint32_t)wd, hi = (uint32_t)(wd >> 32);
+    const int b = P - 1 - t;
 #pragma unroll
     for (int j = 0; j < 32; ++j) {
-      u[j] |= (U)(Tw[j] & 0xFFFFu) << base;
-      u[j + 32] |= (U)(Tw[j] >> 16) << base;
+      u[j] |= (U)((lo >> j) & 1u) << b;
+      u[j + 32] |= (U)((hi >> j) & 1u) << b;
     }
   }
 }

@@ -642,7 +642,7 @@ __global__ __launch_bounds__(64) void k_pack(PackArgs a) {
 // the field precision; the block's bits start at its chunk's word offset plus
 // the block's bit offset from the per-block index
 template <class T, class R>
-__device__ __forceinline__ bool decode_block_add(R& r, int minexp, T acc[64], uint32_t* pw, const uint8_t* sq) {
+__device__ __forceinline__ bool decode_block_add(R& r, int minexp, T acc[64], const uint8_t* sq) {
   typedef typename FT<T>::U U;
   constexpr int P = FT<T>::P;
   constexpr int EB = FT<T>::EBITS;
@@ -678,7 +678,7 @@ __device__ __forceinline__ bool decode_block_add(R& r, int minexp, T acc[64], ui
   p = (p < 0 ? 0 : (p > P ? P : p)) + delta;
   if (emax < 2 - FT<T>::BIAS || p < 1 || p > P) return false;
   U u[64];
-  planes_read<T>(r, u, p, pw, sq);
+  planes_read<T>(r, u, p, sq);
   typename FT<T>::S q[64];
   inverse_zy<T>(u, q);
   inverse_x<T>(q);
@@ -686,10 +686,11 @@ __device__ __forceinline__ bool decode_block_add(R& r, int minexp, T acc[64], ui
   return true;
 }
 
-// words of one wave's four chunks staged in LDS per component; spans larger
-// than this use the global-memory reader (the host picks the variant from
-// the largest span of the streams it decodes)
-constexpr uint32_t kStageWords = 2944;
+// words of one wave's four chunks staged in LDS per component (13.3 KB, so
+// that 12 one-wave workgroups fit a CU's LDS); spans larger than this use
+// the global-memory reader (the host picks the variant from the largest span
+// of the streams it decodes)
+constexpr uint32_t kStageWords = 3328;
 
 // decode the wave's 64 blocks [64 w, 64 w + 64) of a field: x~ = in (or +0)
 // plus components [0, ncomp) of the given streams, left to right.  Every lane
@@ -698,7 +699,7 @@ constexpr uint32_t kStageWords = 2944;
 template <class T, bool kStaged>
 __device__ __forceinline__ bool decode_wave(const Geo& g, const uint8_t* const* s, const uint32_t* const* aux,
                                             const uint64_t* words, const int* minexp, int ncomp, const T* in, T* out,
-                                            uint64_t w, uint32_t* pw, const uint8_t* sq, uint32_t* stage) {
+                                            uint64_t w, const uint8_t* sq, uint32_t* stage) {
   const uint32_t lane = threadIdx.x;
   const uint64_t blk = w * 64 + lane;
   const bool active = blk < g.nblocks;
@@ -747,12 +748,12 @@ __device__ __forceinline__ bool decode_wave(const Geo& g, const uint8_t* const* 
       LBits<kStageWords> r;
       r.init(stage, (uint32_t)(start - s0 + (off >> 5)), (uint32_t)(stop - s0));
       r.skip((uint32_t)(off & 31));
-      ok = decode_block_add<T>(r, minexp[i], acc, pw, sq) && !r.bad();
+      ok = decode_block_add<T>(r, minexp[i], acc, sq) && !r.bad();
     } else {
       GBits r;
       r.init(payload, (uint32_t)(start + (off >> 5)), (uint32_t)stop);
       r.skip((uint32_t)(off & 31));
-      ok = decode_block_add<T>(r, minexp[i], acc, pw, sq) && !r.bad();
+      ok = decode_block_add<T>(r, minexp[i], acc, sq) && !r.bad();
     }
   }
   if (active && ok) store_block(out, g, bp, acc);
@@ -760,13 +761,11 @@ __device__ __forceinline__ bool decode_wave(const Geo& g, const uint8_t* const* 
 }
 
 template <class T, bool kStaged>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1))) void k_decode(DecArgs<T> a) {
-  __shared__ uint32_t s_planes[32 * 64];
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_decode(DecArgs<T> a) {
   __shared__ uint8_t s_squeeze[256];
   __shared__ uint32_t s_stage[kStaged ? kStageWords : 1];
   squeeze_table(s_squeeze);
-  uint32_t* pw = s_planes + threadIdx.x;
-  if (!decode_wave<T, kStaged>(a.g, a.s, a.aux, a.words, a.minexp, a.ncomp, a.in, a.out, blockIdx.x, pw, s_squeeze,
+  if (!decode_wave<T, kStaged>(a.g, a.s, a.aux, a.words, a.minexp, a.ncomp, a.in, a.out, blockIdx.x, s_squeeze,
                                s_stage))
     atomicOr(a.status, 1u);
 }
@@ -774,12 +773,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
 // many retrieval queries in one launch: wave w belongs to the query q with
 // wave_prefix[q] <= w < wave_prefix[q + 1]
 template <class T, bool kStaged>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1))) void k_decode_queries(ServeArgs a) {
-  __shared__ uint32_t s_planes[32 * 64];
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_decode_queries(ServeArgs a) {
   __shared__ uint8_t s_squeeze[256];
   __shared__ uint32_t s_stage[kStaged ? kStageWords : 1];
   squeeze_table(s_squeeze);
-  uint32_t* pw = s_planes + threadIdx.x;
   const uint32_t w = blockIdx.x;
   uint32_t lo = 0, hi = a.nq;  // largest q with wave_prefix[q] <= w
   while (hi - lo > 1) {
@@ -789,7 +786,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
   }
   const QueryDev& q = a.q[lo];
   if (!decode_wave<T, kStaged>(q.g, q.s, q.aux, q.words, q.minexp, q.ncomp, reinterpret_cast<const T*>(q.in),
-                               reinterpret_cast<T*>(q.out), w - a.wave_prefix[lo], pw, s_squeeze, s_stage))
+                               reinterpret_cast<T*>(q.out), w - a.wave_prefix[lo], s_squeeze, s_stage))
     atomicOr(a.status, 1u);
 }
 
@@ -1019,6 +1016,7 @@ template <class T> hipError_t launch_pack(const PackArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_pack<T>, dim3((uint32_t)wgs), dim3(64), 0, s, a);
   return hipGetLastError();
 }
+uint64_t stage_words() { return kStageWords; }
 template <class T> hipError_t launch_decode(const DecArgs<T>& a, uint64_t max_span, hipStream_t s) {
   const uint64_t wgs = (a.g.nblocks + 63) / 64;
   if (max_span <= kStageWords) hipLaunchKernelGGL((k_decode<T, true>), dim3((uint32_t)wgs), dim3(64), 0, s, a);

@@ -175,6 +175,7 @@ template <class T> hipError_t launch_aux(const AuxArgs& a, hipStream_t s);
 template <class T> hipError_t launch_decode_queries(const ServeArgs& a, uint64_t max_span, hipStream_t s);
 template <class T> hipError_t launch_pack(const PackArgs& a, hipStream_t s);
 template <class T> hipError_t launch_decode(const DecArgs<T>& a, uint64_t max_span, hipStream_t s);
+uint64_t stage_words();  // capacity of the decoder's LDS staging buffer, in words
 template <class T> hipError_t launch_range(const T* x, uint64_t n, unsigned long long* out, hipStream_t s);
 hipError_t launch_fill64(unsigned long long* p, uint64_t n, unsigned long long v, hipStream_t s);
 
