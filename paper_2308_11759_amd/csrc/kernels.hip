@@ -707,7 +707,7 @@ __device__ __forceinline__ bool decode_wave(const Geo& g, const uint8_t* const* 
   const uint64_t chunk = blk / kChunkBlocks;
   T acc[64];
   if (in && active) {
-    load_block(in, g, bp, acc);
+    load_block(in, g, opaque_pos(bp), acc);
   } else {
 #pragma unroll
     for (int l = 0; l < 64; ++l) acc[l] = (T)0;
@@ -756,7 +756,8 @@ __device__ __forceinline__ bool decode_wave(const Geo& g, const uint8_t* const* 
       ok = decode_block_add<T>(r, minexp[i], acc, sq) && !r.bad();
     }
   }
-  if (active && ok) store_block(out, g, bp, acc);
+  // the block position is recomputed here rather than kept in registers
+  if (active && ok) store_block(out, g, block_pos(g, opaque(w) * 64 + lane), acc);
   return ok || !active;
 }
 
