@@ -241,26 +241,72 @@ struct LdsBits {
   }
 };
 
-// emit one plane with the group-testing coder, n = significant prefix
-__device__ __forceinline__ void plane_emit(LdsBits& w, uint64_t wd, uint32_t& n) {
-  if (n > 0) w.put64(n == 64 ? wd : (wd & ((1ull << n) - 1ull)), n);
-  if (n < 64) {
-    uint64_t rest = wd >> n;
-    while (rest != 0) {
-      uint32_t z = (uint32_t)__builtin_ctzll(rest);
-      uint32_t j = n + z;
-      if (j == 63) {  // the one at the last position is implied
-        w.put64(1ull, z + 1);
-        n = 64;
-        rest = 0;
-      } else {
-        w.put64(1ull | (1ull << (z + 1)), z + 2);
-        n = j + 1;
-        rest >>= (z + 1);
-      }
-    }
-    if (n < 64) w.put(0, 1);
+// unsqueeze, the inverse of squeeze: every set bit of m, at position k and
+// i-th from the bottom (i >= 1), moves to k + i (128-bit result lo | hi<<64).
+// Applied to the newly significant coefficients of a plane this gives the
+// positions of the run terminators in its group-test section.  The table
+// holds each byte's own unsqueeze (16 bits); the bytes are joined with
+// shifts given by the number of set bits below them.
+__device__ __forceinline__ uint32_t unsqueeze_byte(uint32_t b) {
+  uint32_t r = 0, i = 0;
+  for (uint32_t k = 0; k < 8; ++k)
+    if ((b >> k) & 1u) r |= 1u << (k + ++i);
+  return r;
+}
+__device__ __forceinline__ void unsqueeze_table(uint16_t* tab) {
+  for (uint32_t b = threadIdx.x; b < 256; b += blockDim.x) tab[b] = (uint16_t)unsqueeze_byte(b);
+  __syncthreads();
+}
+__device__ __forceinline__ void unsqueeze64(uint64_t m, const uint16_t* tab, uint64_t& lo, uint64_t& hi) {
+  lo = 0;
+  hi = 0;
+  uint32_t c = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const uint32_t b = (uint32_t)(m >> (8 * k)) & 0xFFu;
+    const uint64_t v = tab[b];
+    const uint32_t sh = 8u * (uint32_t)k + c;  // < 120
+    lo |= sh < 64u ? v << sh : 0ull;
+    hi |= sh >= 64u ? v << (sh - 64u) : (sh > 48u ? v >> (64u - sh) : 0ull);
+    c += (uint32_t)__builtin_popcount(b);
   }
+}
+
+// emit one plane with the group-testing coder, n = significant prefix: the
+// n verbatim bits, then the whole group-test section at once.  In the section
+// the i-th newly significant coefficient, at k past the prefix, puts its
+// terminator at bit k + i (unsqueeze); every terminator but the last is
+// followed by a positive test, bit 0 is the first test, and a negative test
+// ends the section.  When the last significant coefficient is coefficient 63
+// its terminator is implied and the section ends just before it.
+__device__ __forceinline__ void plane_emit(LdsBits& w, uint64_t wd, uint32_t& n, const uint16_t* tab) {
+  if (n > 0) w.put64(n == 64 ? wd : (wd & ((1ull << n) - 1ull)), n);
+  if (n >= 64) return;
+  const uint64_t rest = wd >> n;
+  if (rest == 0) {  // a single negative test
+    w.put(0, 1);
+    return;
+  }
+  const uint32_t top = 63u - (uint32_t)__builtin_clzll(rest);  // last new coefficient, past the prefix
+  const uint32_t lastt = top + (uint32_t)__builtin_popcountll(rest);  // its terminator's bit
+  uint64_t tlo, thi;
+  unsqueeze64(rest, tab, tlo, thi);
+  // positive tests: bit 0 and the bit after every terminator but the last
+  uint64_t slo = tlo | (tlo << 1) | 1ull, shi = thi | (thi << 1) | (tlo >> 63);
+  const bool implied = n + top == 63u;
+  // no positive test follows the last terminator (a negative test does,
+  // unless the terminator is implied: then it is dropped as well)
+  const uint32_t a = lastt + 1u;
+  if (a < 64u) slo &= ~(1ull << a);
+  else shi &= ~(1ull << (a - 64u));
+  if (implied) {
+    if (lastt < 64u) slo &= ~(1ull << lastt);
+    else shi &= ~(1ull << (lastt - 64u));
+  }
+  const uint32_t len = implied ? lastt : lastt + 2u;
+  w.put64(slo, len < 64u ? len : 64u);
+  if (len > 64u) w.put64(shi, len - 64u);
+  n += top + 1u;
 }
 
 // ---------------------------------------------------------------------------
@@ -703,13 +749,14 @@ __device__ __forceinline__ uint32_t planes_cost(const typename FT<T>::U u[64], i
 }
 
 template <class T>
-__device__ __forceinline__ void planes_emit(LdsBits& w, const typename FT<T>::U u[64], int p, uint32_t* pw) {
+__device__ __forceinline__ void planes_emit(LdsBits& w, const typename FT<T>::U u[64], int p, uint32_t* pw,
+                                            const uint16_t* tab) {
   constexpr int P = FT<T>::P;
   uint32_t n = 0;
   for (int g = 0; 16 * g < p; ++g) {
     group_to_lds(u, P - 16 * (g + 1), pw);
     const int tmax = p - 16 * g < 16 ? p - 16 * g : 16;
-    for (int t = 0; t < tmax; ++t) plane_emit(w, lds_plane(pw, t), n);
+    for (int t = 0; t < tmax; ++t) plane_emit(w, lds_plane(pw, t), n, tab);
   }
 }
 

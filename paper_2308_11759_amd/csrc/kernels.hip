@@ -243,7 +243,7 @@ __device__ __forceinline__ void load_block_lds(const T* __restrict__ f, const Ge
 // one wave = 64 consecutive blocks = 4 chunks; `wave` numbers these groups
 // within the field.  s_x: 64 * 64 values of LDS owned by this wave.
 template <class T>
-__device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T* s_x) {
+__device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T* s_x, const uint16_t* unsq) {
   typedef typename FT<T>::U U;
   constexpr int P = FT<T>::P;
   constexpr int CAP = chunk_cap_words<T>();
@@ -484,7 +484,7 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
         for (int t = 0; t < delta; ++t) w.put(1, 1);
         w.put(0, 1);
         w.put((uint64_t)(emax + FT<T>::BIAS), (uint32_t)FT<T>::EBITS);
-        planes_emit<T>(w, u, p, pw);
+        planes_emit<T>(w, u, p, pw, unsq);
       }
       w.flush();
     }
@@ -510,7 +510,9 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
 template <class T>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1))) void k_encode(EncArgs<T> a) {
   __shared__ T s_x[64 * 64];
-  encode_wave<T>(a, blockIdx.x, s_x);
+  __shared__ uint16_t s_unsq[256];
+  unsqueeze_table(s_unsq);
+  encode_wave<T>(a, blockIdx.x, s_x, s_unsq);
 }
 
 // ---------------------------------------------------------------------------
@@ -876,10 +878,12 @@ template <class T> __device__ __forceinline__ EncArgs<T> field_enc_args(const Fi
 template <class T>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1))) void k_encode_batch(BatchArgs b) {
   __shared__ T s_x[64 * 64];
+  __shared__ uint16_t s_unsq[256];
+  unsqueeze_table(s_unsq);
   for (uint32_t it = blockIdx.x; it < b.nitems; it += gridDim.x) {
     const Item w = b.items[it];
     const FieldDev* f = b.fields + w.field;
-    if (b.comp < f->ncomp) encode_wave<T>(field_enc_args<T>(*f, b.comp), w.index, s_x);
+    if (b.comp < f->ncomp) encode_wave<T>(field_enc_args<T>(*f, b.comp), w.index, s_x, s_unsq);
     __syncthreads();  // the next item reuses s_x
   }
 }
