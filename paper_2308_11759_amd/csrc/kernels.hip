@@ -597,19 +597,17 @@ __global__ __launch_bounds__(64) void k_pack(PackArgs a) {
   uint32_t* index = reinterpret_cast<uint32_t*>(base + kHeaderBytes);
   uint32_t* payload = index + a.nchunks;
   const uint32_t lane = threadIdx.x;
-  const uint64_t chunk = (uint64_t)blockIdx.x * 4 + (lane >> 4);
-  const uint32_t sub = lane & 15;
   uint32_t span = 0;  // words of this wave's four chunks (one decode wave)
-  if (chunk < a.nchunks) {
+  for (int c = 0; c < 4; ++c) {  // each chunk copied by the whole wave
+    const uint64_t chunk = (uint64_t)blockIdx.x * 4 + c;
+    if (chunk >= a.nchunks) break;
     const uint32_t words = a.chunk_words[chunk];
     const uint32_t o = a.offsets[chunk];
     const uint32_t* src = a.staging + chunk * (uint64_t)CAP;
-    for (uint32_t i = sub; i < words; i += 16) payload[o + i] = src[i];
-    if (sub == 0) index[chunk] = o;
-    span = sub == 0 ? words : 0u;
+    for (uint32_t i = lane; i < words; i += 64) payload[o + i] = src[i];
+    if (lane == 0) index[chunk] = o;
+    span += words;
   }
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) span += __shfl_xor(span, d, 64);
   // most waves see a maximum already recorded: read before the atomic
   if (lane == 0 && span > *(volatile unsigned long long*)&a.meta[a.comp].max_span)
     atomicMax(&a.meta[a.comp].max_span, (unsigned long long)span);
@@ -822,30 +820,81 @@ __device__ __forceinline__ unsigned long long ordered(double v) {
   return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
 }
 
+// min / max over the finite samples and the count of the others.  Keys are
+// the samples' bits mapped to unsigned integers of the same order (sign and
+// zero sign included), so the reduction is exact integer min / max in the
+// field's own width; the per-wave result is widened to the double key of the
+// same value for the device-wide atomics.  16-byte loads when aligned.
+template <class T> struct RangeKey;
+template <> struct RangeKey<float> {
+  typedef uint32_t K;
+  static __device__ __forceinline__ K key(float v) {
+    const uint32_t b = __float_as_uint(v);
+    return (b >> 31) ? ~b : (b | 0x80000000u);
+  }
+  static __device__ __forceinline__ bool finite(float v) { return (__float_as_uint(v) & 0x7F800000u) != 0x7F800000u; }
+  static __device__ __forceinline__ double value(K k) {
+    return (double)__uint_as_float((k >> 31) ? (k & 0x7FFFFFFFu) : ~k);
+  }
+};
+template <> struct RangeKey<double> {
+  typedef unsigned long long K;
+  static __device__ __forceinline__ K key(double v) { return ordered(v); }
+  static __device__ __forceinline__ bool finite(double v) {
+    return ((unsigned long long)__double_as_longlong(v) & 0x7FF0000000000000ull) != 0x7FF0000000000000ull;
+  }
+  static __device__ __forceinline__ double value(K k) {
+    return __longlong_as_double((long long)((k >> 63) ? (k & 0x7FFFFFFFFFFFFFFFull) : ~k));
+  }
+};
+
 template <class T>
 __global__ __launch_bounds__(256) void k_range(const T* __restrict__ x, uint64_t n, unsigned long long* out) {
-  unsigned long long lo = ~0ull, hi = 0ull, bad = 0ull;
-  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
-    double v = (double)x[i];
-    if (!isfinite(v)) {
-      ++bad;
-      continue;
+  typedef RangeKey<T> RK;
+  typedef typename RK::K K;
+  K lo = ~(K)0, hi = 0;
+  uint32_t bad = 0;
+  auto take = [&](T v) {
+    const K k = RK::key(v);
+    const bool fin = RK::finite(v);
+    lo = fin && k < lo ? k : lo;
+    hi = fin && k > hi ? k : hi;
+    bad += fin ? 0u : 1u;
+  };
+  const uint64_t tid = (uint64_t)blockIdx.x * 256 + threadIdx.x, stride = (uint64_t)gridDim.x * 256;
+  constexpr uint64_t V = 16 / sizeof(T);  // samples per 16-byte load
+  uint64_t done = 0;
+  if (((uintptr_t)x & 15) == 0) {
+    const uint64_t nv = n / V;
+    for (uint64_t i = tid; i < nv; i += stride) {
+      if constexpr (sizeof(T) == 4) {
+        const float4 v = reinterpret_cast<const float4*>(x)[i];
+        take(v.x);
+        take(v.y);
+        take(v.z);
+        take(v.w);
+      } else {
+        const double2 v = reinterpret_cast<const double2*>(x)[i];
+        take(v.x);
+        take(v.y);
+      }
     }
-    unsigned long long o = ordered(v);
-    lo = o < lo ? o : lo;
-    hi = o > hi ? o : hi;
+    done = nv * V;
   }
+  for (uint64_t i = done + tid; i < n; i += stride) take(x[i]);
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) {
-    unsigned long long a = __shfl_xor(lo, d, 64), b = __shfl_xor(hi, d, 64), c = __shfl_xor(bad, d, 64);
+    const K a = __shfl_xor(lo, d, 64), b = __shfl_xor(hi, d, 64);
     lo = a < lo ? a : lo;
     hi = b > hi ? b : hi;
-    bad += c;
+    bad += __shfl_xor(bad, d, 64);
   }
   if ((threadIdx.x & 63) == 0) {
-    atomicMin(&out[0], lo);
-    atomicMax(&out[1], hi);
-    if (bad) atomicAdd(&out[2], bad);
+    if (lo != ~(K)0) {  // this wave saw a finite sample
+      atomicMin(&out[0], ordered(RK::value(lo)));
+      atomicMax(&out[1], ordered(RK::value(hi)));
+    }
+    if (bad) atomicAdd(&out[2], (unsigned long long)bad);
   }
 }
 
@@ -960,19 +1009,17 @@ __global__ __launch_bounds__(64) void k_bpack(BatchArgs b) {
   uint32_t* index = reinterpret_cast<uint32_t*>(base + kHeaderBytes);
   uint32_t* payload = index + f.g.nchunks;
   const uint32_t lane = threadIdx.x;
-  const uint64_t chunk = (uint64_t)q.index * 4 + (lane >> 4);
-  const uint32_t sub = lane & 15;
   uint32_t span = 0;  // words of this wave's four chunks (one decode wave)
-  if (chunk < f.g.nchunks) {
+  for (int c = 0; c < 4; ++c) {  // each chunk copied by the whole wave
+    const uint64_t chunk = (uint64_t)q.index * 4 + c;
+    if (chunk >= f.g.nchunks) break;
     const uint32_t words = f.chunk_words[chunk];
     const uint32_t o = f.offsets[chunk];
     const uint32_t* src = f.staging + chunk * cap;
-    for (uint32_t i = sub; i < words; i += 16) payload[o + i] = src[i];
-    if (sub == 0) index[chunk] = o;
-    span = sub == 0 ? words : 0u;
+    for (uint32_t i = lane; i < words; i += 64) payload[o + i] = src[i];
+    if (lane == 0) index[chunk] = o;
+    span += words;
   }
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) span += __shfl_xor(span, d, 64);
   if (lane == 0 && span > *(volatile unsigned long long*)&f.meta0[b.comp].max_span)
     atomicMax(&f.meta0[b.comp].max_span, (unsigned long long)span);
   if (q.index == 0 && lane < 16) {
