@@ -254,7 +254,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="bulk_512_f32", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-planes", type=int, default=8, help="z-planes of the oracle sample (0 = skip)")
+    ap.add_argument("--cpu-planes", type=int, default=16, help="z-planes of the oracle sample (0 = skip)")
     ap.add_argument("--literal", action="store_true", help="one decode pass per component (literal Alg. 2)")
     ap.add_argument("--fields", type=int, default=256, help="batched workload: number of fields")
     ap.add_argument("--queries", type=int, default=2000, help="served workload: queries per arrival rate")
