@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "codec_device.hpp"
 #include "launch.hpp"
 
@@ -865,20 +867,29 @@ __global__ __launch_bounds__(256) void k_range(const T* __restrict__ x, uint64_t
   constexpr uint64_t V = 16 / sizeof(T);  // samples per 16-byte load
   uint64_t done = 0;
   if (((uintptr_t)x & 15) == 0) {
-    const uint64_t nv = n / V;
-    for (uint64_t i = tid; i < nv; i += stride) {
+    typedef typename std::conditional<sizeof(T) == 4, float4, double2>::type V16;
+    const V16* xv = reinterpret_cast<const V16*>(x);
+    auto take16 = [&](const V16& v) {
       if constexpr (sizeof(T) == 4) {
-        const float4 v = reinterpret_cast<const float4*>(x)[i];
         take(v.x);
         take(v.y);
         take(v.z);
         take(v.w);
       } else {
-        const double2 v = reinterpret_cast<const double2*>(x)[i];
         take(v.x);
         take(v.y);
       }
+    };
+    const uint64_t nv = n / V;
+    uint64_t i = tid;
+    for (; i + 3 * stride < nv; i += 4 * stride) {  // four 16-byte loads in flight
+      const V16 a0 = xv[i], a1 = xv[i + stride], a2 = xv[i + 2 * stride], a3 = xv[i + 3 * stride];
+      take16(a0);
+      take16(a1);
+      take16(a2);
+      take16(a3);
     }
+    for (; i < nv; i += stride) take16(xv[i]);
     done = nv * V;
   }
   for (uint64_t i = done + tid; i < n; i += stride) take(x[i]);
