@@ -124,7 +124,7 @@ pmc_store* store_from_meta(const pmc_field* f, const Geo& g, int n, const double
     s->aux_offset.push_back(i * auxb);
     s->words.push_back(hm[i].payload_words);
     s->nempty.push_back(hm[i].nempty);
-    s->ncoded.push_back(hm[i].ncoded);
+    s->ncoded.push_back(g.nblocks - hm[i].nempty - hm[i].nraw);  // the encoder counts the others only
     s->nraw.push_back(hm[i].nraw);
     s->nesc.push_back(hm[i].nesc);
     s->nmiss.push_back(hm[i].nmiss);

@@ -407,8 +407,10 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
 
   // per-component statistics
   {
+    // every counter lives on one cache line, so the usual wave issues no
+    // atomic at all: coded blocks are counted on the host as the remainder,
+    // and the error maximum is only raised when this wave's exceeds it
     const unsigned long long be = __ballot(active && mode == MODE_EMPTY);
-    const unsigned long long bc = __ballot(active && mode == MODE_CODED);
     const unsigned long long br = __ballot(active && mode == MODE_RAW);
     const unsigned long long bs = __ballot(active && mode == MODE_CODED && delta > 0);
     const unsigned long long bm = __ballot(miss);
@@ -417,12 +419,12 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
     const double wm = wave_max(err);
     if (lane == 0) {
       if (be) atomicAdd(&a.meta->nempty, (unsigned long long)__popcll(be));
-      if (bc) atomicAdd(&a.meta->ncoded, (unsigned long long)__popcll(bc));
       if (br) atomicAdd(&a.meta->nraw, (unsigned long long)__popcll(br));
       if (bs) atomicAdd(&a.meta->nesc, (unsigned long long)__popcll(bs));
       if (bm) atomicAdd(&a.meta->nmiss, (unsigned long long)__popcll(bm));
       if (bn) atomicOr(&a.meta->flags, (unsigned int)FLAG_NONFINITE);
-      atomicMax(&a.meta->linf_bits, (unsigned long long)__double_as_longlong(wm));
+      const unsigned long long wb = (unsigned long long)__double_as_longlong(wm);
+      if (wb > *(volatile unsigned long long*)&a.meta->linf_bits) atomicMax(&a.meta->linf_bits, wb);
     }
   }
 
@@ -900,10 +902,27 @@ __global__ __launch_bounds__(256) void k_range(const T* __restrict__ x, uint64_t
     hi = b > hi ? b : hi;
     bad += __shfl_xor(bad, d, 64);
   }
+  // the workgroup's four waves, then one set of atomics per workgroup (each
+  // skipped when the device-wide value is already at least as extreme)
+  __shared__ K s_lo[4], s_hi[4];
+  __shared__ uint32_t s_bad[4];
+  const uint32_t wv = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
-    if (lo != ~(K)0) {  // this wave saw a finite sample
-      atomicMin(&out[0], ordered(RK::value(lo)));
-      atomicMax(&out[1], ordered(RK::value(hi)));
+    s_lo[wv] = lo;
+    s_hi[wv] = hi;
+    s_bad[wv] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < 4; ++k) {
+      lo = s_lo[k] < lo ? s_lo[k] : lo;
+      hi = s_hi[k] > hi ? s_hi[k] : hi;
+      bad += s_bad[k];
+    }
+    if (lo != ~(K)0) {  // this workgroup saw a finite sample
+      const unsigned long long ol = ordered(RK::value(lo)), oh = ordered(RK::value(hi));
+      if (ol < *(volatile unsigned long long*)&out[0]) atomicMin(&out[0], ol);
+      if (oh > *(volatile unsigned long long*)&out[1]) atomicMax(&out[1], oh);
     }
     if (bad) atomicAdd(&out[2], (unsigned long long)bad);
   }
@@ -1099,7 +1118,7 @@ template <class T> hipError_t launch_aux(const AuxArgs& a, hipStream_t s) {
 }
 template <class T> hipError_t launch_range(const T* x, uint64_t n, unsigned long long* out, hipStream_t s) {
   uint64_t wgs = (n + 255) / 256;
-  if (wgs > 4096) wgs = 4096;
+  if (wgs > 2048) wgs = 2048;
   if (wgs == 0) wgs = 1;
   hipLaunchKernelGGL(k_range<T>, dim3((uint32_t)wgs), dim3(256), 0, s, x, n, out);
   return hipGetLastError();

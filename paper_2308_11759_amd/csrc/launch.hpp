@@ -30,7 +30,7 @@ struct Geo {
 // per-component results kept on the device during compression
 struct CompMeta {
   unsigned long long linf_bits;  // max measured error, float64 bits (>= 0)
-  unsigned long long nempty, ncoded, nraw, nesc, nmiss;
+  unsigned long long nempty, ncoded, nraw, nesc, nmiss;  // ncoded: not counted on the device
   unsigned long long payload_words;
   unsigned long long stream_offset;  // byte offset of the stream in the output
   unsigned long long stream_bytes;
