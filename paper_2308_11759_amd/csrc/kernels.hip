@@ -694,7 +694,7 @@ __device__ __forceinline__ bool decode_block_add(R& r, int minexp, T acc[64], co
 // that 12 one-wave workgroups fit a CU's LDS); spans larger than this use
 // the global-memory reader (the host picks the variant from the largest span
 // of the streams it decodes)
-constexpr uint32_t kStageWords = 3328;
+constexpr uint32_t kStageWords = 3326;
 
 // decode the wave's 64 blocks [64 w, 64 w + 64) of a field: x~ = in (or +0)
 // plus components [0, ncomp) of the given streams, left to right.  Every lane
@@ -768,7 +768,7 @@ __device__ __forceinline__ bool decode_wave(const Geo& g, const uint8_t* const* 
 template <class T, bool kStaged>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_decode(DecArgs<T> a) {
   __shared__ uint8_t s_squeeze[256];
-  __shared__ uint32_t s_stage[kStaged ? kStageWords : 1];
+  __shared__ uint32_t s_stage[kStaged ? kStageWords + 3 : 1];
   squeeze_table(s_squeeze);
   if (!decode_wave<T, kStaged>(a.g, a.s, a.aux, a.words, a.minexp, a.ncomp, a.in, a.out, blockIdx.x, s_squeeze,
                                s_stage))
@@ -780,7 +780,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
 template <class T, bool kStaged>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_decode_queries(ServeArgs a) {
   __shared__ uint8_t s_squeeze[256];
-  __shared__ uint32_t s_stage[kStaged ? kStageWords : 1];
+  __shared__ uint32_t s_stage[kStaged ? kStageWords + 3 : 1];
   squeeze_table(s_squeeze);
   const uint32_t w = blockIdx.x;
   uint32_t lo = 0, hi = a.nq;  // largest q with wave_prefix[q] <= w
