@@ -144,13 +144,26 @@ template <class S> __device__ __forceinline__ void xform_inv(S q[64]) {
 // ---------------------------------------------------------------------------
 // 32x32 bit-matrix transpose in registers: afterwards A[r] bit c equals the
 // old A[c] bit r.  Recursive block swap with strides 16, 8, 4, 2, 1.
+// one butterfly stage: for each pair (a, b) = (A[k], A[k+J]) with bit J of k
+// clear, b takes the M-bits of a >> J and a the (M << J)-bits of b << J.
+// The 16- and 8-bit stages move whole bytes (one v_perm each); the others
+// exchange the masked bits through one xor-difference.
 template <int J, uint32_t M> __device__ __forceinline__ void tstage(uint32_t A[32]) {
 #pragma unroll
   for (int k = 0; k < 32; ++k) {
     if (k & J) continue;
-    uint32_t t = ((A[k] >> J) ^ A[k + J]) & M;
-    A[k + J] ^= t;
-    A[k] ^= t << J;
+    const uint32_t a = A[k], b = A[k + J];
+    if constexpr (J == 16) {
+      A[k] = __builtin_amdgcn_perm(b, a, 0x05040100u);      // a.lo16 | b.lo16 << 16
+      A[k + J] = __builtin_amdgcn_perm(b, a, 0x07060302u);  // a.hi16 | b.hi16 << 16
+    } else if constexpr (J == 8) {
+      A[k] = __builtin_amdgcn_perm(b, a, 0x06020400u);      // a0 b0 a2 b2
+      A[k + J] = __builtin_amdgcn_perm(b, a, 0x07030501u);  // a1 b1 a3 b3
+    } else {
+      const uint32_t t = ((a >> J) ^ b) & M;
+      A[k + J] = b ^ t;
+      A[k] = a ^ (t << J);
+    }
   }
 }
 __device__ __forceinline__ void transpose32(uint32_t A[32]) {
@@ -669,28 +682,36 @@ template <class T> __device__ __forceinline__ void inverse_x(typename FT<T>::S q
 #pragma unroll
   for (int r = 0; r < 16; ++r) lift_inv(q[4 * r], q[4 * r + 1], q[4 * r + 2], q[4 * r + 3]);
 }
-// While every nonzero q * 2^(emax-30) is a normal float (emax >= -96), the
-// int -> float conversion performs the one rounding and the power-of-two
-// scale is exact, so the result equals dequantize() without double precision.
-__device__ __forceinline__ void dequantize_block(const int32_t q[64], int emax, float d[64]) {
-  if (emax >= -96) {
-    const float scale = __uint_as_float((uint32_t)(emax - 30 + 127) << 23);
-#pragma unroll
-    for (int l = 0; l < 64; ++l) d[l] = (float)q[l] * scale;
-  } else {
-#pragma unroll
-    for (int l = 0; l < 64; ++l) d[l] = dequantize(q[l], emax);
-  }
+// While every nonzero q * 2^(emax-30) is a normal float (emax >= -96) and no
+// product overflows (emax <= 126), the int -> float conversion performs the
+// one rounding and the power-of-two scale is exact, so the product equals
+// dequantize() without double precision, and acc + product equals one fused
+// multiply-add of the converted integer (the product being exact).
+__device__ __forceinline__ bool fast_dequant(int emax) { return emax >= -96 && emax <= 126; }
+__device__ __forceinline__ float dequant_scale(int emax) {
+  return __uint_as_float((uint32_t)(emax - 30 + 127) << 23);
 }
-__device__ __forceinline__ void dequantize_block(const int64_t q[64], int emax, double d[64]) {
+// dv[l] * scale is the dequantised value, exactly (scale = 1 on the double route)
+__device__ __forceinline__ float dequantize_block(const int32_t q[64], int emax, float dv[64]) {
+  if (fast_dequant(emax)) {
 #pragma unroll
-  for (int l = 0; l < 64; ++l) d[l] = dequantize(q[l], emax);
+    for (int l = 0; l < 64; ++l) dv[l] = (float)q[l];
+    return dequant_scale(emax);
+  }
+#pragma unroll
+  for (int l = 0; l < 64; ++l) dv[l] = dequantize(q[l], emax);
+  return 1.0f;
+}
+__device__ __forceinline__ double dequantize_block(const int64_t q[64], int emax, double dv[64]) {
+#pragma unroll
+  for (int l = 0; l < 64; ++l) dv[l] = dequantize(q[l], emax);
+  return 1.0;
 }
 __device__ __forceinline__ void dequant_add(const int32_t q[64], int emax, float acc[64]) {
-  if (emax >= -96) {
-    const float scale = __uint_as_float((uint32_t)(emax - 30 + 127) << 23);
+  if (fast_dequant(emax)) {
+    const float scale = dequant_scale(emax);
 #pragma unroll
-    for (int l = 0; l < 64; ++l) acc[l] = acc[l] + (float)q[l] * scale;
+    for (int l = 0; l < 64; ++l) acc[l] = __builtin_fmaf((float)q[l], scale, acc[l]);
   } else {
 #pragma unroll
     for (int l = 0; l < 64; ++l) acc[l] = acc[l] + dequantize(q[l], emax);

@@ -187,6 +187,11 @@ __device__ __forceinline__ BlockPos opaque_pos(BlockPos b) {
   return b;
 }
 
+// a + v * scale where v * scale is exact: one fused multiply-add equals the
+// plain sum of the (exact) product
+__device__ __forceinline__ float fma_exact(float v, float scale, float a) { return __builtin_fmaf(v, scale, a); }
+__device__ __forceinline__ double fma_exact(double v, double scale, double a) { return a + v * scale; }
+
 // NaN-propagating max, matching "take a if not a <= m"
 __device__ __forceinline__ double nmax(double m, double a) { return a <= m ? m : a; }
 
@@ -330,8 +335,8 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
         typename FT<T>::S q[64];
         inverse_zy<T>(u, q);
         inverse_x<T>(q);
-        T d[64];
-        dequantize_block(q, emax, d);
+        T dv[64];
+        const T scale = dequantize_block(q, emax, dv);
         double ea = 0.0;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
@@ -340,7 +345,7 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
             const int l = 4 * r + t;
-            row[t] = tr[t] + d[l];  // x~_{i-1} + x_i in the field precision
+            row[t] = fma_exact(dv[l], scale, tr[t]);  // x~_{i-1} + x_i in the field precision
             ea = nmax(ea, masked_abs(vmask, l, (double)XL.at(l) - (double)row[t]));
           }
           if (!a.last) store_row(a.xt_out, a.g, bq, r, row);
