@@ -155,6 +155,14 @@ def test_staged_and_global_decoders(ctx):
     assert np.array_equal(ctx.retrieve(again, 2).cpu().numpy(), recon[1])
 
 
+def test_staged_and_global_decoders_f64(ctx):
+    """The same two decoder paths for a float64 field (white noise to 2^-30)."""
+    rng = np.random.default_rng(22)
+    x = rng.uniform(-1.0, 1.0, size=(8, 16, 64))
+    store, comps, meta, recon = check_against_oracle(ctx, x, [2.0 ** -2, 2.0 ** -30], "spans64")
+    assert [c["staged"] for c in store.info] == [True, False]
+
+
 def test_decode_oracle_streams(ctx):
     """The GPU decoder reproduces the oracle's Alg. 2 on streams the oracle wrote."""
     x = inputs.spectral_field((17, 20, 33), seed=8, dtype=np.float64)

@@ -130,3 +130,41 @@ def test_caller_outputs_and_unreachable(served):
         srv.submit(fids[0], taus[0][-1] * 0.5)
     assert ei.value.status == pmc.E_UNREACHABLE
     srv.close()
+
+
+def test_queries_with_wide_spans(served):
+    """Queries whose streams exceed the decoder's LDS staging span (white
+    noise to 2^-28) run the global-reader kernel, alone and mixed with
+    ordinary fields; every result equals the isolated retrieval."""
+    import torch
+    from paper_2308_11759_amd import pmc
+    ctx, xs, stores, taus, refs = served
+    rng = np.random.default_rng(23)
+    x = rng.uniform(-1.0, 1.0, size=(16, 16, 64)).astype(np.float32)
+    t = [2.0 ** -2, 2.0 ** -28]
+    st = ctx.compress(torch.from_numpy(x).to("cuda:0"), t)
+    assert [c["staged"] for c in st.info] == [True, False]
+    ref = [ctx.retrieve(st, k).cpu().numpy() for k in (1, 2)]
+    comps, _ = driver.compress(x, t)
+    assert np.array_equal(ref[1], driver.reconstruct(comps, 2, x.shape, x.dtype))
+    srv = pmc.Server(ctx, arena_bytes=128 << 20, max_batch=8)
+    wide = srv.add(st)
+    narrow = srv.add(stores[0])
+    tickets = []
+    for q in range(24):
+        if q % 3 == 2:
+            k = 1 + q % 6
+            tickets.append((srv.submit(narrow, taus[0][k - 1]), "narrow", k))
+        else:
+            k = 1 + q % 2
+            tickets.append((srv.submit(wide, t[k - 1]), "wide", k))
+    wait_all(srv, [tk for tk, _, _ in tickets])
+    for tk, which, k in tickets:
+        done, status, lat = srv.poll(tk)
+        assert done and status == pmc.OK
+        view, kk, src = srv.result(tk, wide if which == "wide" else narrow)
+        assert kk == k
+        want = ref[k - 1] if which == "wide" else refs[0][k - 1]
+        assert np.array_equal(view.cpu().numpy(), want), (tk, which, k, src)
+        srv.release(tk)
+    srv.close()
