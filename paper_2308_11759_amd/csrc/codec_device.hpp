@@ -98,11 +98,11 @@ template <class S> __device__ __forceinline__ void lift_inv(S& a, S& b, S& c, S&
   S t1 = wadd(q3, half(w));
   S t0 = wsub(wdbl(w), t1);
   S s1 = wadd(q2, dc);
-  S s0 = wsub(wdbl(dc), s1);
+  S s0 = wsub(dc, q2);
   a = wadd(t0, s0);
-  d = wsub(wdbl(s0), a);
+  d = wsub(s0, t0);
   b = wadd(t1, s1);
-  c = wsub(wdbl(s1), b);
+  c = wsub(s1, t1);
 }
 
 // separable forward transform on local index l = lx + 4 ly + 16 lz
@@ -373,6 +373,7 @@ struct GBits {
     }
     return get(count);
   }
+  __device__ __forceinline__ uint64_t get64nz(uint32_t count) { return get64(count); }  // 1 <= count <= 64
   __device__ __forceinline__ void skip(uint32_t count) {  // count <= 32
     refill();
     drop(count);
@@ -432,6 +433,11 @@ template <uint32_t CAPW> struct LBits {
     const uint64_t v = peek64();
     skip(count);
     return count >= 64 ? v : v & ((1ull << count) - 1ull);
+  }
+  __device__ __forceinline__ uint64_t get64nz(uint32_t count) {  // 1 <= count <= 64: a shift pair masks
+    const uint64_t v = peek64();
+    skip(count);
+    return (v << (64u - count)) >> (64u - count);
   }
   __device__ __forceinline__ uint64_t consumed(uint32_t from) const { return (uint64_t)(p - from) * 32 + o; }
   __device__ __forceinline__ bool bad() const { return (uint64_t)p * 32 + o > (uint64_t)end * 32; }
@@ -538,7 +544,7 @@ __device__ __forceinline__ uint32_t squeeze32(uint32_t m, const uint8_t* tab) {
 template <class R>
 __device__ __forceinline__ uint64_t plane_read(R& r, uint32_t& n, const uint8_t* sq) {
   uint64_t wd = 0;
-  if (n > 0) wd = r.get64(n);
+  if (n > 0) wd = r.get64nz(n);  // the n verbatim bits
   uint32_t vg = 0;
   while (n < 64) {
     const uint32_t s = (r.peek32() << vg) | vg;
@@ -563,7 +569,10 @@ __device__ __forceinline__ uint64_t plane_read(R& r, uint32_t& n, const uint8_t*
     const bool run = !neg && !tokens;
     const bool implied = run && z <= 31u - g;
     const bool done = neg || implied || (tokens && ends != 0u);
-    const uint32_t c = neg ? 1u : tokens ? (ends != 0u ? g + 1u : g) : implied ? g + 1u + z : 32u;
+    const uint32_t c_tok = g + (ends != 0u ? 1u : 0u);
+    const uint32_t c_run = implied ? g + 1u + z : 32u;
+    const uint32_t c_any = tokens ? c_tok : c_run;
+    const uint32_t c = neg ? 1u : c_any;
     r.skip(c - vg);
     wd |= implied ? (1ull << 63) : 0ull;
     n = implied ? 64u : run ? n + 31u - g : n;
@@ -653,10 +662,11 @@ __device__ __forceinline__ void forward_coeffs(const T e[64], int emax, typename
 // coefficients truncated to p planes -> decoded block values (in d[l])
 // the inverse split so that its last (x) pass can run one block row at a time:
 // coefficients -> integers after the z and y passes ...
+// (from coded-order integers c, already out of negabinary)
 template <class T>
-__device__ __forceinline__ void inverse_zy(const typename FT<T>::U u[64], typename FT<T>::S q[64]) {
+__device__ __forceinline__ void inverse_zy_ints(const typename FT<T>::S c[64], typename FT<T>::S q[64]) {
 #pragma unroll
-  for (int r = 0; r < 64; ++r) q[kOrder.at[r]] = from_nb<T>(u[r]);
+  for (int r = 0; r < 64; ++r) q[kOrder.at[r]] = c[r];
 #pragma unroll
   for (int l = 0; l < 16; ++l) {
     const int b = l;
@@ -667,6 +677,13 @@ __device__ __forceinline__ void inverse_zy(const typename FT<T>::U u[64], typena
     const int b = 16 * (l >> 2) + (l & 3);
     lift_inv(q[b], q[b + 4], q[b + 8], q[b + 12]);
   }
+}
+template <class T>
+__device__ __forceinline__ void inverse_zy(const typename FT<T>::U u[64], typename FT<T>::S q[64]) {
+  typename FT<T>::S c[64];
+#pragma unroll
+  for (int r = 0; r < 64; ++r) c[r] = from_nb<T>(u[r]);
+  inverse_zy_ints<T>(c, q);
 }
 // ... then row r (ly = r & 3, lz = r >> 2): x pass and dequantisation
 template <class T>
@@ -783,39 +800,47 @@ __device__ __forceinline__ void planes_emit(LdsBits& w, const typename FT<T>::U 
   }
 }
 
-// read p planes from the top into u (zero below)
+// read p planes from the top and return the coefficients in coded order as
+// two's complement integers (negabinary decoded; planes below p are zero)
 template <class T, class R>
-__device__ __forceinline__ void planes_read(R& r, typename FT<T>::U u[64], int p, const uint8_t* sq) {
+__device__ __forceinline__ void planes_read(R& r, typename FT<T>::S c[64], int p, const uint8_t* sq) {
   typedef typename FT<T>::U U;
+  typedef typename FT<T>::S S;
   constexpr int P = FT<T>::P;
   uint32_t n = 0;
   // the top 16 planes straight into registers (the plane loop is unrolled so
   // every plane word has a fixed register), then one transpose
-  {
-    uint32_t Tw[32];
+  uint32_t Tw[32];
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      uint64_t wd = 0;
-      if (t < p) wd = plane_read(r, n, sq);
-      Tw[15 - t] = (uint32_t)wd;
-      Tw[31 - t] = (uint32_t)(wd >> 32);
-    }
-    transpose32(Tw);  // back to 16-bit slices of coefficients j and j+32
-#pragma unroll
-    for (int j = 0; j < 32; ++j) {
-      u[j] = (U)(Tw[j] & 0xFFFFu) << (P - 16);
-      u[j + 32] = (U)(Tw[j] >> 16) << (P - 16);
-    }
+  for (int t = 0; t < 16; ++t) {
+    uint64_t wd = 0;
+    if (t < p) wd = plane_read(r, n, sq);
+    Tw[15 - t] = (uint32_t)wd;
+    Tw[31 - t] = (uint32_t)(wd >> 32);
   }
-  // deeper planes (rare): each plane's bits are deposited directly
+  transpose32(Tw);  // back to 16-bit slices of coefficients j and j+32
+  // A coefficient with only its top 16 bits X set (X << s, s = P - 16, even)
+  // has the value ((X ^ 0xAAAA) - 0xAAAA) << s: the negabinary mask's lower
+  // bits cancel.  One xor serves both slices of a word.
+  constexpr U kOff = (U)0xAAAAu << (P - 16);
+#pragma unroll
+  for (int j = 0; j < 32; ++j) {
+    const uint32_t x = Tw[j] ^ 0xAAAAAAAAu;
+    c[j] = (S)(((U)(x & 0xFFFFu) << (P - 16)) - kOff);
+    c[j + 32] = (S)(((U)(x >> 16) << (P - 16)) - kOff);
+  }
+  // deeper planes (rare): a plane bit at an even position b adds 2^b to the
+  // two's complement value, one at an odd position subtracts it (the
+  // negabinary weight of bit b is (-2)^b)
   for (int t = 16; t < p; ++t) {
     const uint64_t wd = plane_read(r, n, sq);
     const uint32_t lo = (uint32_t)wd, hi = (uint32_t)(wd >> 32);
     const int b = P - 1 - t;
+    const U m = (b & 1) ? ~(U)0 : (U)0;  // negate odd positions: (v ^ m) - m
 #pragma unroll
     for (int j = 0; j < 32; ++j) {
-      u[j] |= (U)((lo >> j) & 1u) << b;
-      u[j + 32] |= (U)((hi >> j) & 1u) << b;
+      c[j] = (S)((U)c[j] + ((((U)((lo >> j) & 1u) << b) ^ m) - m));
+      c[j + 32] = (S)((U)c[j + 32] + ((((U)((hi >> j) & 1u) << b) ^ m) - m));
     }
   }
 }

@@ -686,10 +686,9 @@ __device__ __forceinline__ bool decode_block_add(R& r, int minexp, T acc[64], co
   int p = emax - minexp + kGuard;
   p = (p < 0 ? 0 : (p > P ? P : p)) + delta;
   if (emax < 2 - FT<T>::BIAS || p < 1 || p > P) return false;
-  U u[64];
-  planes_read<T>(r, u, p, sq);
-  typename FT<T>::S q[64];
-  inverse_zy<T>(u, q);
+  typename FT<T>::S c[64], q[64];
+  planes_read<T>(r, c, p, sq);
+  inverse_zy_ints<T>(c, q);
   inverse_x<T>(q);
   dequant_add(q, emax, acc);
   return true;
