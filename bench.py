@@ -256,6 +256,8 @@ def main():
     ap.add_argument("--workload", default="bulk_512_f32", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-planes", type=int, default=16, help="z-planes of the oracle sample (0 = skip)")
     ap.add_argument("--literal", action="store_true", help="one decode pass per component (literal Alg. 2)")
+    ap.add_argument("--refine-reps", type=int, default=3,
+                    help="repetitions of the incremental refine chain k = 1..n timed after the steps (0 = skip)")
     ap.add_argument("--fields", type=int, default=256, help="batched workload: number of fields")
     ap.add_argument("--queries", type=int, default=2000, help="served workload: queries per arrival rate")
     ap.add_argument("--rates", default="200,500,1000,2000", help="served workload: arrival rates (QPS)")
@@ -358,12 +360,31 @@ def main():
     traffic = load_traffic(dom, args.workload)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "traffic_gbs": traffic / 1e9 / (dk["avg_launch_ms"] / 1e3) if traffic else None,
+                "traffic_frac": traffic / 1e9 / (dk["avg_launch_ms"] / 1e3) / HBM_PEAK_GBS if traffic else None,
                 "algorithmic_bytes_per_launch": algo[dom] / launches, "avg_launch_ms": dk["avg_launch_ms"]}
 
     comp_ms = sum(kern.get(k, {}).get("ms_per_step", 0.0) for k in
                   ("k_encode_" + tname, "k_scan", "k_pack_" + tname))
     dec_ms = kern.get("k_decode_" + tname, {}).get("ms_per_step", 0.0)
     value = N * s * (1 + n) / (ms_step / 1e3) / 1e9
+
+    # incremental refine (Alg. 2 continued from x~_{k-1}): one component per
+    # call, k = 1..n, reported beside the from-scratch retrievals of the step
+    refine_ms = None
+    if args.steps > 0 and args.refine_reps > 0:
+        ev2, ev3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = args.refine_reps
+        ev2.record()
+        for _ in range(reps):
+            ctx.retrieve(store, 1, out=out)
+            for k in range(2, n + 1):
+                ctx.refine(store, k - 1, k, out)
+        ev3.record()
+        torch.cuda.synchronize()
+        refine_ms = ev2.elapsed_time(ev3) / reps
+        err = float((xd.double() - out.double()).abs().max())
+        assert err == store.info[n - 1]["linf"], (err, store.info[n - 1]["linf"])
 
     if args.copy_calibration:
         src = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
@@ -396,6 +417,8 @@ def main():
                    "decode": "literal" if args.literal else "fused", "step": "range + compress + retrieve k=1..n"},
         "compress_gbs": N * s / (comp_ms / 1e3) / 1e9 if comp_ms else None,
         "retrieve_all_k_gbs": N * s * n / (dec_ms / 1e3) / 1e9 if dec_ms else None,
+        "refine_chain_gbs": N * s * n / (refine_ms / 1e3) / 1e9 if refine_ms else None,
+        "refine_chain_ms": refine_ms,
         "rates_bits_per_value": [round(8.0 * m["bytes"] / N, 3) for m in info],
         "linf": [m["linf"] for m in info],
         "kernels": kern,

@@ -299,6 +299,23 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
   uint32_t nbits = 1;
   double err = eb;
 
+  // the residual's coefficients: computed once, they serve every candidate
+  // plane count and the emission
+  U u[64];
+  if (active && maxabs != 0) {
+    const T* const tin = a.first ? nullptr : a.xt_in;
+    const BlockPos bq = opaque_pos(bp);
+    T e[64];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      T tr[4];
+      load_row(tin, a.g, bq, r, tr);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) e[4 * r + t] = X.at(4 * r + t) - tr[t];
+    }
+    forward_coeffs<T>(e, emax, u);
+  }
+
   // acceptance: smallest plane count p >= p0 whose block meets tau without
   // raising the error; else empty (already within tau) or raw
   if (active && maxabs != 0) {
@@ -308,18 +325,6 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
       const XLds<T> XL{opaque(s_x), lane};
       const T* const tin = a.first ? nullptr : a.xt_in;
       const BlockPos bq = opaque_pos(bp);  // row addresses are recomputed, not held
-      U u[64];
-      {
-        T e[64];
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          T tr[4];
-          load_row(tin, a.g, bq, r, tr);
-#pragma unroll
-          for (int t = 0; t < 4; ++t) e[4 * r + t] = XL.at(4 * r + t) - tr[t];
-        }
-        forward_coeffs<T>(e, emax, u);
-      }
       bool feasible = false;
       uint32_t cb = 0;
       if (p >= 1 && p <= P) {
@@ -328,12 +333,12 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
       }
       if (feasible) {
         const U m = plane_mask<U>(P, p);
-#pragma unroll
-        for (int r = 0; r < 64; ++r) u[r] &= m;
         // decode, add and check one row at a time; x~_i rows are stored as
         // they come (a rejected candidate is overwritten below)
-        typename FT<T>::S q[64];
-        inverse_zy<T>(u, q);
+        typename FT<T>::S c[64], q[64];
+#pragma unroll
+        for (int r = 0; r < 64; ++r) c[r] = from_nb<T>(u[r] & m);  // the top p planes
+        inverse_zy_ints<T>(c, q);
         inverse_x<T>(q);
         T dv[64];
         const T scale = dequantize_block(q, emax, dv);
@@ -431,22 +436,6 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
       const unsigned long long wb = (unsigned long long)__double_as_longlong(wm);
       if (wb > *(volatile unsigned long long*)&a.meta->linf_bits) atomicMax(&a.meta->linf_bits, wb);
     }
-  }
-
-  // what the block emits: coefficients (coded) or the residual's bits (raw)
-  U u[64];
-  if (mode == MODE_CODED) {
-    const T* const tin = a.first ? nullptr : a.xt_in;
-    const BlockPos bq = opaque_pos(bp);
-    T e[64];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      T tr[4];
-      load_row(tin, a.g, bq, r, tr);
-#pragma unroll
-      for (int t = 0; t < 4; ++t) e[4 * r + t] = X.at(4 * r + t) - tr[t];
-    }
-    forward_coeffs<T>(e, emax, u);
   }
 
   __syncthreads();  // every lane is done with x: its LDS is reused below
