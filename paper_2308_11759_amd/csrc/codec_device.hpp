@@ -808,13 +808,19 @@ __device__ __forceinline__ void planes_read(R& r, typename FT<T>::S c[64], int p
   typedef typename FT<T>::S S;
   constexpr int P = FT<T>::P;
   uint32_t n = 0;
+  // Leading empty planes: until a coefficient is significant, a plane
+  // without a new one is a single 0 (its negative group test), so the first
+  // zeros of the block's plane data are that many empty planes, skipped at once.
+  const int z0 = (int)__builtin_ctz(r.peek32() | 0x80000000u);
+  const int zlead = z0 < p ? z0 : p;
+  r.skip((uint32_t)zlead);
   // the top 16 planes straight into registers (the plane loop is unrolled so
   // every plane word has a fixed register), then one transpose
   uint32_t Tw[32];
 #pragma unroll
   for (int t = 0; t < 16; ++t) {
     uint64_t wd = 0;
-    if (t < p) wd = plane_read(r, n, sq);
+    if (t >= zlead && t < p) wd = plane_read(r, n, sq);
     Tw[15 - t] = (uint32_t)wd;
     Tw[31 - t] = (uint32_t)(wd >> 32);
   }
@@ -832,7 +838,7 @@ __device__ __forceinline__ void planes_read(R& r, typename FT<T>::S c[64], int p
   // deeper planes (rare): a plane bit at an even position b adds 2^b to the
   // two's complement value, one at an odd position subtracts it (the
   // negabinary weight of bit b is (-2)^b)
-  for (int t = 16; t < p; ++t) {
+  for (int t = zlead > 16 ? zlead : 16; t < p; ++t) {
     const uint64_t wd = plane_read(r, n, sq);
     const uint32_t lo = (uint32_t)wd, hi = (uint32_t)(wd >> 32);
     const int b = P - 1 - t;
