@@ -791,12 +791,22 @@ __device__ __forceinline__ uint32_t planes_cost(const typename FT<T>::U u[64], i
 template <class T>
 __device__ __forceinline__ void planes_emit(LdsBits& w, const typename FT<T>::U u[64], int p, uint32_t* pw,
                                             const uint16_t* tab) {
+  typedef typename FT<T>::U U;
   constexpr int P = FT<T>::P;
+  // leading empty planes (no coefficient significant yet) are one 0 bit each:
+  // the writer only advances over them, and groups made of them are skipped
+  U any = 0;
+#pragma unroll
+  for (int l = 0; l < 64; ++l) any |= u[l];
+  int zl = any ? (sizeof(U) == 4 ? __builtin_clz((uint32_t)any) : __builtin_clzll((uint64_t)any)) : P;
+  zl = zl < p ? zl : p;
+  w.put64(0, (uint32_t)zl);
   uint32_t n = 0;
-  for (int g = 0; 16 * g < p; ++g) {
+  for (int g = zl / 16; 16 * g < p; ++g) {
     group_to_lds(u, P - 16 * (g + 1), pw);
     const int tmax = p - 16 * g < 16 ? p - 16 * g : 16;
-    for (int t = 0; t < tmax; ++t) plane_emit(w, lds_plane(pw, t), n, tab);
+    for (int t = 0; t < tmax; ++t)
+      if (16 * g + t >= zl) plane_emit(w, lds_plane(pw, t), n, tab);
   }
 }
 
