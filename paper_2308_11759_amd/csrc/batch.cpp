@@ -30,7 +30,7 @@ struct pmc_batch {
   std::vector<std::vector<double>> tau;
   std::vector<std::vector<int>> minexp;
   // workspace layout (byte offsets into d_ws)
-  std::vector<uint64_t> off_xt0, off_xt1, off_staging, off_cw, off_offs, off_tiles;
+  std::vector<uint64_t> off_xt0, off_xt1, off_staging, off_cw, off_offs, off_tiles, off_berr;
   std::vector<uint64_t> meta_first;  // index of the field's first CompMeta
   uint64_t off_table = 0, off_items = 0, off_meta = 0, ws_total = 0;
   // stream regions (byte offsets into d_streams)
@@ -202,6 +202,8 @@ pmc_status pmc_batch_plan(pmc_ctx* ctx, int nf, const pmc_field* fields, const i
     ws += align256(g.nchunks * 4);
     b->off_tiles.push_back(ws);
     ws += align256((g.nchunks + kScanTile - 1) / kScanTile * 8);
+    b->off_berr.push_back(ws);  // per-block error carried between components
+    if (n[i] > 1) ws += align256(g.nblocks * 8);
     b->meta_first.push_back(nmeta);
     nmeta += n[i];
     b->region_off.push_back(reg);
@@ -307,6 +309,7 @@ static pmc_status batch_launch(pmc_batch* b, const void* const* d_x, uint8_t* ws
     d.chunk_words = (uint32_t*)(ws + b->off_cw[i]);
     d.offsets = (uint32_t*)(ws + b->off_offs[i]);
     d.tile_sums = (unsigned long long*)(ws + b->off_tiles[i]);
+    d.berr = (double*)(ws + b->off_berr[i]);
     d.region = streams + b->region_off[i];
     d.aux0 = (uint32_t*)d.region;
     d.aux_stride = aux_bytes(b->g[i]) / 4;

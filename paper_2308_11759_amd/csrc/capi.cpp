@@ -69,7 +69,7 @@ int floor_log2(double tau) {
 }
 
 struct WsLayout {
-  uint64_t xt[2], staging, chunk_words, offsets, tile_sums, meta, total;
+  uint64_t xt[2], staging, chunk_words, offsets, tile_sums, meta, berr, total;
 };
 
 // x~ is double-buffered: component i reads x~_{i-1} from xt[(i-1) & 1] and
@@ -92,6 +92,8 @@ WsLayout ws_layout(const pmc_field* f, const Geo& g, int n) {
   o += align256((g.nchunks + kScanTile - 1) / kScanTile * 8);
   w.meta = o;
   o += align256((uint64_t)n * sizeof(CompMeta));
+  w.berr = o;  // per-block error carried from one component to the next
+  if (n > 1) o += align256(g.nblocks * 8);
   w.total = o;
   return w;
 }
@@ -320,6 +322,7 @@ pmc_status pmc_compress(pmc_ctx* ctx, const pmc_field* f, const void* d_x, int n
       a.chunk_words = (uint32_t*)(ws + w.chunk_words);
       a.aux = (uint32_t*)((uint8_t*)d_streams + i * auxb);
       a.meta = meta + i;
+      a.berr = (double*)(ws + w.berr);
       {
         ProfScope ps(ctx, "k_encode_f32");
         e = launch_encode<float>(a, ctx->stream);
@@ -349,6 +352,7 @@ pmc_status pmc_compress(pmc_ctx* ctx, const pmc_field* f, const void* d_x, int n
       a.chunk_words = (uint32_t*)(ws + w.chunk_words);
       a.aux = (uint32_t*)((uint8_t*)d_streams + i * auxb);
       a.meta = meta + i;
+      a.berr = (double*)(ws + w.berr);
       {
         ProfScope ps(ctx, "k_encode_f64");
         e = launch_encode<double>(a, ctx->stream);

@@ -272,49 +272,52 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
   bp = opaque_pos(bp);
   const uint64_t vmask = valid_mask(bp);
 
-  // residual statistics: exponent, all-zero test, error before this component.
-  // x~_{i-1} is re-read row by row wherever it is needed (it stays in the
-  // caches), so it never occupies 64 registers.
+  // one pass over the rows: the residual e = x - x~_{i-1} (kept in registers
+  // for the transform), its largest magnitude (the block exponent, the
+  // all-zero test) and the largest |x| (non-finite input)
   U maxabs = 0, xmax = 0;  // largest |residual| and |x| bit patterns
-  double eb = 0.0;
-#pragma unroll 4
-  for (int r = 0; r < 16; ++r) {
-    T tr[4];
-    load_row(a.first ? nullptr : a.xt_in, a.g, bp, r, tr);
+  U u[64];                 // the residual's coefficients: every candidate and the emission use them
+  int emax;
+  {
+    const T* const tin = a.first ? nullptr : a.xt_in;
+    T e[64];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int l = 4 * r + t;
-      const T xl = X.at(l);
-      U ab = abs_bits((T)(xl - tr[t]));
-      maxabs = ab > maxabs ? ab : maxabs;
-      eb = nmax(eb, masked_abs(vmask, l, (double)xl - (double)tr[t]));
-      const U xb = abs_bits(xl);
-      xmax = xb > xmax ? xb : xmax;
+    for (int r = 0; r < 16; ++r) {
+      T tr[4];
+      load_row(tin, a.g, bp, r, tr);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int l = 4 * r + t;
+        const T xl = X.at(l);
+        e[l] = xl - tr[t];
+        const U ab = abs_bits(e[l]);
+        maxabs = ab > maxabs ? ab : maxabs;
+        const U xb = abs_bits(xl);
+        xmax = xb > xmax ? xb : xmax;
+      }
     }
+    emax = block_emax<T>(maxabs);
+    if (active && maxabs != 0) forward_coeffs<T>(e, emax, u);
   }
-  const int emax = block_emax<T>(maxabs);
+  // the error before this component, max |x - x~_{i-1}| in double over the
+  // block's samples: the previous component left it per block; for the first
+  // (x~_0 = 0) it is the largest |x| (edge samples repeat valid ones) unless a
+  // NaN makes the running maximum order-dependent, then it is taken sample by
+  // sample as everywhere else
+  double eb = 0.0;
+  if (!a.first) {
+    if (active) eb = a.berr[blk];
+  } else if (xmax <= abs_bits((T)__builtin_inf())) {
+    eb = (double)from_raw(xmax, (T)0);
+  } else {
+#pragma unroll 4
+    for (int l = 0; l < 64; ++l) eb = nmax(eb, masked_abs(vmask, l, (double)X.at(l) - 0.0));
+  }
   int p = emax - a.minexp + kGuard;
   p = p < 0 ? 0 : (p > P ? P : p);
   int mode = MODE_EMPTY, delta = 0;
   uint32_t nbits = 1;
   double err = eb;
-
-  // the residual's coefficients: computed once, they serve every candidate
-  // plane count and the emission
-  U u[64];
-  if (active && maxabs != 0) {
-    const T* const tin = a.first ? nullptr : a.xt_in;
-    const BlockPos bq = opaque_pos(bp);
-    T e[64];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      T tr[4];
-      load_row(tin, a.g, bq, r, tr);
-#pragma unroll
-      for (int t = 0; t < 4; ++t) e[4 * r + t] = X.at(4 * r + t) - tr[t];
-    }
-    forward_coeffs<T>(e, emax, u);
-  }
 
   // acceptance: smallest plane count p >= p0 whose block meets tau without
   // raising the error; else empty (already within tau) or raw
@@ -414,6 +417,7 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
     miss = false;
     nbits = 0;
   }
+  if (active && !a.last) a.berr[blk] = err;  // the next component's error before coding
 
   // per-component statistics
   {
@@ -944,6 +948,7 @@ template <class T> __device__ __forceinline__ EncArgs<T> field_enc_args(const Fi
   a.chunk_words = f.chunk_words;
   a.aux = f.aux0 + (uint64_t)comp * f.aux_stride;
   a.meta = f.meta0 + comp;
+  a.berr = f.berr;
   return a;
 }
 

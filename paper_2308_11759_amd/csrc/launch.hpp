@@ -54,6 +54,7 @@ template <class T> struct EncArgs {
   uint32_t* chunk_words;
   uint32_t* aux;   // per block: bit offset of the block inside its chunk
   CompMeta* meta;  // this component's entry
+  double* berr;    // per block: max error before this component (read unless first), after it (written unless last)
 };
 
 // chunk offsets are an exclusive scan of chunk word counts, done in tiles of
@@ -140,6 +141,7 @@ struct FieldDev {
   uint32_t* aux0;           // block index of component 0; component i at aux0 + i * aux_stride
   uint64_t aux_stride;      // in 32-bit words
   CompMeta* meta0;          // meta of component 0; component i at meta0 + i
+  double* berr;             // per-block error carried between components
   uint8_t* region;          // the field's stream region: block indexes, then streams
   unsigned long long region_cap;
   int ncomp;
