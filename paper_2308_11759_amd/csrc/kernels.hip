@@ -589,7 +589,44 @@ __global__ __launch_bounds__(1024) void k_tile_offsets(ScanArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// staging -> stream: header, index, payload (16 lanes per chunk)
+// copy the four chunks [c0, c0 + 4) from their staging slots (cap words
+// apart) into the payload.  They are consecutive in the payload (the offsets
+// are a prefix sum), so their words form one output range that all lanes copy
+// together, each word fetched from its chunk's slot.  Returns the range's
+// length in words (the chunks' decode-wave span).
+__device__ __forceinline__ uint32_t pack_quad(const uint32_t* __restrict__ staging, uint64_t cap,
+                                              const uint32_t* chunk_words, const uint32_t* offsets, uint64_t nchunks,
+                                              uint64_t c0, uint32_t* __restrict__ payload, uint32_t* index) {
+  const uint32_t lane = threadIdx.x;
+  uint32_t cum[5];
+  cum[0] = 0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) cum[c + 1] = cum[c] + (c0 + c < nchunks ? chunk_words[c0 + c] : 0u);
+  const uint32_t o0 = offsets[c0];
+  const uint32_t span = cum[4];
+  const uint32_t* __restrict__ src = staging + c0 * cap;
+  uint32_t* __restrict__ dst = payload + o0;
+  for (uint32_t j0 = 0; j0 < span; j0 += 256) {
+    uint32_t v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {  // four loads in flight per lane
+      const uint32_t j = j0 + 64 * k + lane;
+      const uint32_t c = (j >= cum[1] ? 1u : 0u) + (j >= cum[2] ? 1u : 0u) + (j >= cum[3] ? 1u : 0u);
+      const uint32_t start = c == 0 ? 0u : c == 1 ? cum[1] : c == 2 ? cum[2] : cum[3];
+      v[k] = j < span ? src[c * cap + (j - start)] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t j = j0 + 64 * k + lane;
+      if (j < span) dst[j] = v[k];
+    }
+  }
+  if (lane < 4 && c0 + lane < nchunks)
+    index[c0 + lane] = o0 + (lane == 0 ? 0u : lane == 1 ? cum[1] : lane == 2 ? cum[2] : cum[3]);
+  return span;
+}
+
+// staging -> stream: header, index, payload (one wave per four chunks)
 template <class T>
 __global__ __launch_bounds__(64) void k_pack(PackArgs a) {
   constexpr int CAP = chunk_cap_words<T>();
@@ -599,16 +636,12 @@ __global__ __launch_bounds__(64) void k_pack(PackArgs a) {
   uint32_t* index = reinterpret_cast<uint32_t*>(base + kHeaderBytes);
   uint32_t* payload = index + a.nchunks;
   const uint32_t lane = threadIdx.x;
-  uint32_t span = 0;  // words of this wave's four chunks (one decode wave)
-  for (int c = 0; c < 4; ++c) {  // each chunk copied by the whole wave
-    const uint64_t chunk = (uint64_t)blockIdx.x * 4 + c;
-    if (chunk >= a.nchunks) break;
-    const uint32_t words = a.chunk_words[chunk];
-    const uint32_t o = a.offsets[chunk];
-    const uint32_t* src = a.staging + chunk * (uint64_t)CAP;
-    for (uint32_t i = lane; i < words; i += 64) payload[o + i] = src[i];
-    if (lane == 0) index[chunk] = o;
-    span += words;
+  // a grid-stride loop over the chunk quads: few, longer-lived waves
+  const uint64_t nquads = (a.nchunks + 3) / 4;
+  uint32_t span = 0;
+  for (uint64_t q = blockIdx.x; q < nquads; q += gridDim.x) {
+    const uint32_t s = pack_quad(a.staging, CAP, a.chunk_words, a.offsets, a.nchunks, q * 4, payload, index);
+    span = s > span ? s : span;
   }
   // most waves see a maximum already recorded: read before the atomic
   if (lane == 0 && span > *(volatile unsigned long long*)&a.meta[a.comp].max_span)
@@ -1037,17 +1070,8 @@ __global__ __launch_bounds__(64) void k_bpack(BatchArgs b) {
   uint32_t* index = reinterpret_cast<uint32_t*>(base + kHeaderBytes);
   uint32_t* payload = index + f.g.nchunks;
   const uint32_t lane = threadIdx.x;
-  uint32_t span = 0;  // words of this wave's four chunks (one decode wave)
-  for (int c = 0; c < 4; ++c) {  // each chunk copied by the whole wave
-    const uint64_t chunk = (uint64_t)q.index * 4 + c;
-    if (chunk >= f.g.nchunks) break;
-    const uint32_t words = f.chunk_words[chunk];
-    const uint32_t o = f.offsets[chunk];
-    const uint32_t* src = f.staging + chunk * cap;
-    for (uint32_t i = lane; i < words; i += 64) payload[o + i] = src[i];
-    if (lane == 0) index[chunk] = o;
-    span += words;
-  }
+  const uint32_t span =
+      pack_quad(f.staging, cap, f.chunk_words, f.offsets, f.g.nchunks, (uint64_t)q.index * 4, payload, index);
   if (lane == 0 && span > *(volatile unsigned long long*)&f.meta0[b.comp].max_span)
     atomicMax(&f.meta0[b.comp].max_span, (unsigned long long)span);
   if (q.index == 0 && lane < 16) {
@@ -1092,7 +1116,8 @@ hipError_t launch_scan(const ScanArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 template <class T> hipError_t launch_pack(const PackArgs& a, hipStream_t s) {
-  const uint64_t wgs = (a.nchunks + 3) / 4;
+  const uint64_t quads = (a.nchunks + 3) / 4;
+  const uint64_t wgs = quads < 8192 ? quads : 8192;
   hipLaunchKernelGGL(k_pack<T>, dim3((uint32_t)wgs), dim3(64), 0, s, a);
   return hipGetLastError();
 }
