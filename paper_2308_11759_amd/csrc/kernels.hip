@@ -120,12 +120,15 @@ __device__ __forceinline__ void store_block(T* __restrict__ f, const Geo& g, con
   }
 }
 
-// store row r of a block (valid samples only)
+// store row r of a block (valid samples only); wfull: every lane of the wave
+// has a full block of aligned rows (a wave-uniform flag), so the store needs
+// no per-lane path
 template <class T>
-__device__ __forceinline__ void store_row(T* __restrict__ f, const Geo& g, const BlockPos& b, int r, const T v[4]) {
-  if ((uint32_t)(r & 3) >= b.vy || (uint32_t)(r >> 2) >= b.vz) return;
+__device__ __forceinline__ void store_row(T* __restrict__ f, const Geo& g, const BlockPos& b, int r, const T v[4],
+                                          bool wfull = false) {
+  if (!wfull && ((uint32_t)(r & 3) >= b.vy || (uint32_t)(r >> 2) >= b.vz)) return;
   T* row = const_cast<T*>(row_ptr((const T*)f, g, b, r));
-  if (b.vx == 4 && g.rows_aligned) {
+  if (wfull || (b.vx == 4 && g.rows_aligned)) {
     if constexpr (sizeof(T) == 4) {
       *reinterpret_cast<float4*>(row) = make_float4(v[0], v[1], v[2], v[3]);
     } else {
@@ -165,6 +168,37 @@ __device__ __forceinline__ void load_row(const T* f, const Geo& g, const BlockPo
     v[1] = row[min<uint32_t>(1, m)];
     v[2] = row[min<uint32_t>(2, m)];
     v[3] = row[min<uint32_t>(3, m)];
+  }
+}
+
+// rows [r0, r0 + R) of a block into v[4R].  When every lane of the wave has
+// aligned full rows (wvec, a wave-uniform flag) the R loads are plain 16-byte
+// loads with no per-lane branch, so they are all in flight together;
+// otherwise each row takes load_row's per-lane path.  A null field reads as +0.
+template <class T, int R>
+__device__ __forceinline__ void load_rows(const T* f, const Geo& g, const BlockPos& b, int r0, bool wvec,
+                                          T v[4 * R]) {
+  if (!f) {
+#pragma unroll
+    for (int k = 0; k < 4 * R; ++k) v[k] = (T)0;
+    return;
+  }
+  if (wvec) {
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const T* row = row_ptr(f, g, b, r0 + k);
+      if constexpr (sizeof(T) == 4) {
+        const float4 q = *reinterpret_cast<const float4*>(row);
+        v[4 * k] = q.x; v[4 * k + 1] = q.y; v[4 * k + 2] = q.z; v[4 * k + 3] = q.w;
+      } else {
+        const double2 q0 = *reinterpret_cast<const double2*>(row);
+        const double2 q1 = *reinterpret_cast<const double2*>(row + 2);
+        v[4 * k] = q0.x; v[4 * k + 1] = q0.y; v[4 * k + 2] = q1.x; v[4 * k + 3] = q1.y;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < R; ++k) load_row(f, g, b, r0 + k, v + 4 * k);
   }
 }
 
@@ -222,6 +256,8 @@ template <class T> struct XLds {
   __device__ __forceinline__ T at(int l) const { return *slot(l >> 2, l & 3); }
 };
 
+// (the direct loads are only issued here: the caller waits, s_waitcnt 0,
+// before reading s_x, and may issue other loads first)
 template <class T>
 __device__ __forceinline__ void load_block_lds(const T* __restrict__ f, const Geo& g, const BlockPos& b, T* s_x,
                                                uint32_t lane) {
@@ -244,7 +280,6 @@ __device__ __forceinline__ void load_block_lds(const T* __restrict__ f, const Ge
       for (int t = 0; t < 4; ++t) *X.slot(r, t) = row[min<uint32_t>(t, m)];
     }
   }
-  __builtin_amdgcn_s_waitcnt(0);  // direct loads and LDS writes complete
 }
 
 // one wave = 64 consecutive blocks = 4 chunks; `wave` numbers these groups
@@ -266,7 +301,14 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
   const bool active = blk < a.g.nblocks;
 
   BlockPos bp = block_pos(a.g, active ? blk : 0);
+  // every lane's rows are aligned full rows: row loads without per-lane paths
+  const bool wvec = __all(bp.vx == 4 && a.g.rows_aligned);
+  const bool wfull = __all(bp.vx == 4 && bp.vy == 4 && bp.vz == 4 && a.g.rows_aligned);  // and no partial rows
+  // x into LDS and x~_{i-1} into registers, all loads in flight together
   load_block_lds(a.x, a.g, bp, s_x, lane);
+  T e[64];
+  load_rows<T, 16>(a.first ? nullptr : a.xt_in, a.g, bp, 0, wvec, e);
+  __builtin_amdgcn_s_waitcnt(0);  // direct loads, LDS writes and the rows complete
   const XLds<T> X{s_x, lane};
   // row addresses are recomputed where used instead of kept in registers
   bp = opaque_pos(bp);
@@ -279,17 +321,13 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
   U u[64];                 // the residual's coefficients: every candidate and the emission use them
   int emax;
   {
-    const T* const tin = a.first ? nullptr : a.xt_in;
-    T e[64];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      T tr[4];
-      load_row(tin, a.g, bp, r, tr);
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int l = 4 * r + t;
         const T xl = X.at(l);
-        e[l] = xl - tr[t];
+        e[l] = xl - e[l];
         const U ab = abs_bits(e[l]);
         maxabs = ab > maxabs ? ab : maxabs;
         const U xb = abs_bits(xl);
@@ -347,16 +385,21 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
         const T scale = dequantize_block(q, emax, dv);
         double ea = 0.0;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          T row[4], tr[4];
-          load_row(tin, a.g, bq, r, tr);
+        for (int r0 = 0; r0 < 16; r0 += 4) {
+          T tr[16];
+          load_rows<T, 4>(tin, a.g, bq, r0, wvec, tr);  // four rows in flight
 #pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const int l = 4 * r + t;
-            row[t] = fma_exact(dv[l], scale, tr[t]);  // x~_{i-1} + x_i in the field precision
-            ea = nmax(ea, masked_abs(vmask, l, (double)XL.at(l) - (double)row[t]));
+          for (int k = 0; k < 4; ++k) {
+            const int r = r0 + k;
+            T row[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+              const int l = 4 * r + t;
+              row[t] = fma_exact(dv[l], scale, tr[4 * k + t]);  // x~_{i-1} + x_i in the field precision
+              ea = nmax(ea, masked_abs(vmask, l, (double)XL.at(l) - (double)row[t]));
+            }
+            if (!a.last) store_row(a.xt_out, a.g, bq, r, row, wfull);
           }
-          if (!a.last) store_row(a.xt_out, a.g, bq, r, row);
         }
         if (ea <= a.tau && ea <= eb) {
           mode = MODE_CODED;
