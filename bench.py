@@ -36,9 +36,12 @@ WORKLOADS = {
     "bulk_256_f64": ((256, 256, 256), np.float64, 2, 8, lambda i, r: 2.0 ** (-3 * i), 0.0),
     "small_64_f64": (None, np.float64, 0, 4, lambda i, r: r * 10.0 ** -i, 0.0),
     "largest_1024_f32": ((1024, 1024, 1024), np.float32, 3, 12, lambda i, r: 2.0 ** (-2 * i), 1e-4),
+    "largest_768_f64": ((768, 768, 768), np.float64, 4, 10, lambda i, r: 2.0 ** (-2 * i), 1e-4),
     "batched_256": None,
     "served_64": None,
 }
+TAU_TEXT = {"bulk_512_f32": "2^-3i", "bulk_256_f64": "2^-3i", "small_64_f64": "range*10^-i",
+            "largest_1024_f32": "2^-2i", "largest_768_f64": "2^-2i"}
 
 
 def make_field(name):
@@ -266,8 +269,8 @@ def main():
                     help="also run three 512 MiB device-to-device copies (scale for rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (the field would be split "
-              "into z-slabs, one per GPU; see DESIGN.md).", file=sys.stderr)
+        print("bench.py runs on one GPU only: there is no multi-GPU path (a field would be split into "
+              "z-slabs, one per GPU, with only the range and the stream sizes exchanged).", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "batched_256":
@@ -413,7 +416,7 @@ def main():
         "dtype": "f32" if dt == np.float32 else "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "shape": list(x.shape), "components": n,
-                   "tau": "2^-3i" if args.workload.startswith("bulk") else "see DESIGN.md",
+                   "tau": TAU_TEXT[args.workload],
                    "decode": "literal" if args.literal else "fused", "step": "range + compress + retrieve k=1..n"},
         "compress_gbs": N * s / (comp_ms / 1e3) / 1e9 if comp_ms else None,
         "retrieve_all_k_gbs": N * s * n / (dec_ms / 1e3) / 1e9 if dec_ms else None,
