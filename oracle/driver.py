@@ -59,13 +59,13 @@ def compress(x, taus, codec=None):
     for a, b in zip(taus, taus[1:]):
         if not a > b:
             raise ValueError("tolerances must be strictly decreasing")
-    xt = np.zeros_like(x)                       # line 1: x~ <- 0
+    xt = np.zeros_like(x)                       # x~ starts at zero
     comps, meta = [], []
-    for tau in taus:                            # line 2
-        e = x - xt                              # line 3 (field precision, RNE)
-        y, st = codec.encode(e, tau, x, xt)     # line 4
-        xi = codec.decode(y, x.shape, x.dtype)  # line 5
-        xt = xt + xi                            # line 6 (left-to-right sum)
+    for tau in taus:                            # one component per tolerance
+        e = x - xt                              # residual (field precision, RNE)
+        y, st = codec.encode(e, tau, x, xt)     # compress it under tau
+        xi = codec.decode(y, x.shape, x.dtype)  # decode the new component
+        xt = xt + xi                            # partial-sum update (left-to-right sum)
         m = dict(st)
         m["tau"] = tau
         m["linf"] = measured_error(x, xt)

@@ -247,7 +247,7 @@ def stream_cap(shape, dtype):
 
 
 def encode(e, x, xt, tau):
-    """y = C(e, tau) for one component; e = x - xt already computed (Alg. 1 line 3).
+    """y = C(e, tau) for one component; e = x - xt already computed (the residual step of Alg. 1).
 
     Returns (stream bytes as np.uint8 array, stats dict)."""
     assert e.dtype == x.dtype == xt.dtype and e.shape == x.shape == xt.shape
@@ -282,7 +282,7 @@ def stream_info(stream):
 
 
 def decode(stream, shape, dtype):
-    """x_i = D(y_i) as a dense field (Alg. 2 line 3).  Raises on a corrupt stream."""
+    """x_i = D(y_i) as a dense field (the decode step of Alg. 2).  Raises on a corrupt stream."""
     rc, out = decode_rc(stream, shape, dtype)
     if rc != OK:
         raise RuntimeError("oracle decode failed: %d" % rc)

@@ -613,7 +613,7 @@ uint64_t orc_stream_cap(const orc_field* f) {
 /*
  * Encode one component: y = C(e, tau) with the acceptance rule that needs
  * x and xt = x~_{i-1} (Alg. 1, Sec. 4.1; Eq. (1), Sec. 4.3).  e must be
- * x - xt computed in the field type by the caller (Alg. 1 line 3).
+ * x - xt computed in the field type by the caller (the residual step of Alg. 1).
  */
 int orc_encode(const orc_field* f, const void* e, const void* x, const void* xt, double tau,
                uint8_t* out, uint64_t cap, uint64_t* nbytes, orc_stats* st) {
@@ -702,7 +702,7 @@ int orc_stream_info(const uint8_t* s, uint64_t nbytes, orc_field* f, double* tau
   return ORC_OK;
 }
 
-/* x_i = D(y_i): decode a whole component into a dense field (Alg. 2 line 3) */
+/* x_i = D(y_i): decode a whole component into a dense field (the decode step of Alg. 2) */
 int orc_decode(const uint8_t* s, uint64_t nbytes, const orc_field* expect, void* out) {
   orc_field f;
   double tau;

@@ -1,9 +1,9 @@
 // kernels.hip -- HIP kernels of the multi-component codec for gfx950, and the
 // host-side launchers the C-ABI calls.
 //
-//  k_encode   one component of Alg. 1 (Sec. 4.1): residual (line 3), block
-//             coding (line 4), decode-for-verify (line 5), x~ update (line 6)
-//             and the measured error (Sec. 4.3); one lane per 4x4x4 block,
+//  k_encode   one component of Alg. 1 (Sec. 4.1): residual, block coding,
+//             decode-for-verify, the x~ update and the measured error
+//             (Sec. 4.3); one lane per 4x4x4 block,
 //             one wave per 4 chunks, chunk bitstreams assembled in LDS
 //  k_tile_*   chunk word counts -> chunk offsets and stream size
 //  k_pack     staging -> final stream (header, chunk index, payload)
