@@ -403,7 +403,7 @@ def main():
         cpu = cpu_baseline(x, taus, args.cpu_planes)
 
     rec = {
-        "metric": "compress/retrieve GB/s (512^3 f32, 8 comps)",
+        "metric": "compress/retrieve GB/s (%d^3 %s, %d comps)" % (x.shape[0], "f32" if dt == np.float32 else "f64", n),
         "value": value,
         "unit": "GB/s",
         "n_gpus": 1,
