@@ -72,6 +72,16 @@ __device__ __forceinline__ const T* row_ptr(const T* f, const Geo& g, const Bloc
   return f + b.x0 + g.nx * ((b.y0 + ly) + g.ny * (b.z0 + lz));
 }
 
+// A full block's rows start at block_base + row_step(r): the step depends only
+// on the field's shape, so it is the same for every lane (scalar registers)
+// and a lane keeps one address instead of one per row.
+template <class T> __device__ __forceinline__ T* block_base(T* f, const Geo& g, const BlockPos& b) {
+  return f + (b.x0 + g.nx * (b.y0 + g.ny * b.z0));
+}
+__device__ __forceinline__ uint64_t row_step(const Geo& g, int r) {
+  return g.nx * (uint64_t)(r & 3) + g.nx * g.ny * (uint64_t)(r >> 2);
+}
+
 template <class T>
 __device__ __forceinline__ void load_block(const T* __restrict__ f, const Geo& g, const BlockPos& b, T v[64]) {
   const bool vec = b.vx == 4 && g.rows_aligned;
@@ -127,7 +137,7 @@ template <class T>
 __device__ __forceinline__ void store_row(T* __restrict__ f, const Geo& g, const BlockPos& b, int r, const T v[4],
                                           bool wfull = false) {
   if (!wfull && ((uint32_t)(r & 3) >= b.vy || (uint32_t)(r >> 2) >= b.vz)) return;
-  T* row = const_cast<T*>(row_ptr((const T*)f, g, b, r));
+  T* row = wfull ? block_base(f, g, b) + row_step(g, r) : const_cast<T*>(row_ptr((const T*)f, g, b, r));
   if (wfull || (b.vx == 4 && g.rows_aligned)) {
     if constexpr (sizeof(T) == 4) {
       *reinterpret_cast<float4*>(row) = make_float4(v[0], v[1], v[2], v[3]);
@@ -171,22 +181,24 @@ __device__ __forceinline__ void load_row(const T* f, const Geo& g, const BlockPo
   }
 }
 
-// rows [r0, r0 + R) of a block into v[4R].  When every lane of the wave has
-// aligned full rows (wvec, a wave-uniform flag) the R loads are plain 16-byte
-// loads with no per-lane branch, so they are all in flight together;
-// otherwise each row takes load_row's per-lane path.  A null field reads as +0.
+// rows [r0, r0 + R) of a block into v[4R].  When every lane of the wave has a
+// full block of aligned rows (wfull, a wave-uniform flag) the R loads are
+// plain 16-byte loads at the block base plus a uniform step, with no per-lane
+// branch, so they are all in flight together; otherwise each row takes
+// load_row's per-lane path.  A null field reads as +0.
 template <class T, int R>
-__device__ __forceinline__ void load_rows(const T* f, const Geo& g, const BlockPos& b, int r0, bool wvec,
+__device__ __forceinline__ void load_rows(const T* f, const Geo& g, const BlockPos& b, int r0, bool wfull,
                                           T v[4 * R]) {
   if (!f) {
 #pragma unroll
     for (int k = 0; k < 4 * R; ++k) v[k] = (T)0;
     return;
   }
-  if (wvec) {
+  if (wfull) {
+    const T* const base = block_base(f, g, b);
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-      const T* row = row_ptr(f, g, b, r0 + k);
+      const T* row = base + row_step(g, r0 + k);
       if constexpr (sizeof(T) == 4) {
         const float4 q = *reinterpret_cast<const float4*>(row);
         v[4 * k] = q.x; v[4 * k + 1] = q.y; v[4 * k + 2] = q.z; v[4 * k + 3] = q.w;
@@ -301,13 +313,12 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
   const bool active = blk < a.g.nblocks;
 
   BlockPos bp = block_pos(a.g, active ? blk : 0);
-  // every lane's rows are aligned full rows: row loads without per-lane paths
-  const bool wvec = __all(bp.vx == 4 && a.g.rows_aligned);
-  const bool wfull = __all(bp.vx == 4 && bp.vy == 4 && bp.vz == 4 && a.g.rows_aligned);  // and no partial rows
+  // every lane has a full block of aligned rows: row accesses without per-lane paths
+  const bool wfull = __all(bp.vx == 4 && bp.vy == 4 && bp.vz == 4 && a.g.rows_aligned);
   // x into LDS and x~_{i-1} into registers, all loads in flight together
   load_block_lds(a.x, a.g, bp, s_x, lane);
   T e[64];
-  load_rows<T, 16>(a.first ? nullptr : a.xt_in, a.g, bp, 0, wvec, e);
+  load_rows<T, 16>(a.first ? nullptr : a.xt_in, a.g, bp, 0, wfull, e);
   __builtin_amdgcn_s_waitcnt(0);  // direct loads, LDS writes and the rows complete
   const XLds<T> X{s_x, lane};
   // row addresses are recomputed where used instead of kept in registers
@@ -387,7 +398,7 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
 #pragma unroll
         for (int r0 = 0; r0 < 16; r0 += 4) {
           T tr[16];
-          load_rows<T, 4>(tin, a.g, bq, r0, wvec, tr);  // four rows in flight
+          load_rows<T, 4>(tin, a.g, bq, r0, wfull, tr);  // four rows in flight
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
             const int r = r0 + k;
