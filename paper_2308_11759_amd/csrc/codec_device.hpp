@@ -395,23 +395,25 @@ struct GBits {
 // LDS bit reader over words staged in LDS (a wave's chunks): three words and
 // a bit offset; peeks are funnel shifts and every skip reloads the three
 // words at the new position, so there is no refill branch.  Words
-// [0, CAPW + 2) exist (the data fill at most CAPW); bits past `end` are
+// [0, capw + 3) exist (the data fill at most capw); bits past `end` are
 // unspecified and bad() reports any use of them.
-template <uint32_t CAPW> struct LBits {
+struct LBits {
   const uint32_t* s;
   uint32_t p, o, end;  // word of the next bit, its bit offset, end word
+  uint32_t capw;       // reads are clamped to words [0, capw + 3)
   uint32_t w0, w1, w2;
   __device__ __forceinline__ void load() {
-    const uint32_t q = p < CAPW ? p : CAPW;  // only a malformed stream runs past the data
+    const uint32_t q = p < capw ? p : capw;  // only a malformed stream runs past the data
     w0 = s[q];
     w1 = s[q + 1];
     w2 = s[q + 2];
   }
-  __device__ __forceinline__ void init(const uint32_t* st, uint32_t first, uint32_t e) {
+  __device__ __forceinline__ void init(const uint32_t* st, uint32_t first, uint32_t e, uint32_t cap) {
     s = st;
     p = first;
     o = 0;
     end = e;
+    capw = cap;
     load();
   }
   __device__ __forceinline__ uint32_t peek32() const { return __builtin_amdgcn_alignbit(w1, w0, o); }

@@ -779,6 +779,39 @@ __device__ __forceinline__ bool decode_block_add(R& r, int minexp, T acc[64], co
 // the global-memory reader (the host picks the variant from the largest span
 // of the streams it decodes)
 constexpr uint32_t kStageWords = 3326;
+// The staging buffer is double-buffered while spans are small: two halves of
+// kHalfWords data words (64-word multiples, since a copy writes whole 64-word
+// rows) plus 3 spare words each for the reader's look-ahead.  The next
+// component's words load into one half while the wave decodes from the other.
+// A component whose span exceeds a half uses the whole buffer and is staged
+// without overlap.
+constexpr uint32_t kHalfWords = 1600;
+constexpr uint32_t kHalf1 = kHalfWords + 3;  // word offset of the second half
+static_assert(kHalf1 + kHalfWords + 3 <= kStageWords + 3, "halves fit the buffer");
+
+// the wave's span of payload words of one component: its chunks [4w, 4w + 4)
+// are consecutive in the payload
+struct Span {
+  uint64_t s0, s1;
+  bool ok;
+};
+__device__ __forceinline__ Span wave_span(const uint32_t* index, uint64_t nchunks, uint64_t words, uint64_t w) {
+  const uint64_t c0 = w * 4, c1 = min<uint64_t>(c0 + 4, nchunks);
+  Span sp;
+  sp.s0 = index[c0];
+  sp.s1 = c1 < nchunks ? (uint64_t)index[c1] : words;
+  sp.ok = sp.s0 <= sp.s1 && sp.s1 <= words && sp.s1 - sp.s0 <= kStageWords;
+  return sp;
+}
+// issue (not wait for) the copy of a span into the staging words at `base`
+__device__ __forceinline__ void stage_span(const uint32_t* payload, const Span& sp, uint32_t* stage, uint32_t base) {
+  const uint32_t lane = threadIdx.x;
+  const uint32_t span = (uint32_t)(sp.s1 - sp.s0);
+  for (uint32_t k = 0; k < span; k += 64) {
+    const uint32_t j = k + lane < span ? k + lane : span - 1;
+    __builtin_amdgcn_global_load_lds((gmem_void_t*)(payload + sp.s0 + j), (lds_void_t*)(stage + base + k), 4, 0, 0);
+  }
+}
 
 // decode the wave's 64 blocks [64 w, 64 w + 64) of a field: x~ = in (or +0)
 // plus components [0, ncomp) of the given streams, left to right.  Every lane
@@ -801,43 +834,90 @@ __device__ __forceinline__ bool decode_wave(const Geo& g, const uint8_t* const* 
     for (int l = 0; l < 64; ++l) acc[l] = (T)0;
   }
   bool ok = true;
-  for (int i = 0; i < ncomp; ++i) {
-    const uint32_t* index = reinterpret_cast<const uint32_t*>(s[i] + kHeaderBytes);
-    const uint32_t* payload = index + g.nchunks;
-    uint64_t s0 = 0, s1 = 0;
-    bool span_ok = true;
-    if constexpr (kStaged) {
-      // the wave's chunks [4w, 4w + 4) are consecutive in the payload
-      const uint64_t c0 = w * 4, c1 = min<uint64_t>(c0 + 4, g.nchunks);
-      s0 = index[c0];
-      s1 = c1 < g.nchunks ? (uint64_t)index[c1] : words[i];
-      span_ok = s0 <= s1 && s1 <= words[i] && s1 - s0 <= kStageWords;
-      __syncthreads();  // the previous component's words are no longer read
-      if (span_ok) {
-        const uint32_t span = (uint32_t)(s1 - s0);
-        for (uint32_t k = 0; k < span; k += 64) {
-          const uint32_t j = k + lane < span ? k + lane : span - 1;
-          __builtin_amdgcn_global_load_lds((gmem_void_t*)(payload + s0 + j), (lds_void_t*)(stage + k), 4, 0, 0);
-        }
-        __builtin_amdgcn_s_waitcnt(0);
+  if constexpr (kStaged) {
+    // component i: its span, where it sits in LDS, and this lane's chunk range
+    // and bit offset (loaded together with the span's words)
+    Span cur{0, 0, false};
+    uint32_t cur_base = 0, cur_cap = kStageWords;
+    uint32_t start = 0, stop = 0, off = 0;  // word offsets (a payload has < 2^32 words) and bit offset
+    if (ncomp > 0) {
+      const uint32_t* index = reinterpret_cast<const uint32_t*>(s[0] + kHeaderBytes);
+      cur = wave_span(index, g.nchunks, words[0], w);
+      cur_cap = cur.s1 - cur.s0 <= kHalfWords ? kHalfWords : kStageWords;
+      if (cur.ok) stage_span(index + g.nchunks, cur, stage, 0);
+      if (active) {
+        start = index[chunk];
+        stop = chunk + 1 < g.nchunks ? index[chunk + 1] : (uint32_t)min<uint64_t>(words[0], 0xFFFFFFFFull);
+        off = aux[0][blk];
       }
+    }
+    for (int i = 0; i < ncomp; ++i) {
+      __builtin_amdgcn_s_waitcnt(0);  // component i's words and lane values
       __syncthreads();
+      // the next component: into the other half while this one decodes, when
+      // both fit a half
+      Span nxt{0, 0, false};
+      uint32_t nxt_base = 0, nxt_cap = kStageWords;
+      uint32_t nstart = 0, nstop = 0, noff = 0;
+      bool pre = false;
+      const uint32_t* nindex = nullptr;
+      if (i + 1 < ncomp) {
+        nindex = reinterpret_cast<const uint32_t*>(s[i + 1] + kHeaderBytes);
+        nxt = wave_span(nindex, g.nchunks, words[i + 1], w);
+        pre = nxt.ok && cur.ok && cur.s1 - cur.s0 <= kHalfWords && nxt.s1 - nxt.s0 <= kHalfWords;
+        if (pre) {
+          nxt_base = cur_base == 0 ? kHalf1 : 0;
+          nxt_cap = kHalfWords;
+          stage_span(nindex + g.nchunks, nxt, stage, nxt_base);
+          if (active) {
+            nstart = nindex[chunk];
+            nstop = chunk + 1 < g.nchunks ? nindex[chunk + 1] : (uint32_t)min<uint64_t>(words[i + 1], 0xFFFFFFFFull);
+            noff = aux[i + 1][blk];
+          }
+        }
+      }
+      if (active && ok) {
+        if (!cur.ok || words[i] > 0xFFFFFFFFull || start > stop || stop > words[i] ||
+            off >= (uint64_t)(stop - start) * 32 || start < cur.s0 || stop > cur.s1) {
+          ok = false;
+        } else {
+          const uint32_t s0 = (uint32_t)cur.s0;
+          LBits r;
+          r.init(stage + cur_base, start - s0 + (off >> 5), stop - s0, cur_cap);
+          r.skip((uint32_t)(off & 31));
+          ok = decode_block_add<T>(r, minexp[i], acc, sq) && !r.bad();
+        }
+      }
+      if (i + 1 < ncomp && !pre) {  // staged after this component, into the whole buffer's first half or all of it
+        __syncthreads();  // every lane is done with this component's words
+        nxt_base = 0;
+        nxt_cap = nxt.s1 - nxt.s0 <= kHalfWords ? kHalfWords : kStageWords;
+        if (nxt.ok) stage_span(nindex + g.nchunks, nxt, stage, 0);
+        if (active) {
+          nstart = nindex[chunk];
+          nstop = chunk + 1 < g.nchunks ? nindex[chunk + 1] : (uint32_t)min<uint64_t>(words[i + 1], 0xFFFFFFFFull);
+          noff = aux[i + 1][blk];
+        }
+      }
+      cur = nxt;
+      cur_base = nxt_base;
+      cur_cap = nxt_cap;
+      start = nstart;
+      stop = nstop;
+      off = noff;
     }
-    if (!active || !ok) continue;
-    const uint64_t start = index[chunk];
-    const uint64_t stop = chunk + 1 < g.nchunks ? (uint64_t)index[chunk + 1] : words[i];
-    const uint64_t off = aux[i][blk];
-    if (!span_ok || start > stop || stop > words[i] || stop > 0xFFFFFFFFull || off >= (stop - start) * 32 ||
-        (kStaged && (start < s0 || stop > s1))) {
-      ok = false;
-      continue;
-    }
-    if constexpr (kStaged) {
-      LBits<kStageWords> r;
-      r.init(stage, (uint32_t)(start - s0 + (off >> 5)), (uint32_t)(stop - s0));
-      r.skip((uint32_t)(off & 31));
-      ok = decode_block_add<T>(r, minexp[i], acc, sq) && !r.bad();
-    } else {
+  } else {
+    for (int i = 0; i < ncomp; ++i) {
+      if (!active || !ok) continue;
+      const uint32_t* index = reinterpret_cast<const uint32_t*>(s[i] + kHeaderBytes);
+      const uint32_t* payload = index + g.nchunks;
+      const uint64_t start = index[chunk];
+      const uint64_t stop = chunk + 1 < g.nchunks ? (uint64_t)index[chunk + 1] : words[i];
+      const uint64_t off = aux[i][blk];
+      if (start > stop || stop > words[i] || stop > 0xFFFFFFFFull || off >= (stop - start) * 32) {
+        ok = false;
+        continue;
+      }
       GBits r;
       r.init(payload, (uint32_t)(start + (off >> 5)), (uint32_t)stop);
       r.skip((uint32_t)(off & 31));

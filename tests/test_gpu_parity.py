@@ -163,6 +163,24 @@ def test_staged_and_global_decoders_f64(ctx):
     assert [c["staged"] for c in store.info] == [True, False]
 
 
+def test_double_buffered_staging(ctx):
+    """While two consecutive components each span at most half of the staging
+    buffer (1600 words a half), the next one is copied into the other half
+    during decoding; a larger span takes the whole buffer and is staged after
+    the previous component.  White noise with tolerances chosen so that the
+    spans alternate between the two cases (spans taken from oracle streams:
+    half, half, half, whole, half, half and whole, half, whole, half); every
+    retrieval matches the oracle."""
+    rng = np.random.default_rng(23)
+    x = rng.uniform(-1.0, 1.0, size=(16, 16, 64)).astype(np.float32)
+    for taus in ([2.0 ** -2, 2.0 ** -4, 2.0 ** -6, 2.0 ** -20, 2.0 ** -21, 2.0 ** -22],
+                 [2.0 ** -13, 2.0 ** -14, 2.0 ** -26, 2.0 ** -27]):
+        store, comps, meta, recon = check_against_oracle(ctx, x, taus, "halves")
+        spans = [c["max_span"] for c in store.info]
+        assert all(c["staged"] for c in store.info), spans
+        assert min(spans) <= 1600 < max(spans), spans
+
+
 def test_decode_oracle_streams(ctx):
     """The GPU decoder reproduces the oracle's Alg. 2 on streams the oracle wrote."""
     x = inputs.spectral_field((17, 20, 33), seed=8, dtype=np.float64)
