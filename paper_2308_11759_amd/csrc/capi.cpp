@@ -475,6 +475,7 @@ static pmc_status decode_range(pmc_ctx* ctx, const pmc_store* s, int k0, int k1,
         a.aux[i - i0] = (const uint32_t*)(s->d_base + s->aux_offset[i]);
         a.words[i - i0] = s->words[i];
         a.minexp[i - i0] = s->minexp[i];
+        if (i > 0) a.relmask |= 1u << (i - i0);  // residual components
       }
       a.ncomp = i1 - i0;
       a.in = (const float*)in;
@@ -490,6 +491,7 @@ static pmc_status decode_range(pmc_ctx* ctx, const pmc_store* s, int k0, int k1,
         a.aux[i - i0] = (const uint32_t*)(s->d_base + s->aux_offset[i]);
         a.words[i - i0] = s->words[i];
         a.minexp[i - i0] = s->minexp[i];
+        if (i > 0) a.relmask |= 1u << (i - i0);  // residual components
       }
       a.ncomp = i1 - i0;
       a.in = (const double*)in;

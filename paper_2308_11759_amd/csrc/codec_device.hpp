@@ -813,9 +813,16 @@ __device__ __forceinline__ void planes_emit(LdsBits& w, const typename FT<T>::U 
 }
 
 // read p planes from the top and return the coefficients in coded order as
-// two's complement integers (negabinary decoded; planes below p are zero)
+// two's complement integers (negabinary decoded; planes below p are zero).
+// rel selects which 16 planes go through the register transpose: the block's
+// top 16 (rel = false), or the 16 from its first non-empty plane (rel =
+// true).  The loop over the 16 plane slots is unrolled, so a wave runs each
+// slot's group-test windows for as long as its slowest lane; in residual
+// components, whose blocks are noise-like, the planes where most coefficients
+// become significant follow the first non-empty one, and counting slots from
+// there lines them up across the wave's blocks.
 template <class T, class R>
-__device__ __forceinline__ void planes_read(R& r, typename FT<T>::S c[64], int p, const uint8_t* sq) {
+__device__ __forceinline__ void planes_read(R& r, typename FT<T>::S c[64], int p, const uint8_t* sq, bool rel) {
   typedef typename FT<T>::U U;
   typedef typename FT<T>::S S;
   constexpr int P = FT<T>::P;
@@ -826,31 +833,36 @@ __device__ __forceinline__ void planes_read(R& r, typename FT<T>::S c[64], int p
   const int z0 = (int)__builtin_ctz(r.peek32() | 0x80000000u);
   const int zlead = z0 < p ? z0 : p;
   r.skip((uint32_t)zlead);
-  // the top 16 planes straight into registers (the plane loop is unrolled so
-  // every plane word has a fixed register), then one transpose
+  // slot t' holds plane base + t'
+  const int base = rel ? (zlead < P - 16 ? zlead : P - 16) : 0;
   uint32_t Tw[32];
 #pragma unroll
-  for (int t = 0; t < 16; ++t) {
+  for (int tp = 0; tp < 16; ++tp) {
+    const int t = base + tp;
     uint64_t wd = 0;
     if (t >= zlead && t < p) wd = plane_read(r, n, sq);
-    Tw[15 - t] = (uint32_t)wd;
-    Tw[31 - t] = (uint32_t)(wd >> 32);
+    Tw[15 - tp] = (uint32_t)wd;
+    Tw[31 - tp] = (uint32_t)(wd >> 32);
   }
   transpose32(Tw);  // back to 16-bit slices of coefficients j and j+32
-  // A coefficient with only its top 16 bits X set (X << s, s = P - 16, even)
-  // has the value ((X ^ 0xAAAA) - 0xAAAA) << s: the negabinary mask's lower
-  // bits cancel.  One xor serves both slices of a word.
-  constexpr U kOff = (U)0xAAAAu << (P - 16);
+  // A slice X stands for the coefficient X << sh (sh = P - 16 - base; the
+  // planes above are empty), whose value is ((X ^ M) - M) << sh with M the
+  // negabinary mask's bits at the slice's positions (0xAAAA for even sh,
+  // 0x5555 for odd): the mask's lower bits cancel.  One xor serves both
+  // slices of a word.
+  const int sh = P - 16 - base;
+  const uint32_t M = (sh & 1) ? 0x5555u : 0xAAAAu;
+  const uint32_t MM = M | (M << 16);
 #pragma unroll
   for (int j = 0; j < 32; ++j) {
-    const uint32_t x = Tw[j] ^ 0xAAAAAAAAu;
-    c[j] = (S)(((U)(x & 0xFFFFu) << (P - 16)) - kOff);
-    c[j + 32] = (S)(((U)(x >> 16) << (P - 16)) - kOff);
+    const uint32_t x = Tw[j] ^ MM;
+    c[j] = (S)((U)(S)(int32_t)((x & 0xFFFFu) - M) << sh);
+    c[j + 32] = (S)((U)(S)(int32_t)((x >> 16) - M) << sh);
   }
   // deeper planes (rare): a plane bit at an even position b adds 2^b to the
   // two's complement value, one at an odd position subtracts it (the
   // negabinary weight of bit b is (-2)^b)
-  for (int t = zlead > 16 ? zlead : 16; t < p; ++t) {
+  for (int t = base + 16 > zlead ? base + 16 : zlead; t < p; ++t) {
     const uint64_t wd = plane_read(r, n, sq);
     const uint32_t lo = (uint32_t)wd, hi = (uint32_t)(wd >> 32);
     const int b = P - 1 - t;

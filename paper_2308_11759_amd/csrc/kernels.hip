@@ -731,7 +731,7 @@ __global__ __launch_bounds__(64) void k_pack(PackArgs a) {
 // the field precision; the block's bits start at its chunk's word offset plus
 // the block's bit offset from the per-block index
 template <class T, class R>
-__device__ __forceinline__ bool decode_block_add(R& r, int minexp, T acc[64], const uint8_t* sq) {
+__device__ __forceinline__ bool decode_block_add(R& r, int minexp, T acc[64], const uint8_t* sq, bool rel) {
   typedef typename FT<T>::U U;
   constexpr int P = FT<T>::P;
   constexpr int EB = FT<T>::EBITS;
@@ -767,7 +767,7 @@ __device__ __forceinline__ bool decode_block_add(R& r, int minexp, T acc[64], co
   p = (p < 0 ? 0 : (p > P ? P : p)) + delta;
   if (emax < 2 - FT<T>::BIAS || p < 1 || p > P) return false;
   typename FT<T>::S c[64], q[64];
-  planes_read<T>(r, c, p, sq);
+  planes_read<T>(r, c, p, sq, rel);
   inverse_zy_ints<T>(c, q);
   inverse_x<T>(q);
   dequant_add(q, emax, acc);
@@ -819,8 +819,8 @@ __device__ __forceinline__ void stage_span(const uint32_t* payload, const Span& 
 // malformed stream.
 template <class T, bool kStaged>
 __device__ __forceinline__ bool decode_wave(const Geo& g, const uint8_t* const* s, const uint32_t* const* aux,
-                                            const uint64_t* words, const int* minexp, int ncomp, const T* in, T* out,
-                                            uint64_t w, const uint8_t* sq, uint32_t* stage) {
+                                            const uint64_t* words, const int* minexp, int ncomp, uint32_t relmask,
+                                            const T* in, T* out, uint64_t w, const uint8_t* sq, uint32_t* stage) {
   const uint32_t lane = threadIdx.x;
   const uint64_t blk = w * 64 + lane;
   const bool active = blk < g.nblocks;
@@ -885,7 +885,7 @@ __device__ __forceinline__ bool decode_wave(const Geo& g, const uint8_t* const* 
           LBits r;
           r.init(stage + cur_base, start - s0 + (off >> 5), stop - s0, cur_cap);
           r.skip((uint32_t)(off & 31));
-          ok = decode_block_add<T>(r, minexp[i], acc, sq) && !r.bad();
+          ok = decode_block_add<T>(r, minexp[i], acc, sq, (relmask >> i) & 1u) && !r.bad();
         }
       }
       if (i + 1 < ncomp && !pre) {  // staged after this component, into the whole buffer's first half or all of it
@@ -921,7 +921,7 @@ __device__ __forceinline__ bool decode_wave(const Geo& g, const uint8_t* const* 
       GBits r;
       r.init(payload, (uint32_t)(start + (off >> 5)), (uint32_t)stop);
       r.skip((uint32_t)(off & 31));
-      ok = decode_block_add<T>(r, minexp[i], acc, sq) && !r.bad();
+      ok = decode_block_add<T>(r, minexp[i], acc, sq, (relmask >> i) & 1u) && !r.bad();
     }
   }
   // the block position is recomputed here rather than kept in registers
@@ -934,8 +934,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
   __shared__ uint8_t s_squeeze[256];
   __shared__ uint32_t s_stage[kStaged ? kStageWords + 3 : 1];
   squeeze_table(s_squeeze);
-  if (!decode_wave<T, kStaged>(a.g, a.s, a.aux, a.words, a.minexp, a.ncomp, a.in, a.out, blockIdx.x, s_squeeze,
-                               s_stage))
+  if (!decode_wave<T, kStaged>(a.g, a.s, a.aux, a.words, a.minexp, a.ncomp, a.relmask, a.in, a.out, blockIdx.x,
+                               s_squeeze, s_stage))
     atomicOr(a.status, 1u);
 }
 
@@ -954,7 +954,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     else hi = mid;
   }
   const QueryDev& q = a.q[lo];
-  if (!decode_wave<T, kStaged>(q.g, q.s, q.aux, q.words, q.minexp, q.ncomp, reinterpret_cast<const T*>(q.in),
+  if (!decode_wave<T, kStaged>(q.g, q.s, q.aux, q.words, q.minexp, q.ncomp, q.relmask, reinterpret_cast<const T*>(q.in),
                                reinterpret_cast<T*>(q.out), w - a.wave_prefix[lo], s_squeeze, s_stage))
     atomicOr(a.status, 1u);
 }

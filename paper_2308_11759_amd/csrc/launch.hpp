@@ -91,6 +91,7 @@ template <class T> struct DecArgs {
   uint64_t words[kMaxDecode];      // payload words of each stream
   int minexp[kMaxDecode];
   int ncomp;
+  uint32_t relmask;  // bit i: component i is a residual (not a store's first), planes counted from its first non-empty one
   const T* in;  // x~ to continue from; NULL = +0
   T* out;
   Geo g;
@@ -105,6 +106,7 @@ struct QueryDev {
   uint64_t words[kMaxComps];
   int minexp[kMaxComps];
   int ncomp;
+  uint32_t relmask;  // as DecArgs::relmask
   int dtype;
   const void* in;
   void* out;

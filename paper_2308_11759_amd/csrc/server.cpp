@@ -282,6 +282,7 @@ bool launch_step(pmc_server* sv) {
       d.aux[i] = (const uint32_t*)(s->d_base + s->aux_offset[c]);
       d.words[i] = s->words[c];
       d.minexp[i] = s->minexp[c];
+      if (c > 0) d.relmask |= 1u << i;  // residual components
       span[t] = std::max(span[t], s->max_span[c]);
     }
     d.dtype = s->f.dtype;
