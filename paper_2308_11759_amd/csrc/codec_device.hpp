@@ -123,23 +123,6 @@ template <class S> __device__ __forceinline__ void xform_fwd(S q[64]) {
     lift_fwd(q[b], q[b + 16], q[b + 32], q[b + 48]);
   }
 }
-template <class S> __device__ __forceinline__ void xform_inv(S q[64]) {
-#pragma unroll
-  for (int l = 0; l < 16; ++l) {
-    const int b = l;
-    lift_inv(q[b], q[b + 16], q[b + 32], q[b + 48]);
-  }
-#pragma unroll
-  for (int l = 0; l < 16; ++l) {
-    const int b = 16 * (l >> 2) + (l & 3);
-    lift_inv(q[b], q[b + 4], q[b + 8], q[b + 12]);
-  }
-#pragma unroll
-  for (int l = 0; l < 16; ++l) {
-    const int b = 4 * l;
-    lift_inv(q[b], q[b + 1], q[b + 2], q[b + 3]);
-  }
-}
 
 // ---------------------------------------------------------------------------
 // 32x32 bit-matrix transpose in registers: afterwards A[r] bit c equals the
@@ -455,56 +438,6 @@ __device__ __forceinline__ uint32_t prefix_xor(uint32_t s) {
   return s;
 }
 
-// the group tests of one plane one token at a time: a positive test and its
-// run "0...01" are taken in one step from a 32-bit peek of the buffer
-__device__ __forceinline__ void plane_tokens(GBits& r, uint32_t& n, uint64_t& wd) {
-  while (n < 64) {
-    r.refill();
-    const uint32_t lo = (uint32_t)r.buf;
-    if ((lo & 1u) == 0u) {  // negative group test ends the plane
-      r.drop(1);
-      break;
-    }
-    const uint32_t limit = 63u - n;  // explicit run positions n..62
-    const uint32_t vis = limit < 31u ? limit : 31u;
-    const uint32_t run = (lo >> 1) & ((1u << vis) - 1u);
-    if (run != 0u) {
-      const uint32_t z = (uint32_t)__builtin_ctz(run);
-      r.drop(z + 2);
-      wd |= 1ull << (n + z);
-      n += z + 1;
-    } else if (limit <= 31u) {  // all explicit positions zero: the last one is implied
-      r.drop(limit + 1);
-      wd |= 1ull << 63;
-      n = 64;
-    } else {  // a run of more than 31 zeros: continue it without group bits
-      r.drop(32);
-      n += 31;
-      for (;;) {
-        r.refill();
-        const uint32_t lo2 = (uint32_t)r.buf;
-        const uint32_t lim2 = 63u - n;
-        const uint32_t run2 = lim2 >= 32u ? lo2 : (lo2 & ((1u << lim2) - 1u));
-        if (run2 != 0u) {
-          const uint32_t z = (uint32_t)__builtin_ctz(run2);
-          r.drop(z + 1);
-          wd |= 1ull << (n + z);
-          n += z + 1;
-          break;
-        }
-        if (lim2 <= 32u) {
-          r.drop(lim2);
-          wd |= 1ull << 63;
-          n = 64;
-          break;
-        }
-        r.drop(32);
-        n += 32;
-      }
-    }
-  }
-}
-
 // squeeze: every set bit of m, at position t and i-th from the bottom
 // (i >= 1), moves to t - i.  Applied to the run terminators of a group-test
 // section (which are at least two bits apart and never at bit 0) this drops
@@ -661,10 +594,8 @@ __device__ __forceinline__ void forward_coeffs(const T e[64], int emax, typename
   for (int r = 0; r < 64; ++r) u[r] = to_nb<T>(q[kOrder.at[r]]);
 }
 
-// coefficients truncated to p planes -> decoded block values (in d[l])
-// the inverse split so that its last (x) pass can run one block row at a time:
-// coefficients -> integers after the z and y passes ...
-// (from coded-order integers c, already out of negabinary)
+// the inverse transform: coded-order integers c (already out of negabinary)
+// -> block order, then the z and y passes ...
 template <class T>
 __device__ __forceinline__ void inverse_zy_ints(const typename FT<T>::S c[64], typename FT<T>::S q[64]) {
 #pragma unroll
@@ -680,23 +611,7 @@ __device__ __forceinline__ void inverse_zy_ints(const typename FT<T>::S c[64], t
     lift_inv(q[b], q[b + 4], q[b + 8], q[b + 12]);
   }
 }
-template <class T>
-__device__ __forceinline__ void inverse_zy(const typename FT<T>::U u[64], typename FT<T>::S q[64]) {
-  typename FT<T>::S c[64];
-#pragma unroll
-  for (int r = 0; r < 64; ++r) c[r] = from_nb<T>(u[r]);
-  inverse_zy_ints<T>(c, q);
-}
-// ... then row r (ly = r & 3, lz = r >> 2): x pass and dequantisation
-template <class T>
-__device__ __forceinline__ void inverse_row(typename FT<T>::S q[64], int r, int emax, T out[4]) {
-  lift_inv(q[4 * r], q[4 * r + 1], q[4 * r + 2], q[4 * r + 3]);
-#pragma unroll
-  for (int t = 0; t < 4; ++t) out[t] = dequantize(q[4 * r + t], emax);
-}
-
-// whole-block form for the decoder: the x pass of every row, then
-// acc += dequantised values in the field precision
+// ... then the x pass of every row
 template <class T> __device__ __forceinline__ void inverse_x(typename FT<T>::S q[64]) {
 #pragma unroll
   for (int r = 0; r < 16; ++r) lift_inv(q[4 * r], q[4 * r + 1], q[4 * r + 2], q[4 * r + 3]);
@@ -773,19 +688,6 @@ template <class T> __device__ __forceinline__ uint32_t planes_cost_reg(const typ
     for (int t = 0; t < 16; ++t) {
       if (t < tmax) bits += plane_cost((uint64_t)Tw[15 - t] | ((uint64_t)Tw[31 - t] << 32), n);
     }
-  }
-  return bits;
-}
-
-// bits of p planes from the top
-template <class T>
-__device__ __forceinline__ uint32_t planes_cost(const typename FT<T>::U u[64], int p, uint32_t* pw) {
-  constexpr int P = FT<T>::P;
-  uint32_t n = 0, bits = 0;
-  for (int g = 0; 16 * g < p; ++g) {
-    group_to_lds(u, P - 16 * (g + 1), pw);
-    const int tmax = p - 16 * g < 16 ? p - 16 * g : 16;
-    for (int t = 0; t < tmax; ++t) bits += plane_cost(lds_plane(pw, t), n);
   }
   return bits;
 }
