@@ -706,11 +706,12 @@ __device__ __forceinline__ void planes_emit(LdsBits& w, const typename FT<T>::U 
   zl = zl < p ? zl : p;
   w.put64(0, (uint32_t)zl);
   uint32_t n = 0;
+  // each lane starts at its own first non-empty plane, so the wave's loop
+  // runs max(p - zl) times rather than max(p) - min(zl)
   for (int g = zl / 16; 16 * g < p; ++g) {
     group_to_lds(u, P - 16 * (g + 1), pw);
     const int tmax = p - 16 * g < 16 ? p - 16 * g : 16;
-    for (int t = 0; t < tmax; ++t)
-      if (16 * g + t >= zl) plane_emit(w, lds_plane(pw, t), n, tab);
+    for (int t = 16 * g >= zl ? 0 : zl - 16 * g; t < tmax; ++t) plane_emit(w, lds_plane(pw, t), n, tab);
   }
 }
 
@@ -755,11 +756,12 @@ __device__ __forceinline__ void planes_read(R& r, typename FT<T>::S c[64], int p
   const int sh = P - 16 - base;
   const uint32_t M = (sh & 1) ? 0x5555u : 0xAAAAu;
   const uint32_t MM = M | (M << 16);
+  const U off = (U)0 - ((U)M << sh);  // -(M << sh), modulo 2^P
 #pragma unroll
   for (int j = 0; j < 32; ++j) {
     const uint32_t x = Tw[j] ^ MM;
-    c[j] = (S)((U)(S)(int32_t)((x & 0xFFFFu) - M) << sh);
-    c[j + 32] = (S)((U)(S)(int32_t)((x >> 16) - M) << sh);
+    c[j] = (S)(((U)(x & 0xFFFFu) << sh) + off);
+    c[j + 32] = (S)(((U)(x >> 16) << sh) + off);
   }
   // deeper planes (rare): a plane bit at an even position b adds 2^b to the
   // two's complement value, one at an odd position subtracts it (the
