@@ -326,8 +326,10 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
   const uint64_t vmask = valid_mask(bp);
 
   // one pass over the rows: the residual e = x - x~_{i-1} (kept in registers
-  // for the transform), its largest magnitude (the block exponent, the
-  // all-zero test) and the largest |x| (non-finite input)
+  // for the transform) and its largest magnitude (the block exponent, the
+  // all-zero test).  The first component, where x~_0 = 0 and the residual is
+  // x itself, also gives the largest |x| (non-finite input; x is the same for
+  // every component, and the host combines the components' flags).
   U maxabs = 0, xmax = 0;  // largest |residual| and |x| bit patterns
   U u[64];                 // the residual's coefficients: every candidate and the emission use them
   int emax;
@@ -337,14 +339,12 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int l = 4 * r + t;
-        const T xl = X.at(l);
-        e[l] = xl - e[l];
+        e[l] = X.at(l) - e[l];
         const U ab = abs_bits(e[l]);
         maxabs = ab > maxabs ? ab : maxabs;
-        const U xb = abs_bits(xl);
-        xmax = xb > xmax ? xb : xmax;
       }
     }
+    if (a.first) xmax = maxabs;  // x - (+0) has the magnitude of x
     emax = block_emax<T>(maxabs);
     if (active && maxabs != 0) forward_coeffs<T>(e, emax, u);
   }
