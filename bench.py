@@ -312,12 +312,21 @@ def main():
         log("warmup %d done" % w)
     if store is None:
         store = ctx.compress(xd, taus, streams=streams)
-    # parity probe at full size: Eq. (1) for every k, on the device
+    # parity probe at full size: Eq. (1) for every k, on the device; and the
+    # accuracy gain of each x~_k at its cumulative rate (Sec. 5.1.1)
+    gain = {"sigma": None, "rate_bits_per_value": [], "rmse": [], "gain": []}
+    bits = 0
     for k in range(1, n + 1):
         ctx.retrieve(store, k, out=out)
         err = float((xd.double() - out.double()).abs().max())
         assert err <= taus[k - 1], (k, err, taus[k - 1])
         assert err == store.info[k - 1]["linf"], (k, err, store.info[k - 1]["linf"])
+        bits += 8 * store.info[k - 1]["bytes"]
+        sigma, rmse, g = ctx.accuracy_gain(xd, out, bits / x.size)
+        gain["sigma"] = sigma
+        gain["rate_bits_per_value"].append(round(bits / x.size, 4))
+        gain["rmse"].append(rmse)
+        gain["gain"].append(round(g, 4))
     torch.cuda.synchronize()
 
     ctx.set_option(pmc.OPT_PROFILE, 1)
@@ -424,6 +433,7 @@ def main():
         "refine_chain_ms": refine_ms,
         "rates_bits_per_value": [round(8.0 * m["bytes"] / N, 3) for m in info],
         "linf": [m["linf"] for m in info],
+        "accuracy_gain": gain,
         "kernels": kern,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -90,6 +90,21 @@ pmc_status pmc_prof_read(pmc_ctx* ctx, pmc_prof_entry* out, int cap, int* n, int
 pmc_status pmc_range(pmc_ctx* ctx, const pmc_field* f, const void* d_x, void* d_ws, size_t ws_bytes,
                      double* vmin, double* vmax, uint64_t* nonfinite);
 
+/* ---- accuracy gain of a reconstruction (Sec. 5.1.1, its defining equation) -
+ * gain = log2(sigma / rmse) - rate: sigma is the standard deviation of x
+ * (over all values, float64), rmse the root-mean-square of x - xt, rate the
+ * caller's bits per value (for x~_k: all bytes of components 1..k times 8,
+ * over the value count).  out[0] = sigma, out[1] = rmse, out[2] = gain
+ * (+inf when rmse = 0, -inf when sigma = 0 < rmse).  d_x and d_xt are device
+ * fields of the same shape and type (f); d_ws: at least pmc_stats_ws_bytes()
+ * bytes of device scratch.  Sums are float64 in a fixed order, so a result
+ * repeats bit for bit.  Synchronises the context's stream.  Errors:
+ * PMC_E_ARG (null pointer, bad field), PMC_E_NOMEM (workspace too small),
+ * PMC_E_HIP. */
+size_t pmc_stats_ws_bytes(void);
+pmc_status pmc_accuracy_gain(pmc_ctx* ctx, const pmc_field* f, const void* d_x, const void* d_xt, double rate,
+                             void* d_ws, size_t ws_bytes, double out[3]);
+
 /* ---- multi-component compression (Alg. 1, Sec. 4.1) ----------------------
  * Sizes for pmc_compress: device workspace bytes, and the capacity one
  * component's stream can need in the worst case (all blocks raw).  The total

@@ -14,6 +14,8 @@ Codecs plug in through ``encode(e, tau, x, xt) -> (y, stats)`` and
 scalar cast-to-float32 "compressor" of Sec. 3, which turns Alg. 1 into the
 classical multi-component floating-point expansion.
 """
+import math
+
 import numpy as np
 
 from . import lib
@@ -48,6 +50,19 @@ def measured_error(x, xt):
     if x.size == 0:
         return 0.0
     return float(np.max(np.abs(x.astype(np.float64) - xt.astype(np.float64))))
+
+
+def accuracy_gain(x, xt, rate):
+    """Sec. 5.1.1: gain = log2(sigma / rmse) - rate, sigma the standard deviation
+    of x, rmse the root-mean-square of x - x~, rate in bits per value; all in
+    float64.  Returns (sigma, rmse, gain)."""
+    xd = np.asarray(x, dtype=np.float64)
+    ed = xd - np.asarray(xt, dtype=np.float64)
+    sigma = math.sqrt(float(np.mean((xd - np.mean(xd)) ** 2)))
+    rmse = math.sqrt(float(np.mean(ed ** 2)))
+    with np.errstate(divide="ignore"):
+        gain = float(np.log2(np.float64(sigma) / np.float64(rmse))) - rate
+    return sigma, rmse, gain
 
 
 def compress(x, taus, codec=None):

@@ -242,6 +242,48 @@ pmc_status pmc_range(pmc_ctx* ctx, const pmc_field* f, const void* d_x, void* d_
   return PMC_OK;
 }
 
+size_t pmc_stats_ws_bytes(void) { return (size_t)sum_sq_ws_bytes() + 256; }
+
+pmc_status pmc_accuracy_gain(pmc_ctx* ctx, const pmc_field* f, const void* d_x, const void* d_xt, double rate,
+                             void* d_ws, size_t ws_bytes, double out[3]) {
+  if (!ctx) return PMC_E_ARG;
+  Geo g;
+  if (!make_geo(f, &g) || !d_x || !d_xt || !out) return fail(ctx, PMC_E_ARG, "bad field or null pointer");
+  if (!d_ws || ws_bytes < pmc_stats_ws_bytes())
+    return fail(ctx, PMC_E_NOMEM, "accuracy gain needs %llu bytes of workspace",
+                (unsigned long long)pmc_stats_ws_bytes());
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hipfail(ctx, e, "hipSetDevice");
+  const uint64_t n = g.nx * g.ny * g.nz;
+  double* ws = (double*)d_ws;
+  double* res = (double*)((uint8_t*)d_ws + sum_sq_ws_bytes());
+  // one sum pass: (shift, with xt?) -> host pair
+  auto pass = [&](const void* b, double shift, double h[2]) -> pmc_status {
+    hipError_t r;
+    if (f->dtype == PMC_F32)
+      r = launch_sum_sq<float>((const float*)d_x, (const float*)b, shift, n, ws, res, ctx->stream);
+    else
+      r = launch_sum_sq<double>((const double*)d_x, (const double*)b, shift, n, ws, res, ctx->stream);
+    if (r != hipSuccess) return hipfail(ctx, r, "sum kernel");
+    if ((r = hipMemcpyAsync(h, res, 16, hipMemcpyDeviceToHost, ctx->stream)) != hipSuccess)
+      return hipfail(ctx, r, "copy");
+    if ((r = hipStreamSynchronize(ctx->stream)) != hipSuccess) return hipfail(ctx, r, "sync");
+    return PMC_OK;
+  };
+  double h[2];
+  pmc_status st;
+  if ((st = pass(nullptr, 0.0, h)) != PMC_OK) return st;
+  const double mean = h[0] / (double)n;
+  if ((st = pass(nullptr, mean, h)) != PMC_OK) return st;  // second pass about the mean
+  const double sigma = std::sqrt(h[1] / (double)n);
+  if ((st = pass(d_xt, 0.0, h)) != PMC_OK) return st;
+  const double rmse = std::sqrt(h[1] / (double)n);
+  out[0] = sigma;
+  out[1] = rmse;
+  out[2] = std::log2(sigma / rmse) - rate;
+  return PMC_OK;
+}
+
 pmc_status pmc_compress_sizes(const pmc_field* f, int n, size_t* ws_bytes, size_t* stream_cap_per_comp) {
   Geo g;
   if (!make_geo(f, &g) || n < 1 || n > kMaxComps) return PMC_E_ARG;

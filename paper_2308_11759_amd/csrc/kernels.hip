@@ -1268,6 +1268,73 @@ template <class T> hipError_t launch_decode_queries(const ServeArgs& a, uint64_t
   else hipLaunchKernelGGL((k_decode_queries<T, false>), dim3(a.nwaves), dim3(64), 0, s, a);
   return hipGetLastError();
 }
+// ---------------------------------------------------------------------------
+// sums of d = a - b - shift and of d^2 in float64 over a field (b NULL: 0),
+// for the accuracy gain of Sec. 5.1.1 (standard deviation of the data,
+// root-mean-square error of a reconstruction).  Deterministic: each
+// workgroup reduces a fixed grid-stride share in a fixed order into its own
+// partial pair, and one workgroup then adds the partials in index order.
+constexpr int kSumGroups = 1024;  // workgroups of the first stage (the partials)
+
+__device__ __forceinline__ void block_sum2(double& s, double& q, double* sh) {
+  const uint32_t t = threadIdx.x;
+  sh[t] = s;
+  sh[256 + t] = q;
+  __syncthreads();
+  for (uint32_t h = 128; h > 0; h >>= 1) {
+    if (t < h) {
+      sh[t] = sh[t] + sh[t + h];
+      sh[256 + t] = sh[256 + t] + sh[256 + t + h];
+    }
+    __syncthreads();
+  }
+  s = sh[0];
+  q = sh[256];
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_sum_sq(const T* __restrict__ a, const T* __restrict__ b, double shift,
+                                                uint64_t n, double* partials) {
+  __shared__ double sh[512];
+  double s = 0.0, q = 0.0;
+  const uint64_t stride = (uint64_t)gridDim.x * 256;
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+    const double d = ((double)a[i] - (b ? (double)b[i] : 0.0)) - shift;
+    s = s + d;
+    q = q + d * d;
+  }
+  block_sum2(s, q, sh);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = s;
+    partials[2 * blockIdx.x + 1] = q;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_sum_sq_final(const double* partials, uint32_t groups, double* out) {
+  __shared__ double sh[512];
+  double s = 0.0, q = 0.0;
+  for (uint32_t g = threadIdx.x; g < groups; g += 256) {
+    s = s + partials[2 * g];
+    q = q + partials[2 * g + 1];
+  }
+  block_sum2(s, q, sh);
+  if (threadIdx.x == 0) {
+    out[0] = s;
+    out[1] = q;
+  }
+}
+
+template <class T>
+hipError_t launch_sum_sq(const T* a, const T* b, double shift, uint64_t n, double* ws, double* out, hipStream_t s) {
+  uint64_t groups = (n + 255) / 256;
+  if (groups > kSumGroups) groups = kSumGroups;
+  if (groups == 0) groups = 1;
+  hipLaunchKernelGGL(k_sum_sq<T>, dim3((uint32_t)groups), dim3(256), 0, s, a, b, shift, n, ws);
+  hipLaunchKernelGGL(k_sum_sq_final, dim3(1), dim3(256), 0, s, ws, (uint32_t)groups, out);
+  return hipGetLastError();
+}
+uint64_t sum_sq_ws_bytes() { return (uint64_t)kSumGroups * 16 + 256; }
+
 template <class T> hipError_t launch_aux(const AuxArgs& a, hipStream_t s) {
   const uint64_t wgs = (a.g.nchunks + 63) / 64;
   hipLaunchKernelGGL(k_aux<T>, dim3((uint32_t)wgs), dim3(64), 0, s, a);
@@ -1319,5 +1386,8 @@ template hipError_t launch_aux<float>(const AuxArgs&, hipStream_t);
 template hipError_t launch_aux<double>(const AuxArgs&, hipStream_t);
 template hipError_t launch_range<float>(const float*, uint64_t, unsigned long long*, hipStream_t);
 template hipError_t launch_range<double>(const double*, uint64_t, unsigned long long*, hipStream_t);
+template hipError_t launch_sum_sq<float>(const float*, const float*, double, uint64_t, double*, double*, hipStream_t);
+template hipError_t launch_sum_sq<double>(const double*, const double*, double, uint64_t, double*, double*,
+                                          hipStream_t);
 
 }  // namespace pmc

@@ -182,6 +182,11 @@ template <class T> hipError_t launch_decode(const DecArgs<T>& a, uint64_t max_sp
 uint64_t stage_words();  // capacity of the decoder's LDS staging buffer, in words
 template <class T> hipError_t launch_range(const T* x, uint64_t n, unsigned long long* out, hipStream_t s);
 hipError_t launch_fill64(unsigned long long* p, uint64_t n, unsigned long long v, hipStream_t s);
+// out[0] = sum of d, out[1] = sum of d^2 in float64, d = a - b - shift (b NULL: 0);
+// ws holds sum_sq_ws_bytes() bytes of partials; out may lie inside ws past them
+template <class T>
+hipError_t launch_sum_sq(const T* a, const T* b, double shift, uint64_t n, double* ws, double* out, hipStream_t s);
+uint64_t sum_sq_ws_bytes();
 
 // capacity of one chunk's staging slot in 32-bit words
 inline uint64_t chunk_cap_words_host(int dtype) {

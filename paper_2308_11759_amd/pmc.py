@@ -56,6 +56,8 @@ SIGNATURES = {
     "pmc_last_error": (ctypes.c_char_p, [_vp]),
     "pmc_ctx_set_option": (_int, [_vp, _int, _int]),
     "pmc_range": (_int, [_vp, _P(Field), _vp, _vp, _sz, _P(_dbl), _P(_dbl), _P(_u64)]),
+    "pmc_stats_ws_bytes": (_sz, []),
+    "pmc_accuracy_gain": (_int, [_vp, _P(Field), _vp, _vp, _dbl, _vp, _sz, _P(_dbl)]),
     "pmc_compress_sizes": (_int, [_P(Field), _int, _P(_sz), _P(_sz)]),
     "pmc_compress": (_int, [_vp, _P(Field), _vp, _int, _P(_dbl), _vp, _sz, _vp, _sz, _P(_vp)]),
     "pmc_store_info": (_int, [_vp, _P(_int), _P(_dbl), _P(_dbl), _P(_u64), _P(_u64), _P(_u64)]),
@@ -193,6 +195,18 @@ class Context:
                                        ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.byref(lo),
                                        ctypes.byref(hi), ctypes.byref(bad)))
         return lo.value, hi.value, bad.value
+
+    def accuracy_gain(self, x, xt, rate):
+        """Sec. 5.1.1: (sigma, rmse, gain) with gain = log2(sigma / rmse) - rate."""
+        f = field_of(x)
+        if field_of(xt).dtype != f.dtype or tuple(xt.shape) != tuple(x.shape):
+            raise ValueError("x and xt must have the same shape and dtype")
+        ws = self._workspace(self.lib.pmc_stats_ws_bytes())
+        out = (ctypes.c_double * 3)()
+        self._check(self.lib.pmc_accuracy_gain(self.handle, ctypes.byref(f), ctypes.c_void_p(x.data_ptr()),
+                                               ctypes.c_void_p(xt.data_ptr()), float(rate),
+                                               ctypes.c_void_p(ws.data_ptr()), ws.numel(), out))
+        return out[0], out[1], out[2]
 
     def compress_sizes(self, x, n):
         f = field_of(x)

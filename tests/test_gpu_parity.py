@@ -289,3 +289,28 @@ def test_corrupt_payload_is_contained(ctx):
             ctx.retrieve(s, 2)
         except pmc.PmcError as e:
             assert e.status == pmc.E_CORRUPT
+
+
+def test_accuracy_gain(ctx):
+    """Sec. 5.1.1: the library's sigma, rmse and gain of every x~_k agree with
+    the oracle's float64 formulas (the sums run in another order: relative
+    1e-10), and repeat bit for bit (fixed reduction order)."""
+    for x, label in ((inputs.spectral_field((29, 22, 37), seed=11, dtype=np.float32), "f32"),
+                     (inputs.blobs_field(24, seed=3), "f64")):
+        r = float(x.max() - x.min())
+        taus = [r * 10.0 ** -(i + 1) for i in range(3)]
+        store = ctx.compress(to_dev(x), taus)
+        xd = to_dev(x)
+        bits = 0
+        for k in range(1, 4):
+            bits += 8 * store.info[k - 1]["bytes"]
+            rate = bits / x.size
+            out = ctx.retrieve(store, k)
+            got = ctx.accuracy_gain(xd, out, rate)
+            assert ctx.accuracy_gain(xd, out, rate) == got
+            want = driver.accuracy_gain(x, out.cpu().numpy(), rate)
+            say("gain %s k=%d: %s vs oracle %s" % (label, k, got, want))
+            assert got[0] == pytest.approx(want[0], rel=1e-10)
+            assert got[1] == pytest.approx(want[1], rel=1e-10)
+            assert got[2] == pytest.approx(want[2], rel=1e-10, abs=1e-10)
+        assert ctx.accuracy_gain(xd, xd, 1.0)[2] == float("inf")

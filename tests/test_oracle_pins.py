@@ -488,3 +488,35 @@ def test_corrupt_streams_rejected():
         bad[pos] ^= np.uint8(1 << int(rng.integers(0, 8)))
         rc, _ = orc.decode_rc(bad, x.shape, x.dtype)
         assert rc in (orc.OK, orc.E_CORRUPT)
+
+
+def test_accuracy_gain_closed_forms():
+    """Sec. 5.1.1: gain = log2(sigma / rmse) - rate, pinned by fields whose
+    standard deviation and error are known exactly."""
+    # the digits 0..9 repeated: variance (10^2 - 1) / 12; a constant offset c
+    # as the error: rmse = |c|
+    x = np.tile(np.arange(10, dtype=np.float64), 7)
+    for c, rate in ((0.25, 3.0), (-2.0, 0.5)):
+        sigma, rmse, gain = driver.accuracy_gain(x, x + c, rate)
+        assert sigma == pytest.approx(math.sqrt(99.0 / 12.0), rel=1e-15)
+        assert rmse == abs(c)
+        assert gain == pytest.approx(math.log2(math.sqrt(99.0 / 12.0) / abs(c)) - rate, rel=1e-15)
+    # alternating +-1 and x~ = 1.5 x: sigma = 1, rmse = 1/2, gain = 1 - rate
+    a = np.tile([1.0, -1.0], 32)
+    assert driver.accuracy_gain(a, 1.5 * a, 2.0) == (1.0, 0.5, -1.0)
+    # a lossless reconstruction has infinite gain
+    assert driver.accuracy_gain(a, a, 5.0)[2] == math.inf
+
+
+def test_accuracy_gain_invariants():
+    """Scaling data and error by a power of two leaves the gain unchanged, and
+    halving the error raises it by exactly one bit."""
+    rng = np.random.default_rng(5)
+    x = rng.normal(size=4096)
+    e = rng.normal(scale=1e-3, size=4096)
+    g0 = driver.accuracy_gain(x, x + e, 1.5)[2]
+    g1 = driver.accuracy_gain(8.0 * x, 8.0 * (x + e), 1.5)[2]
+    assert g1 == pytest.approx(g0, abs=1e-12)
+    s0, r0, _ = driver.accuracy_gain(x, x - e, 0.0)
+    s1, r1, _ = driver.accuracy_gain(x, x - e / 2, 0.0)
+    assert math.log2(s1 / r1) - math.log2(s0 / r0) == pytest.approx(1.0, abs=1e-12)
