@@ -156,6 +156,16 @@ pmc_status pmc_retrieve(pmc_ctx* ctx, const pmc_store* s, int k, void* d_out, vo
  * (incremental refinement without decoder state, Sec. 4.2 last paragraph). */
 pmc_status pmc_refine(pmc_ctx* ctx, const pmc_store* s, int k_from, int k_to, void* d_inout, void* d_ws,
                       size_t ws_bytes);
+/* Region retrieval (Sec. 6.1: blocks decoded on demand while the components
+ * stay compressed): x~_k restricted to the box lo[a] <= coordinate < hi[a]
+ * (a = 0, 1, 2 for x, y, z; x fastest, as in pmc_field).  Only the blocks
+ * meeting the box are decoded; d_out receives the box alone, dense, x
+ * fastest: (hi[0]-lo[0]) * (hi[1]-lo[1]) * (hi[2]-lo[2]) values of the
+ * field's type, bit-identical to the same samples of pmc_retrieve(k).
+ * 1 <= k <= n; each axis needs lo < hi <= extent (else PMC_E_ARG).  d_ws as
+ * for pmc_retrieve; enqueued on the context's stream. */
+pmc_status pmc_retrieve_box(pmc_ctx* ctx, const pmc_store* s, int k, const uint64_t lo[3], const uint64_t hi[3],
+                            void* d_out, void* d_ws, size_t ws_bytes);
 
 /* ---- persistence --------------------------------------------------------
  * Serialise metadata and streams to host memory (synchronises).  With

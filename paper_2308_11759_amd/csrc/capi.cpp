@@ -556,6 +556,77 @@ static pmc_status decode_range(pmc_ctx* ctx, const pmc_store* s, int k0, int k1,
   return PMC_OK;
 }
 
+pmc_status pmc_retrieve_box(pmc_ctx* ctx, const pmc_store* s, int k, const uint64_t lo[3], const uint64_t hi[3],
+                            void* d_out, void* d_ws, size_t ws_bytes) {
+  if (!ctx) return PMC_E_ARG;
+  if (!s || !d_out || !lo || !hi) return fail(ctx, PMC_E_ARG, "null argument");
+  if (k < 1 || k > s->n) return fail(ctx, PMC_E_ARG, "k must be in [1, %d]", s->n);
+  const uint64_t dims[3] = {s->g.nx, s->g.ny, s->g.nz};
+  for (int a = 0; a < 3; ++a)
+    if (!(lo[a] < hi[a] && hi[a] <= dims[a])) return fail(ctx, PMC_E_ARG, "box axis %d outside the field", a);
+  if (!d_ws || ws_bytes < pmc_decode_ws_bytes()) return fail(ctx, PMC_E_NOMEM, "decode needs 256 bytes of workspace");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hipfail(ctx, e, "hipSetDevice");
+  unsigned int* status = (unsigned int*)d_ws;
+  if ((e = launch_fill64((unsigned long long*)status, 1, 0ull, ctx->stream)) != hipSuccess)
+    return hipfail(ctx, e, "status init");
+  BoxArgs b{};
+  for (int a = 0; a < 3; ++a) {
+    b.lo[a] = lo[a];
+    b.hi[a] = hi[a];
+    b.blo[a] = lo[a] / 4;
+    b.bhi[a] = (hi[a] + 3) / 4;
+  }
+  b.waves_per_row = (uint32_t)((b.bhi[0] - b.blo[0] + 63) / 64 + 1);  // a row of blocks meets at most this many waves
+  const void* in = nullptr;
+  for (int i0 = 0; i0 < k; i0 += kMaxDecode) {
+    const int i1 = i0 + kMaxDecode < k ? i0 + kMaxDecode : k;
+    uint64_t span = 0;
+    for (int i = i0; i < i1; ++i) span = std::max(span, s->max_span[i]);
+    if (s->f.dtype == PMC_F32) {
+      DecArgs<float> a{};
+      for (int i = i0; i < i1; ++i) {
+        a.s[i - i0] = s->d_base + s->offset[i];
+        a.aux[i - i0] = (const uint32_t*)(s->d_base + s->aux_offset[i]);
+        a.words[i - i0] = s->words[i];
+        a.minexp[i - i0] = s->minexp[i];
+        if (i > 0) a.relmask |= 1u << (i - i0);
+      }
+      a.ncomp = i1 - i0;
+      a.in = (const float*)in;
+      a.out = (float*)d_out;
+      a.g = s->g;
+      a.status = status;
+      e = launch_decode_box<float>(a, b, span, ctx->stream);
+    } else {
+      DecArgs<double> a{};
+      for (int i = i0; i < i1; ++i) {
+        a.s[i - i0] = s->d_base + s->offset[i];
+        a.aux[i - i0] = (const uint32_t*)(s->d_base + s->aux_offset[i]);
+        a.words[i - i0] = s->words[i];
+        a.minexp[i - i0] = s->minexp[i];
+        if (i > 0) a.relmask |= 1u << (i - i0);
+      }
+      a.ncomp = i1 - i0;
+      a.in = (const double*)in;
+      a.out = (double*)d_out;
+      a.g = s->g;
+      a.status = status;
+      e = launch_decode_box<double>(a, b, span, ctx->stream);
+    }
+    if (e != hipSuccess) return hipfail(ctx, e, "decode");
+    in = d_out;
+  }
+  if (ctx->sync_check) {
+    unsigned int h = 0;
+    if ((e = hipMemcpyAsync(&h, status, 4, hipMemcpyDeviceToHost, ctx->stream)) != hipSuccess)
+      return hipfail(ctx, e, "status copy");
+    if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return hipfail(ctx, e, "sync");
+    if (h) return fail(ctx, PMC_E_CORRUPT, "malformed stream");
+  }
+  return PMC_OK;
+}
+
 pmc_status pmc_retrieve(pmc_ctx* ctx, const pmc_store* s, int k, void* d_out, void* d_ws, size_t ws_bytes) {
   if (!ctx) return PMC_E_ARG;
   if (!s || !d_out) return fail(ctx, PMC_E_ARG, "null argument");

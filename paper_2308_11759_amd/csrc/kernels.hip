@@ -153,6 +153,31 @@ __device__ __forceinline__ void store_row(T* __restrict__ f, const Geo& g, const
   }
 }
 
+// the samples of a block that lie in a box, read from / written to the box's
+// own dense array (x fastest); samples outside the field are outside every
+// box, and samples of the block outside the box are not touched (read as +0)
+template <class T>
+__device__ __forceinline__ void load_box(const T* __restrict__ f, const BoxArgs& bx, const BlockPos& b, T v[64]) {
+  const uint64_t nx = bx.hi[0] - bx.lo[0], ny = bx.hi[1] - bx.lo[1];
+#pragma unroll
+  for (int l = 0; l < 64; ++l) {
+    const uint64_t x = b.x0 + (l & 3), y = b.y0 + ((l >> 2) & 3), z = b.z0 + (l >> 4);
+    v[l] = (x >= bx.lo[0] && x < bx.hi[0] && y >= bx.lo[1] && y < bx.hi[1] && z >= bx.lo[2] && z < bx.hi[2])
+               ? f[(x - bx.lo[0]) + nx * ((y - bx.lo[1]) + ny * (z - bx.lo[2]))]
+               : (T)0;
+  }
+}
+template <class T>
+__device__ __forceinline__ void store_box(T* __restrict__ f, const BoxArgs& bx, const BlockPos& b, const T v[64]) {
+  const uint64_t nx = bx.hi[0] - bx.lo[0], ny = bx.hi[1] - bx.lo[1];
+#pragma unroll
+  for (int l = 0; l < 64; ++l) {
+    const uint64_t x = b.x0 + (l & 3), y = b.y0 + ((l >> 2) & 3), z = b.z0 + (l >> 4);
+    if (x >= bx.lo[0] && x < bx.hi[0] && y >= bx.lo[1] && y < bx.hi[1] && z >= bx.lo[2] && z < bx.hi[2])
+      f[(x - bx.lo[0]) + nx * ((y - bx.lo[1]) + ny * (z - bx.lo[2]))] = v[l];
+  }
+}
+
 // load row r of a block (edge replication as in load_block); a null field
 // reads as +0
 template <class T>
@@ -817,18 +842,25 @@ __device__ __forceinline__ void stage_span(const uint32_t* payload, const Span& 
 // plus components [0, ncomp) of the given streams, left to right.  Every lane
 // runs the component loop (the staging copies are shared); false on a
 // malformed stream.
-template <class T, bool kStaged>
+template <class T, bool kStaged, bool kBox = false>
 __device__ __forceinline__ bool decode_wave(const Geo& g, const uint8_t* const* s, const uint32_t* const* aux,
                                             const uint64_t* words, const int* minexp, int ncomp, uint32_t relmask,
-                                            const T* in, T* out, uint64_t w, const uint8_t* sq, uint32_t* stage) {
+                                            const T* in, T* out, uint64_t w, const uint8_t* sq, uint32_t* stage,
+                                            const BoxArgs* box = nullptr) {
   const uint32_t lane = threadIdx.x;
   const uint64_t blk = w * 64 + lane;
-  const bool active = blk < g.nblocks;
+  bool active = blk < g.nblocks;
   const BlockPos bp = block_pos(g, active ? blk : 0);
+  if constexpr (kBox) {  // only this row's blocks in the box are decoded (each by
+                         // one workgroup); the wave still stages its chunks,
+                         // whose bit offsets locate every block
+    active = active && blk >= box->row_first && blk <= box->row_last;
+  }
   const uint64_t chunk = blk / kChunkBlocks;
   T acc[64];
   if (in && active) {
-    load_block(in, g, opaque_pos(bp), acc);
+    if constexpr (kBox) load_box(in, *box, bp, acc);
+    else load_block(in, g, opaque_pos(bp), acc);
   } else {
 #pragma unroll
     for (int l = 0; l < 64; ++l) acc[l] = (T)0;
@@ -925,7 +957,10 @@ __device__ __forceinline__ bool decode_wave(const Geo& g, const uint8_t* const* 
     }
   }
   // the block position is recomputed here rather than kept in registers
-  if (active && ok) store_block(out, g, block_pos(g, opaque(w) * 64 + lane), acc);
+  if (active && ok) {
+    if constexpr (kBox) store_box(out, *box, block_pos(g, opaque(w) * 64 + lane), acc);
+    else store_block(out, g, block_pos(g, opaque(w) * 64 + lane), acc);
+  }
   return ok || !active;
 }
 
@@ -936,6 +971,29 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
   squeeze_table(s_squeeze);
   if (!decode_wave<T, kStaged>(a.g, a.s, a.aux, a.words, a.minexp, a.ncomp, a.relmask, a.in, a.out, blockIdx.x,
                                s_squeeze, s_stage))
+    atomicOr(a.status, 1u);
+}
+
+// region retrieval: workgroup (row, i) decodes the i-th wave of the box's
+// block row `row` (rows in y-then-z order); waves past the row's last block
+// exit.  a.in / a.out are box arrays (a.in: the box after earlier components).
+// A wave whose blocks span several box rows (narrow fields) is staged once
+// per row, and each row's workgroup decodes only that row's blocks.
+template <class T, bool kStaged>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_decode_box(
+    DecArgs<T> a, BoxArgs b) {
+  __shared__ uint8_t s_squeeze[256];
+  __shared__ uint32_t s_stage[kStaged ? kStageWords + 3 : 1];
+  const uint32_t row = blockIdx.x / b.waves_per_row, i = blockIdx.x % b.waves_per_row;
+  const uint64_t nry = b.bhi[1] - b.blo[1];
+  const uint64_t by = b.blo[1] + row % nry, bz = b.blo[2] + row / nry;
+  b.row_first = (bz * a.g.nby + by) * a.g.nbx + b.blo[0];
+  b.row_last = (bz * a.g.nby + by) * a.g.nbx + b.bhi[0] - 1;
+  const uint64_t w = b.row_first / 64 + i;
+  if (w > b.row_last / 64) return;  // uniform over the workgroup
+  squeeze_table(s_squeeze);
+  if (!decode_wave<T, kStaged, true>(a.g, a.s, a.aux, a.words, a.minexp, a.ncomp, a.relmask, a.in, a.out, w,
+                                     s_squeeze, s_stage, &b))
     atomicOr(a.status, 1u);
 }
 
@@ -1262,6 +1320,15 @@ template <class T> hipError_t launch_decode(const DecArgs<T>& a, uint64_t max_sp
   else hipLaunchKernelGGL((k_decode<T, false>), dim3((uint32_t)wgs), dim3(64), 0, s, a);
   return hipGetLastError();
 }
+template <class T>
+hipError_t launch_decode_box(const DecArgs<T>& a, const BoxArgs& b, uint64_t max_span, hipStream_t s) {
+  const uint64_t rows = (b.bhi[1] - b.blo[1]) * (b.bhi[2] - b.blo[2]);
+  const uint64_t wgs = rows * b.waves_per_row;
+  if (wgs == 0) return hipSuccess;
+  if (max_span <= kStageWords) hipLaunchKernelGGL((k_decode_box<T, true>), dim3((uint32_t)wgs), dim3(64), 0, s, a, b);
+  else hipLaunchKernelGGL((k_decode_box<T, false>), dim3((uint32_t)wgs), dim3(64), 0, s, a, b);
+  return hipGetLastError();
+}
 template <class T> hipError_t launch_decode_queries(const ServeArgs& a, uint64_t max_span, hipStream_t s) {
   if (a.nwaves == 0) return hipSuccess;
   if (max_span <= kStageWords) hipLaunchKernelGGL((k_decode_queries<T, true>), dim3(a.nwaves), dim3(64), 0, s, a);
@@ -1386,6 +1453,8 @@ template hipError_t launch_aux<float>(const AuxArgs&, hipStream_t);
 template hipError_t launch_aux<double>(const AuxArgs&, hipStream_t);
 template hipError_t launch_range<float>(const float*, uint64_t, unsigned long long*, hipStream_t);
 template hipError_t launch_range<double>(const double*, uint64_t, unsigned long long*, hipStream_t);
+template hipError_t launch_decode_box<float>(const DecArgs<float>&, const BoxArgs&, uint64_t, hipStream_t);
+template hipError_t launch_decode_box<double>(const DecArgs<double>&, const BoxArgs&, uint64_t, hipStream_t);
 template hipError_t launch_sum_sq<float>(const float*, const float*, double, uint64_t, double*, double*, hipStream_t);
 template hipError_t launch_sum_sq<double>(const double*, const double*, double, uint64_t, double*, double*,
                                           hipStream_t);

@@ -98,6 +98,17 @@ template <class T> struct DecArgs {
   unsigned int* status;  // bit 0: malformed stream
 };
 
+// a box [lo, hi) of the field (value coordinates x, y, z) for region
+// retrieval: blo/bhi are its block ranges; the output is the box alone, dense,
+// x fastest.  Work: one workgroup per (block row of the box, wave of that row)
+struct BoxArgs {
+  uint64_t lo[3], hi[3];
+  uint64_t blo[3], bhi[3];
+  uint32_t waves_per_row;
+  uint32_t pad;
+  uint64_t row_first, row_last;  // set per workgroup: the blocks of its row inside the box
+};
+
 // one retrieval query of a server step: out = in (or +0) + components
 // [0, ncomp) of the listed streams
 struct QueryDev {
@@ -179,6 +190,8 @@ template <class T> hipError_t launch_aux(const AuxArgs& a, hipStream_t s);
 template <class T> hipError_t launch_decode_queries(const ServeArgs& a, uint64_t max_span, hipStream_t s);
 template <class T> hipError_t launch_pack(const PackArgs& a, hipStream_t s);
 template <class T> hipError_t launch_decode(const DecArgs<T>& a, uint64_t max_span, hipStream_t s);
+// components [0, a.ncomp) of the blocks meeting the box, written to a.out as the box alone
+template <class T> hipError_t launch_decode_box(const DecArgs<T>& a, const BoxArgs& b, uint64_t max_span, hipStream_t s);
 uint64_t stage_words();  // capacity of the decoder's LDS staging buffer, in words
 template <class T> hipError_t launch_range(const T* x, uint64_t n, unsigned long long* out, hipStream_t s);
 hipError_t launch_fill64(unsigned long long* p, uint64_t n, unsigned long long v, hipStream_t s);

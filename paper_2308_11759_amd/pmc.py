@@ -57,6 +57,7 @@ SIGNATURES = {
     "pmc_ctx_set_option": (_int, [_vp, _int, _int]),
     "pmc_range": (_int, [_vp, _P(Field), _vp, _vp, _sz, _P(_dbl), _P(_dbl), _P(_u64)]),
     "pmc_stats_ws_bytes": (_sz, []),
+    "pmc_retrieve_box": (_int, [_vp, _vp, _int, _P(_u64), _P(_u64), _vp, _vp, _sz]),
     "pmc_accuracy_gain": (_int, [_vp, _P(Field), _vp, _vp, _dbl, _vp, _sz, _P(_dbl)]),
     "pmc_compress_sizes": (_int, [_P(Field), _int, _P(_sz), _P(_sz)]),
     "pmc_compress": (_int, [_vp, _P(Field), _vp, _int, _P(_dbl), _vp, _sz, _vp, _sz, _P(_vp)]),
@@ -247,6 +248,21 @@ class Context:
             out = torch.empty(store.shape, dtype=store.dtype, device=self.device)
         self._check(self.lib.pmc_retrieve(self.handle, store.handle, int(k), ctypes.c_void_p(out.data_ptr()),
                                           ctypes.c_void_p(self._dec_ws.data_ptr()), self._dec_ws.numel()))
+        return out
+
+    def retrieve_box(self, store, k, lo, hi, out=None):
+        """x~_k on the box lo <= (x, y, z) < hi only (Sec. 6.1); returns a
+        (z, y, x)-shaped tensor of the box."""
+        lo = [int(v) for v in lo]
+        hi = [int(v) for v in hi]
+        shape = (hi[2] - lo[2], hi[1] - lo[1], hi[0] - lo[0])
+        if out is None:
+            out = torch.empty(shape, dtype=store.dtype, device=self.device)
+        elif out.dtype != store.dtype or out.numel() != shape[0] * shape[1] * shape[2] or not out.is_contiguous():
+            raise ValueError("out must be a contiguous %s tensor of %s values" % (store.dtype, shape))
+        self._check(self.lib.pmc_retrieve_box(self.handle, store.handle, int(k), (ctypes.c_uint64 * 3)(*lo),
+                                              (ctypes.c_uint64 * 3)(*hi), ctypes.c_void_p(out.data_ptr()),
+                                              ctypes.c_void_p(self._dec_ws.data_ptr()), self._dec_ws.numel()))
         return out
 
     def refine(self, store, k_from, k_to, xt):

@@ -314,3 +314,34 @@ def test_accuracy_gain(ctx):
             assert got[1] == pytest.approx(want[1], rel=1e-10)
             assert got[2] == pytest.approx(want[2], rel=1e-10, abs=1e-10)
         assert ctx.accuracy_gain(xd, xd, 1.0)[2] == float("inf")
+
+
+def test_region_retrieval(ctx):
+    """Sec. 6.1: x~_k on a box, decoding only the blocks that meet it, equals
+    the same samples of the oracle's x~_k: boxes inside one block, across
+    block and chunk boundaries, at the ragged far edge, and the whole field;
+    a store of 20 components takes two fused launches, the second continuing
+    from the box the first wrote."""
+    from paper_2308_11759_amd import pmc
+    x = inputs.spectral_field((29, 22, 37), seed=11, dtype=np.float32)  # (z, y, x)
+    taus = [2.0 ** (-3 * (i + 1)) for i in range(6)]
+    comps, meta, recon = oracle_run(x, taus)
+    store = ctx.compress(to_dev(x), taus)
+    boxes = [((0, 0, 0), (37, 22, 29)), ((5, 6, 7), (6, 7, 8)), ((3, 1, 2), (30, 21, 17)),
+             ((33, 18, 25), (37, 22, 29)), ((0, 4, 8), (37, 5, 9))]
+    for lo, hi in boxes:
+        for k in (1, 3, 6):
+            got = ctx.retrieve_box(store, k, lo, hi).cpu().numpy()
+            want = recon[k - 1][lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
+            assert np.array_equal(got, want), (lo, hi, k)
+    with pytest.raises(pmc.PmcError):
+        ctx.retrieve_box(store, 1, (0, 0, 0), (38, 22, 29))
+    with pytest.raises(pmc.PmcError):
+        ctx.retrieve_box(store, 1, (4, 0, 0), (4, 22, 29))
+    # more components than one launch fuses
+    y = inputs.spectral_field((8, 12, 20), seed=12, dtype=np.float64)
+    taus = [2.0 ** (-2 * (i + 1)) for i in range(20)]
+    comps, meta, recon = oracle_run(y, taus)
+    store = ctx.compress(to_dev(y), taus)
+    got = ctx.retrieve_box(store, 20, (3, 2, 1), (19, 11, 7)).cpu().numpy()
+    assert np.array_equal(got, recon[19][1:7, 2:11, 3:19])
