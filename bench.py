@@ -398,6 +398,47 @@ def main():
         err = float((xd.double() - out.double()).abs().max())
         assert err == store.info[n - 1]["linf"], (err, store.info[n - 1]["linf"])
 
+    # region retrieval (Sec. 6.1): x~_n on a 64^3 box (or the whole field if
+    # smaller), decoding only the blocks that meet it
+    region = None
+    if args.steps > 0 and args.refine_reps > 0:
+        edge = [min(64, d) for d in x.shape[::-1]]  # x, y, z
+        lo = [(d - e) // 2 for d, e in zip(x.shape[::-1], edge)]
+        hi = [l + e for l, e in zip(lo, edge)]
+        box = ctx.retrieve_box(store, n, lo, hi)
+        torch.cuda.synchronize()
+        ev4, ev5 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev4.record()
+        for _ in range(5):
+            ctx.retrieve_box(store, n, lo, hi, out=box)
+        ev5.record()
+        torch.cuda.synchronize()
+        full = ctx.retrieve(store, n)
+        assert torch.equal(box, full[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]])
+        del full
+        region = {"box_lo_xyz": lo, "box_hi_xyz": hi, "k": n, "ms": ev4.elapsed_time(ev5) / 5,
+                  "box_fraction": float(np.prod(edge)) / x.size}
+
+    # lossless limit (Sec. 5.1.3): the bench's schedule, then steps of 2^-16
+    # down to 2^-152, below every float32 difference; report the first k with
+    # x~_k == x bit for bit, and the ratio there
+    lossless = None
+    if args.steps > 0 and args.refine_reps > 0 and dt == np.float32 and args.workload.startswith("bulk"):
+        ltaus = list(taus) + [taus[-1] * 2.0 ** (-16 * j) for j in range(1, 9)]
+        lws, lcap = ctx.compress_sizes(xd, len(ltaus))
+        lstreams = torch.empty(lcap * len(ltaus), dtype=torch.uint8, device=dev)
+        lstore = ctx.compress(xd, ltaus, streams=lstreams)
+        first = None
+        for k in range(1, len(ltaus) + 1):
+            if torch.equal(ctx.retrieve(lstore, k, out=out), xd):  # zero error (the sign of zero is not kept)
+                first = k
+                break
+        if first is not None:
+            nbytes = sum(m["bytes"] for m in lstore.info[:first])
+            lossless = {"components": len(ltaus), "first_exact_k": first, "tau_first_exact": ltaus[first - 1],
+                        "bytes": nbytes, "ratio": N * s / nbytes}
+        del lstore, lstreams
+
     if args.copy_calibration:
         src = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
@@ -431,6 +472,8 @@ def main():
         "retrieve_all_k_gbs": N * s * n / (dec_ms / 1e3) / 1e9 if dec_ms else None,
         "refine_chain_gbs": N * s * n / (refine_ms / 1e3) / 1e9 if refine_ms else None,
         "refine_chain_ms": refine_ms,
+        "region_retrieval": region,
+        "lossless": lossless,
         "rates_bits_per_value": [round(8.0 * m["bytes"] / N, 3) for m in info],
         "linf": [m["linf"] for m in info],
         "accuracy_gain": gain,
