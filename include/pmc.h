@@ -105,6 +105,22 @@ size_t pmc_stats_ws_bytes(void);
 pmc_status pmc_accuracy_gain(pmc_ctx* ctx, const pmc_field* f, const void* d_x, const void* d_xt, double rate,
                              void* d_ws, size_t ws_bytes, double out[3]);
 
+/* ---- a second compressor: the float32 cast of Sec. 3 ------------------------
+ * The multi-component driver with C(e) = fl32(e) (round to nearest even
+ * float32) and D(y) = y in the field's type; tolerances play no part.  For a
+ * float64 field the components form a floating-point expansion (three
+ * reproduce every normal double).  pmc_cast_compress runs all n components
+ * (1 <= n <= 32) of Alg. 1: component i (i = 0..n-1) goes to d_comps + i * N
+ * (N = values of the field; the caller owns the n * N floats), and linf[i]
+ * (host, optional) receives max |x - x~_{i+1}| in float64 (synchronises).
+ * d_ws: at least 256 bytes of device scratch.  pmc_cast_retrieve writes
+ * x~_k = (...((+0 + y_1) + y_2) ...) + y_k, 0 <= k <= 32, in the field's type
+ * (enqueued only).  Non-finite input gives unspecified errors.  Errors:
+ * PMC_E_ARG, PMC_E_NOMEM, PMC_E_HIP. */
+pmc_status pmc_cast_compress(pmc_ctx* ctx, const pmc_field* f, const void* d_x, int n, float* d_comps, void* d_ws,
+                             size_t ws_bytes, double* linf);
+pmc_status pmc_cast_retrieve(pmc_ctx* ctx, const pmc_field* f, const float* d_comps, int k, void* d_out);
+
 /* ---- multi-component compression (Alg. 1, Sec. 4.1) ----------------------
  * Sizes for pmc_compress: device workspace bytes, and the capacity one
  * component's stream can need in the worst case (all blocks raw).  The total

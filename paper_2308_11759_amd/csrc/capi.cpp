@@ -284,6 +284,46 @@ pmc_status pmc_accuracy_gain(pmc_ctx* ctx, const pmc_field* f, const void* d_x, 
   return PMC_OK;
 }
 
+pmc_status pmc_cast_compress(pmc_ctx* ctx, const pmc_field* f, const void* d_x, int n, float* d_comps, void* d_ws,
+                             size_t ws_bytes, double* linf) {
+  if (!ctx) return PMC_E_ARG;
+  Geo g;
+  if (!make_geo(f, &g) || !d_x || !d_comps) return fail(ctx, PMC_E_ARG, "bad field or null pointer");
+  if (n < 1 || n > kMaxComps) return fail(ctx, PMC_E_ARG, "n must be in [1, %d]", kMaxComps);
+  if (!d_ws || ws_bytes < 8 * (size_t)kMaxComps)
+    return fail(ctx, PMC_E_NOMEM, "cast compression needs %d bytes of workspace", 8 * kMaxComps);
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hipfail(ctx, e, "hipSetDevice");
+  const uint64_t N = g.nx * g.ny * g.nz;
+  unsigned long long* lb = (unsigned long long*)d_ws;
+  if ((e = launch_fill64(lb, (uint64_t)n, 0ull, ctx->stream)) != hipSuccess) return hipfail(ctx, e, "fill");
+  if (f->dtype == PMC_F32) e = launch_cast_encode<float>((const float*)d_x, N, n, d_comps, lb, ctx->stream);
+  else e = launch_cast_encode<double>((const double*)d_x, N, n, d_comps, lb, ctx->stream);
+  if (e != hipSuccess) return hipfail(ctx, e, "cast encode");
+  if (linf) {
+    std::vector<unsigned long long> h(n);
+    if ((e = hipMemcpyAsync(h.data(), lb, 8 * (size_t)n, hipMemcpyDeviceToHost, ctx->stream)) != hipSuccess)
+      return hipfail(ctx, e, "copy");
+    if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return hipfail(ctx, e, "sync");
+    for (int i = 0; i < n; ++i) std::memcpy(&linf[i], &h[i], 8);
+  }
+  return PMC_OK;
+}
+
+pmc_status pmc_cast_retrieve(pmc_ctx* ctx, const pmc_field* f, const float* d_comps, int k, void* d_out) {
+  if (!ctx) return PMC_E_ARG;
+  Geo g;
+  if (!make_geo(f, &g) || !d_comps || !d_out) return fail(ctx, PMC_E_ARG, "bad field or null pointer");
+  if (k < 0 || k > kMaxComps) return fail(ctx, PMC_E_ARG, "k must be in [0, %d]", kMaxComps);
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hipfail(ctx, e, "hipSetDevice");
+  const uint64_t N = g.nx * g.ny * g.nz;
+  if (f->dtype == PMC_F32) e = launch_cast_decode<float>(d_comps, N, k, (float*)d_out, ctx->stream);
+  else e = launch_cast_decode<double>(d_comps, N, k, (double*)d_out, ctx->stream);
+  if (e != hipSuccess) return hipfail(ctx, e, "cast decode");
+  return PMC_OK;
+}
+
 pmc_status pmc_compress_sizes(const pmc_field* f, int n, size_t* ws_bytes, size_t* stream_cap_per_comp) {
   Geo g;
   if (!make_geo(f, &g) || n < 1 || n > kMaxComps) return PMC_E_ARG;

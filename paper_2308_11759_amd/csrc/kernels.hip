@@ -1402,6 +1402,74 @@ hipError_t launch_sum_sq(const T* a, const T* b, double shift, uint64_t n, doubl
 }
 uint64_t sum_sq_ws_bytes() { return (uint64_t)kSumGroups * 16 + 256; }
 
+// ---------------------------------------------------------------------------
+// Sec. 3's scalar special case as a second compressor behind the same
+// driver: C(e) = fl32(e) (round to nearest even float32), D(y) = y in the
+// field's type.  One thread per value runs all n components of Alg. 1 in
+// registers: e = x - x~ in the field's type, y = fl32(e), x~ = x~ + y; the
+// measured errors max |x - x~_i| (float64) are raised per wave with atomics on
+// their bit patterns (non-negative doubles order like their bits).
+template <class T>
+__global__ __launch_bounds__(256) void k_cast_encode(const T* __restrict__ x, uint64_t N, int n,
+                                                     float* __restrict__ comps, unsigned long long* linf_bits) {
+  double mx[kMaxComps];
+#pragma unroll
+  for (int i = 0; i < kMaxComps; ++i) mx[i] = 0.0;
+  const uint64_t stride = (uint64_t)gridDim.x * 256;
+  for (uint64_t j = (uint64_t)blockIdx.x * 256 + threadIdx.x; j < N; j += stride) {
+    const T xj = x[j];
+    T xt = (T)0;
+#pragma unroll
+    for (int i = 0; i < kMaxComps; ++i) {
+      if (i < n) {
+        const float y = (float)(xj - xt);  // the residual in the field's type, then rounded once
+        comps[(uint64_t)i * N + j] = y;
+        xt = xt + (T)y;
+        const double err = __builtin_fabs((double)xj - (double)xt);
+        mx[i] = err > mx[i] ? err : mx[i];
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kMaxComps; ++i) {
+    if (i < n) {
+      const double wm = wave_max(mx[i]);
+      const unsigned long long wb = (unsigned long long)__double_as_longlong(wm);
+      if ((threadIdx.x & 63) == 0 && wb > *(volatile unsigned long long*)&linf_bits[i]) atomicMax(&linf_bits[i], wb);
+    }
+  }
+}
+// x~_k = (...((+0 + y_1) + y_2) ...) + y_k in the field's type
+template <class T>
+__global__ __launch_bounds__(256) void k_cast_decode(const float* __restrict__ comps, uint64_t N, int k,
+                                                     T* __restrict__ out) {
+  const uint64_t stride = (uint64_t)gridDim.x * 256;
+  for (uint64_t j = (uint64_t)blockIdx.x * 256 + threadIdx.x; j < N; j += stride) {
+    T acc = (T)0;
+    for (int i = 0; i < k; ++i) acc = acc + (T)comps[(uint64_t)i * N + j];
+    out[j] = acc;
+  }
+}
+template <class T>
+hipError_t launch_cast_encode(const T* x, uint64_t N, int n, float* comps, unsigned long long* linf, hipStream_t s) {
+  uint64_t wgs = (N + 255) / 256;
+  if (wgs > 4096) wgs = 4096;
+  if (wgs == 0) wgs = 1;
+  hipLaunchKernelGGL(k_cast_encode<T>, dim3((uint32_t)wgs), dim3(256), 0, s, x, N, n, comps, linf);
+  return hipGetLastError();
+}
+template <class T> hipError_t launch_cast_decode(const float* comps, uint64_t N, int k, T* out, hipStream_t s) {
+  uint64_t wgs = (N + 255) / 256;
+  if (wgs > 4096) wgs = 4096;
+  if (wgs == 0) wgs = 1;
+  hipLaunchKernelGGL(k_cast_decode<T>, dim3((uint32_t)wgs), dim3(256), 0, s, comps, N, k, out);
+  return hipGetLastError();
+}
+template hipError_t launch_cast_encode<float>(const float*, uint64_t, int, float*, unsigned long long*, hipStream_t);
+template hipError_t launch_cast_encode<double>(const double*, uint64_t, int, float*, unsigned long long*, hipStream_t);
+template hipError_t launch_cast_decode<float>(const float*, uint64_t, int, float*, hipStream_t);
+template hipError_t launch_cast_decode<double>(const float*, uint64_t, int, double*, hipStream_t);
+
 template <class T> hipError_t launch_aux(const AuxArgs& a, hipStream_t s) {
   const uint64_t wgs = (a.g.nchunks + 63) / 64;
   hipLaunchKernelGGL(k_aux<T>, dim3((uint32_t)wgs), dim3(64), 0, s, a);

@@ -200,6 +200,11 @@ hipError_t launch_fill64(unsigned long long* p, uint64_t n, unsigned long long v
 template <class T>
 hipError_t launch_sum_sq(const T* a, const T* b, double shift, uint64_t n, double* ws, double* out, hipStream_t s);
 uint64_t sum_sq_ws_bytes();
+// the float32-cast compressor: comps holds n components of N values each;
+// linf: n zeroed bit patterns of the measured errors (raised with atomics)
+template <class T>
+hipError_t launch_cast_encode(const T* x, uint64_t N, int n, float* comps, unsigned long long* linf, hipStream_t s);
+template <class T> hipError_t launch_cast_decode(const float* comps, uint64_t N, int k, T* out, hipStream_t s);
 
 // capacity of one chunk's staging slot in 32-bit words
 inline uint64_t chunk_cap_words_host(int dtype) {

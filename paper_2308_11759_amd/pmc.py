@@ -58,6 +58,8 @@ SIGNATURES = {
     "pmc_range": (_int, [_vp, _P(Field), _vp, _vp, _sz, _P(_dbl), _P(_dbl), _P(_u64)]),
     "pmc_stats_ws_bytes": (_sz, []),
     "pmc_retrieve_box": (_int, [_vp, _vp, _int, _P(_u64), _P(_u64), _vp, _vp, _sz]),
+    "pmc_cast_compress": (_int, [_vp, _P(Field), _vp, _int, _vp, _vp, _sz, _P(_dbl)]),
+    "pmc_cast_retrieve": (_int, [_vp, _P(Field), _vp, _int, _vp]),
     "pmc_accuracy_gain": (_int, [_vp, _P(Field), _vp, _vp, _dbl, _vp, _sz, _P(_dbl)]),
     "pmc_compress_sizes": (_int, [_P(Field), _int, _P(_sz), _P(_sz)]),
     "pmc_compress": (_int, [_vp, _P(Field), _vp, _int, _P(_dbl), _vp, _sz, _vp, _sz, _P(_vp)]),
@@ -208,6 +210,29 @@ class Context:
                                                ctypes.c_void_p(xt.data_ptr()), float(rate),
                                                ctypes.c_void_p(ws.data_ptr()), ws.numel(), out))
         return out[0], out[1], out[2]
+
+    def cast_compress(self, x, n):
+        """Sec. 3's float32-cast compressor: (components as an (n,) + x.shape
+        float32 tensor, measured errors max |x - x~_i|)."""
+        f = field_of(x)
+        comps = torch.empty((int(n),) + tuple(x.shape), dtype=torch.float32, device=self.device)
+        ws = self._workspace(256)
+        linf = (ctypes.c_double * int(n))()
+        self._check(self.lib.pmc_cast_compress(self.handle, ctypes.byref(f), ctypes.c_void_p(x.data_ptr()), int(n),
+                                               ctypes.c_void_p(comps.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                                               ws.numel(), linf))
+        return comps, list(linf)
+
+    def cast_retrieve(self, comps, k, out):
+        """x~_k of the float32-cast compressor into out (the field's shape and type)."""
+        f = field_of(out)
+        if comps.dtype != torch.float32 or tuple(comps.shape[1:]) != tuple(out.shape) or not comps.is_contiguous():
+            raise ValueError("comps must be a contiguous float32 (n,) + out.shape tensor")
+        if not 0 <= int(k) <= comps.shape[0]:
+            raise ValueError("k out of range")
+        self._check(self.lib.pmc_cast_retrieve(self.handle, ctypes.byref(f), ctypes.c_void_p(comps.data_ptr()),
+                                               int(k), ctypes.c_void_p(out.data_ptr())))
+        return out
 
     def compress_sizes(self, x, n):
         f = field_of(x)

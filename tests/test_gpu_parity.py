@@ -345,3 +345,29 @@ def test_region_retrieval(ctx):
     store = ctx.compress(to_dev(y), taus)
     got = ctx.retrieve_box(store, 20, (3, 2, 1), (19, 11, 7)).cpu().numpy()
     assert np.array_equal(got, recon[19][1:7, 2:11, 3:19])
+
+
+def test_cast_compressor_matches_oracle(ctx):
+    """Sec. 3: the same multi-component driver with the float32 cast as the
+    compressor.  Components, measured errors and every x~_k equal the
+    oracle's CastF32Codec bit for bit; for a float64 field of normal values
+    three components reproduce x exactly."""
+    import torch
+    rng = np.random.default_rng(17)
+    x = (rng.normal(size=(9, 10, 11)) * 2.0 ** rng.integers(-40, 40, size=(9, 10, 11))).astype(np.float64)
+    n = 4
+    comps, linf = ctx.cast_compress(to_dev(x), n)
+    ocomps, ometa = driver.compress(x, [1.0, 0.5, 0.25, 0.125], driver.CastF32Codec())
+    out = torch.empty(x.shape, dtype=torch.float64, device="cuda:0")
+    for i in range(n):
+        assert np.array_equal(comps[i].cpu().numpy(), ocomps[i].reshape(x.shape)), i
+        assert linf[i] == ometa[i]["linf"], (i, linf[i], ometa[i]["linf"])
+        got = ctx.cast_retrieve(comps, i + 1, out).cpu().numpy()
+        want = driver.reconstruct(ocomps, i + 1, x.shape, x.dtype, driver.CastF32Codec())
+        assert np.array_equal(got, want), i
+    assert np.array_equal(ctx.cast_retrieve(comps, 3, out).cpu().numpy(), x)
+    assert linf[2] == 0.0
+    # a float32 field: the first component is the field itself
+    y = inputs.spectral_field((7, 9, 13), seed=3, dtype=np.float32)
+    c32, l32 = ctx.cast_compress(to_dev(y), 2)
+    assert np.array_equal(c32[0].cpu().numpy(), y) and l32 == [0.0, 0.0]
