@@ -1409,18 +1409,20 @@ uint64_t sum_sq_ws_bytes() { return (uint64_t)kSumGroups * 16 + 256; }
 // registers: e = x - x~ in the field's type, y = fl32(e), x~ = x~ + y; the
 // measured errors max |x - x~_i| (float64) are raised per wave with atomics on
 // their bit patterns (non-negative doubles order like their bits).
-template <class T>
+// (NC: a compile-time bound on n, so that the per-component maxima have fixed
+// registers; launched with the smallest of 4, 8, 32 that holds n)
+template <class T, int NC>
 __global__ __launch_bounds__(256) void k_cast_encode(const T* __restrict__ x, uint64_t N, int n,
                                                      float* __restrict__ comps, unsigned long long* linf_bits) {
-  double mx[kMaxComps];
+  double mx[NC];
 #pragma unroll
-  for (int i = 0; i < kMaxComps; ++i) mx[i] = 0.0;
+  for (int i = 0; i < NC; ++i) mx[i] = 0.0;
   const uint64_t stride = (uint64_t)gridDim.x * 256;
   for (uint64_t j = (uint64_t)blockIdx.x * 256 + threadIdx.x; j < N; j += stride) {
     const T xj = x[j];
     T xt = (T)0;
 #pragma unroll
-    for (int i = 0; i < kMaxComps; ++i) {
+    for (int i = 0; i < NC; ++i) {
       if (i < n) {
         const float y = (float)(xj - xt);  // the residual in the field's type, then rounded once
         comps[(uint64_t)i * N + j] = y;
@@ -1431,7 +1433,7 @@ __global__ __launch_bounds__(256) void k_cast_encode(const T* __restrict__ x, ui
     }
   }
 #pragma unroll
-  for (int i = 0; i < kMaxComps; ++i) {
+  for (int i = 0; i < NC; ++i) {
     if (i < n) {
       const double wm = wave_max(mx[i]);
       const unsigned long long wb = (unsigned long long)__double_as_longlong(wm);
@@ -1455,7 +1457,9 @@ hipError_t launch_cast_encode(const T* x, uint64_t N, int n, float* comps, unsig
   uint64_t wgs = (N + 255) / 256;
   if (wgs > 4096) wgs = 4096;
   if (wgs == 0) wgs = 1;
-  hipLaunchKernelGGL(k_cast_encode<T>, dim3((uint32_t)wgs), dim3(256), 0, s, x, N, n, comps, linf);
+  if (n <= 4) hipLaunchKernelGGL((k_cast_encode<T, 4>), dim3((uint32_t)wgs), dim3(256), 0, s, x, N, n, comps, linf);
+  else if (n <= 8) hipLaunchKernelGGL((k_cast_encode<T, 8>), dim3((uint32_t)wgs), dim3(256), 0, s, x, N, n, comps, linf);
+  else hipLaunchKernelGGL((k_cast_encode<T, kMaxComps>), dim3((uint32_t)wgs), dim3(256), 0, s, x, N, n, comps, linf);
   return hipGetLastError();
 }
 template <class T> hipError_t launch_cast_decode(const float* comps, uint64_t N, int k, T* out, hipStream_t s) {
