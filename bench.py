@@ -251,6 +251,49 @@ def bench_served(args):
     print(json.dumps(rec))
 
 
+def rate_distortion(ctx, xd, rng, depth, out):
+    """Sec. 5.1's rate-distortion comparison on one field: multi-component
+    stores at granularity Delta in {4, 6, 8} (tau_i = 2^(-Delta i) * range, i = 1
+    .. depth / Delta) against single-component compressions at
+    tau = 2^(-2j) * range (Delta = 2), each run from scratch.  Per point: the
+    rate in bits/value (cumulative for a store), the accuracy gain of Sec.
+    5.1.1 and the measured max error over tau; and for each store point the
+    extra bits/value it spends over the single-component run at the same tau."""
+    N = xd.numel()
+
+    def points(store):
+        res = {"rate": [], "gain": [], "err_over_tau": []}
+        bits = 0
+        for k in range(1, store.n + 1):
+            m = store.info[k - 1]
+            bits += 8 * m["bytes"]
+            ctx.retrieve(store, k, out=out)
+            _, _, g = ctx.accuracy_gain(xd, out, bits / N)
+            res["rate"].append(round(bits / N, 4))
+            res["gain"].append(round(g, 4))
+            res["err_over_tau"].append(round(m["linf"] / m["tau"], 4))
+        return res
+
+    rd = {"depth_bits": depth}
+    single = {"rate": [], "gain": [], "err_over_tau": []}
+    for j in range(1, depth // 2 + 1):
+        st = ctx.compress(xd, [rng * 2.0 ** (-2 * j)])
+        p = points(st)
+        for key in single:
+            single[key] += p[key]
+        del st
+    rd["single_delta2"] = single
+    for delta in (4, 6, 8):
+        st = ctx.compress(xd, [rng * 2.0 ** (-delta * i) for i in range(1, depth // delta + 1)])
+        p = points(st)
+        del st
+        # tau_i of the store equals tau_j of the single runs at j = Delta i / 2
+        p["overhead_bits"] = [round(r - single["rate"][delta * i // 2 - 1], 4)
+                              for i, r in enumerate(p["rate"], start=1)]
+        rd["multi_delta%d" % delta] = p
+    return rd
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -457,6 +500,12 @@ def main():
                 "linf": clinf, "exact_at_3": exact}
         del comps
 
+    # rate-distortion of multi-component stores against single-component
+    # runs (Sec. 5.1), over 24 bits of the range (float32) or 48 (float64)
+    rdist = None
+    if args.steps > 0 and args.refine_reps > 0 and args.workload.startswith("bulk"):
+        rdist = rate_distortion(ctx, xd, rng, 24 if dt == np.float32 else 48, out)
+
     if args.copy_calibration:
         src = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
@@ -493,6 +542,7 @@ def main():
         "region_retrieval": region,
         "lossless": lossless,
         "cast_codec": cast,
+        "rate_distortion": rdist,
         "rates_bits_per_value": [round(8.0 * m["bytes"] / N, 3) for m in info],
         "linf": [m["linf"] for m in info],
         "accuracy_gain": gain,

@@ -107,6 +107,22 @@ __device__ __forceinline__ void load_block(const T* __restrict__ f, const Geo& g
   }
 }
 
+// one 16-byte row piece written with the streaming (nt) cache policy: the
+// partial sums a launch writes are read back only by a later launch, after far
+// more than the L2 holds has passed through it, so keeping them in L2 would
+// only push out lines this launch still reads
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+template <class T>
+__device__ __forceinline__ void store_row16_nt(T* row, T a, T b, T c, T d) {
+  if constexpr (sizeof(T) == 4) {
+    __builtin_nontemporal_store(nt_f4{a, b, c, d}, reinterpret_cast<nt_f4*>(row));
+  } else {
+    __builtin_nontemporal_store(nt_d2{a, b}, reinterpret_cast<nt_d2*>(row));
+    __builtin_nontemporal_store(nt_d2{c, d}, reinterpret_cast<nt_d2*>(row + 2));
+  }
+}
+
 template <class T>
 __device__ __forceinline__ void store_block(T* __restrict__ f, const Geo& g, const BlockPos& b, const T v[64]) {
   const bool vec = b.vx == 4 && g.rows_aligned;
@@ -115,12 +131,7 @@ __device__ __forceinline__ void store_block(T* __restrict__ f, const Geo& g, con
     if ((uint32_t)(r & 3) >= b.vy || (uint32_t)(r >> 2) >= b.vz) continue;
     T* row = const_cast<T*>(row_ptr((const T*)f, g, b, r));
     if (vec) {
-      if constexpr (sizeof(T) == 4) {
-        *reinterpret_cast<float4*>(row) = make_float4(v[4 * r], v[4 * r + 1], v[4 * r + 2], v[4 * r + 3]);
-      } else {
-        *reinterpret_cast<double2*>(row) = make_double2(v[4 * r], v[4 * r + 1]);
-        *reinterpret_cast<double2*>(row + 2) = make_double2(v[4 * r + 2], v[4 * r + 3]);
-      }
+      store_row16_nt(row, v[4 * r], v[4 * r + 1], v[4 * r + 2], v[4 * r + 3]);
     } else {
       row[0] = v[4 * r];
       if (b.vx > 1) row[1] = v[4 * r + 1];
@@ -139,12 +150,7 @@ __device__ __forceinline__ void store_row(T* __restrict__ f, const Geo& g, const
   if (!wfull && ((uint32_t)(r & 3) >= b.vy || (uint32_t)(r >> 2) >= b.vz)) return;
   T* row = wfull ? block_base(f, g, b) + row_step(g, r) : const_cast<T*>(row_ptr((const T*)f, g, b, r));
   if (wfull || (b.vx == 4 && g.rows_aligned)) {
-    if constexpr (sizeof(T) == 4) {
-      *reinterpret_cast<float4*>(row) = make_float4(v[0], v[1], v[2], v[3]);
-    } else {
-      *reinterpret_cast<double2*>(row) = make_double2(v[0], v[1]);
-      *reinterpret_cast<double2*>(row + 2) = make_double2(v[2], v[3]);
-    }
+    store_row16_nt(row, v[0], v[1], v[2], v[3]);
   } else {
     row[0] = v[0];
     if (b.vx > 1) row[1] = v[1];
@@ -294,7 +300,10 @@ template <class T> struct XLds {
 };
 
 // (the direct loads are only issued here: the caller waits, s_waitcnt 0,
-// before reading s_x, and may issue other loads first)
+// before reading s_x, and may issue other loads first.  x is read from memory
+// once per launch, so its loads take the streaming (nt) policy, cache-policy
+// bit 1, leaving L2 to the x~ rows that the check pass reads a second time)
+constexpr int kNt = 2;
 template <class T>
 __device__ __forceinline__ void load_block_lds(const T* __restrict__ f, const Geo& g, const BlockPos& b, T* s_x,
                                                uint32_t lane) {
@@ -305,11 +314,11 @@ __device__ __forceinline__ void load_block_lds(const T* __restrict__ f, const Ge
     const T* row = row_ptr(f, g, b, r);
     if (vec) {
       if constexpr (sizeof(T) == 4) {
-        __builtin_amdgcn_global_load_lds((gmem_void_t*)row, (lds_void_t*)(s_x + r * 256), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((gmem_void_t*)row, (lds_void_t*)(s_x + r * 256), 16, 0, kNt);
       } else {
-        __builtin_amdgcn_global_load_lds((gmem_void_t*)row, (lds_void_t*)(s_x + (r * 2) * 128), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((gmem_void_t*)row, (lds_void_t*)(s_x + (r * 2) * 128), 16, 0, kNt);
         __builtin_amdgcn_global_load_lds((gmem_void_t*)(row + 2), (lds_void_t*)(s_x + (r * 2 + 1) * 128), 16, 0,
-                                         0);
+                                         kNt);
       }
     } else {
       const uint32_t m = b.vx - 1;

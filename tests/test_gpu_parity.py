@@ -371,3 +371,20 @@ def test_cast_compressor_matches_oracle(ctx):
     y = inputs.spectral_field((7, 9, 13), seed=3, dtype=np.float32)
     c32, l32 = ctx.cast_compress(to_dev(y), 2)
     assert np.array_equal(c32[0].cpu().numpy(), y) and l32 == [0.0, 0.0]
+
+
+def test_granularity_schedules_and_single_runs(ctx):
+    """Sec. 5.1's rate-distortion setup: stores at granularity Delta in
+    {4, 6, 8} (tau_i = 2^(-Delta i) * range) and single-component runs at
+    tau = 2^(-2j) * range match the oracle bit for bit; a store's first
+    component is the single-component run at tau_1 (x~_0 = 0 in Alg. 1)."""
+    x = inputs.spectral_field((20, 28, 33), seed=21, dtype=np.float32)
+    r = float(x.max() - x.min())
+    single = {}
+    for j in range(1, 13):
+        store, _, _, _ = check_against_oracle(ctx, x, [r * 2.0 ** (-2 * j)], "single j=%d" % j)
+        single[2 * j] = store.stream(0).cpu().numpy()
+    for delta in (4, 6, 8):
+        taus = [r * 2.0 ** (-delta * i) for i in range(1, 24 // delta + 1)]
+        store, _, _, _ = check_against_oracle(ctx, x, taus, "delta=%d" % delta)
+        assert np.array_equal(store.stream(0).cpu().numpy(), single[delta])

@@ -420,6 +420,21 @@ def test_driver_bound_monotone_and_partial_sums():
             xt_prev = xt
 
 
+def test_first_component_is_a_single_component_run():
+    """Alg. 1 starts from x~_0 = 0, so the first component of any store is
+    the one-component compression of x at tau_1, whatever follows it; and a
+    one-component store's reconstruction is D(C(x, tau)) with error <= tau."""
+    for x, ratio, n in _small_fields():
+        rng_ = float(x.max() - x.min())
+        taus = [rng_ * ratio ** -(i + 1) for i in range(n)]
+        comps, meta = driver.compress(x, taus)
+        one, meta1 = driver.compress(x, taus[:1])
+        assert np.array_equal(one[0], comps[0])
+        assert meta1[0]["linf"] == meta[0]["linf"] <= taus[0]
+        other, _ = driver.compress(x, [taus[0], taus[0] / 3.0])
+        assert np.array_equal(other[0], comps[0])
+
+
 def test_cast_f32_codec_non_overlapping_pair():
     """Sec. 3: with fl = round-to-float32, x = a + b with a, b float32 and
     |b| < ulp(a)/2 (held exactly by the double x) splits into x_1 = a,
