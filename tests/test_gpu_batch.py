@@ -106,3 +106,42 @@ def test_batch_inputs_can_change(setup):
             assert np.array_equal(got[f][i], oracle[f][0][i])
     del moved
     torch.cuda.synchronize()
+
+
+def test_full_batched_config():
+    """The batched workload at its full size, in the tuned schedule the bench
+    times: 256 fields, edges log-uniform in [16, 256] per axis, float32 and
+    float64 alternating, 6 components with tau_i = range_f * 4^-i.  Every
+    field of at most 2^17 values is compared with the oracle's whole-field
+    compression, stream for stream, with x~_6 bit for bit; every field's
+    x~_6 meets Eq. (1) and equals its stored measured error (on the device)."""
+    import torch
+    from paper_2308_11759_amd import pmc
+    shapes = inputs.batched_shapes(256)
+    xs, taus, dev = [], [], []
+    for f, (shape, is32) in enumerate(shapes):
+        x = inputs.spectral_field(shape, seed=100 + f, dtype=np.float32 if is32 else np.float64)
+        r = float(x.max()) - float(x.min())
+        xs.append(x)
+        taus.append([r * 4.0 ** -i for i in range(1, 7)])
+        dev.append(torch.from_numpy(x).to("cuda:0"))
+    say("full batch: %d fields, %d values" % (len(xs), sum(x.size for x in xs)))
+    ctx = pmc.Context(0)
+    batch = ctx.batch([(x.shape, d.dtype) for x, d in zip(xs, dev)], taus)
+    gm, order, _ = batch.tune(dev)
+    say("  tuned schedule: grid x%d, order %d" % (gm, order))
+    stores = batch.compress(dev)
+    checked = 0
+    for f, (x, st) in enumerate(zip(xs, stores)):
+        out = ctx.retrieve(st, 6)
+        err = float((dev[f].double() - out.double()).abs().max())
+        assert err <= taus[f][5] and err == st.info[5]["linf"], f
+        if x.size <= 1 << 17:
+            comps, meta = driver.compress(x, taus[f])
+            for i in range(6):
+                assert np.array_equal(st.stream(i).cpu().numpy(), comps[i]), (f, i)
+                assert st.info[i]["linf"] == meta[i]["linf"]
+            assert np.array_equal(out.cpu().numpy(), driver.reconstruct(comps, 6, x.shape, x.dtype)), f
+            checked += 1
+    say("  %d fields bit-exact against the oracle; Eq. (1) on all %d" % (checked, len(xs)))
+    torch.cuda.synchronize()
