@@ -736,8 +736,17 @@ __device__ __forceinline__ void planes_read(R& r, typename FT<T>::S c[64], int p
   const int z0 = (int)__builtin_ctz(r.peek32() | 0x80000000u);
   const int zlead = z0 < p ? z0 : p;
   r.skip((uint32_t)zlead);
-  // slot t' holds plane base + t'
-  const int base = rel ? (zlead < P - 16 ? zlead : P - 16) : 0;
+  // slot t' holds plane base + t'.  Which planes share a slot across the
+  // wave matters: a slot costs the wave as many group-test windows as its
+  // slowest lane needs.  Residual components are noise-like, and the planes
+  // where most coefficients become significant follow each block's first
+  // non-empty plane, so slots count from that plane.  In a store's first
+  // component those planes lie at a similar absolute bit level in every block
+  // (the data's fine-scale content), i.e. at a fixed distance above the last
+  // coded plane, so slots count back from the last plane (base may be
+  // negative: leading slots then hold no plane).  Planes above base are empty
+  // in either case (base <= zlead).
+  const int base = rel ? (zlead < P - 16 ? zlead : P - 16) : (p - 16 < zlead ? p - 16 : zlead);
   uint32_t Tw[32];
 #pragma unroll
   for (int tp = 0; tp < 16; ++tp) {
@@ -752,7 +761,9 @@ __device__ __forceinline__ void planes_read(R& r, typename FT<T>::S c[64], int p
   // planes above are empty), whose value is ((X ^ M) - M) << sh with M the
   // negabinary mask's bits at the slice's positions (0xAAAA for even sh,
   // 0x5555 for odd): the mask's lower bits cancel.  One xor serves both
-  // slices of a word.
+  // slices of a word.  With base < 0 the slice's top -base bits are zero
+  // digits and sh + 15 >= P: what the shift drops is the mask alone, dropped
+  // from the offset alike (all modulo 2^P).
   const int sh = P - 16 - base;
   const uint32_t M = (sh & 1) ? 0x5555u : 0xAAAAu;
   const uint32_t MM = M | (M << 16);
