@@ -108,8 +108,10 @@ pmc_status pmc_accuracy_gain(pmc_ctx* ctx, const pmc_field* f, const void* d_x, 
 /* ---- a second compressor: the float32 cast of Sec. 3 ------------------------
  * The multi-component driver with C(e) = fl32(e) (round to nearest even
  * float32) and D(y) = y in the field's type; tolerances play no part.  For a
- * float64 field the components form a floating-point expansion (three
- * reproduce every normal double).  pmc_cast_compress runs all n components
+ * float64 field the components form a floating-point expansion: three
+ * reproduce every double x with 2^-97 <= |x| < 2^128 (and zero); below that
+ * the last component's bits fall under the float32 subnormal spacing, above
+ * it the first cast overflows.  pmc_cast_compress runs all n components
  * (1 <= n <= 32) of Alg. 1: component i (i = 0..n-1) goes to d_comps + i * N
  * (N = values of the field; the caller owns the n * N floats), and linf[i]
  * (host, optional) receives max |x - x~_{i+1}| in float64 (synchronises).

@@ -466,6 +466,19 @@ def test_cast_f32_codec_three_components_are_lossless():
     assert meta[2]["linf"] == 0.0
 
 
+def test_cast_f32_codec_exact_range():
+    """The expansion's limits: exact for 2^-97 <= |x| < 2^128 (x's last bit,
+    2^(e-52), is still a float32 subnormal step at e = -97), not below, where
+    the third component loses bits."""
+    rng = np.random.default_rng(18)
+    m = rng.uniform(1.0, 2.0, size=2000) * rng.choice([-1.0, 1.0], size=2000)
+    for e, exact in ((-97, True), (0, True), (127, True), (-100, False)):
+        x = m * 2.0 ** e
+        comps, _ = driver.compress(x, [1.0, 0.5, 0.25], driver.CastF32Codec())
+        xt = driver.reconstruct(comps, 3, x.shape, x.dtype, driver.CastF32Codec())
+        assert bool(np.array_equal(xt, x)) == exact, e
+
+
 def test_lossless_limit_block_codec():
     """Sec. 5.1.3: enough components reach zero error.  With tau_n below the
     smallest nonzero float32 difference, Eq. (1) forces x~_n == x."""
