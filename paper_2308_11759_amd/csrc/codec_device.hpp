@@ -800,6 +800,7 @@ template <class T, class R> __device__ __forceinline__ bool block_skip(R& r, int
     return true;
   }
   int delta = 0;
+#pragma unroll 1
   while (r.get(1)) {
     if (++delta > P) return false;
   }

@@ -306,8 +306,8 @@ template <class T> struct XLds {
 constexpr int kNt = 2;
 template <class T>
 __device__ __forceinline__ void load_block_lds(const T* __restrict__ f, const Geo& g, const BlockPos& b, T* s_x,
-                                               uint32_t lane) {
-  const bool vec = b.vx == 4 && g.rows_aligned;
+                                               uint32_t lane, bool wfull) {
+  const bool vec = wfull || (b.vx == 4 && g.rows_aligned);
   XLds<T> X{s_x, lane};
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
@@ -329,8 +329,11 @@ __device__ __forceinline__ void load_block_lds(const T* __restrict__ f, const Ge
 }
 
 // one wave = 64 consecutive blocks = 4 chunks; `wave` numbers these groups
-// within the field.  s_x: 64 * 64 values of LDS owned by this wave.
-template <class T>
+// within the field.  s_x: 64 * 64 values of LDS owned by this wave.  kFull:
+// the caller guarantees that every block is full and rows are aligned (all
+// three dimensions multiples of 4), so the per-lane edge paths compile away
+// and their conditions hold no registers.
+template <class T, bool kFull = false>
 __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T* s_x, const uint16_t* unsq) {
   typedef typename FT<T>::U U;
   constexpr int P = FT<T>::P;
@@ -347,17 +350,22 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
   const bool active = blk < a.g.nblocks;
 
   BlockPos bp = block_pos(a.g, active ? blk : 0);
+  if constexpr (kFull) {
+    bp.vx = 4;
+    bp.vy = 4;
+    bp.vz = 4;
+  }
   // every lane has a full block of aligned rows: row accesses without per-lane paths
-  const bool wfull = __all(bp.vx == 4 && bp.vy == 4 && bp.vz == 4 && a.g.rows_aligned);
+  const bool wfull = kFull || __all(bp.vx == 4 && bp.vy == 4 && bp.vz == 4 && a.g.rows_aligned);
   // x into LDS and x~_{i-1} into registers, all loads in flight together
-  load_block_lds(a.x, a.g, bp, s_x, lane);
+  load_block_lds(a.x, a.g, bp, s_x, lane, wfull);
   T e[64];
   load_rows<T, 16>(a.first ? nullptr : a.xt_in, a.g, bp, 0, wfull, e);
   __builtin_amdgcn_s_waitcnt(0);  // direct loads, LDS writes and the rows complete
   const XLds<T> X{s_x, lane};
   // row addresses are recomputed where used instead of kept in registers
   bp = opaque_pos(bp);
-  const uint64_t vmask = valid_mask(bp);
+  const uint64_t vmask = kFull ? ~0ull : valid_mask(bp);
 
   // one pass over the rows: the residual e = x - x~_{i-1} (kept in registers
   // for the transform) and its largest magnitude (the block exponent, the
@@ -474,7 +482,7 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
 #pragma unroll 1
     for (int r = 0; r < 16; ++r) {
       T tr[4], d[4];
-      load_row(a.first ? nullptr : a.xt_in, a.g, bp, r, tr);
+      load_rows<T, 1>(a.first ? nullptr : a.xt_in, a.g, bp, r, wfull, tr);
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int l = 4 * r + t;
@@ -482,7 +490,7 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
         d[t] = tr[t] + (xl - tr[t]);
         ea = nmax(ea, masked_abs(vmask, l, (double)xl - (double)d[t]));
       }
-      if (!a.last) store_row(a.xt_out, a.g, bp, r, d);
+      if (!a.last) store_row(a.xt_out, a.g, bp, r, d, wfull);
     }
     err = ea;
     miss = !(ea <= a.tau && ea <= eb);
@@ -493,10 +501,10 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
 #pragma unroll 1
       for (int r = 0; r < 16; ++r) {
         T tr[4], d[4];
-        load_row(a.first ? nullptr : a.xt_in, a.g, bp, r, tr);
+        load_rows<T, 1>(a.first ? nullptr : a.xt_in, a.g, bp, r, wfull, tr);
 #pragma unroll
         for (int t = 0; t < 4; ++t) d[t] = tr[t] + (T)0;
-        store_row(a.xt_out, a.g, bp, r, d);
+        store_row(a.xt_out, a.g, bp, r, d, wfull);
       }
     }
   }
@@ -597,12 +605,12 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
   }
 }
 
-template <class T>
+template <class T, bool kFull>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1))) void k_encode(EncArgs<T> a) {
   __shared__ T s_x[64 * 64];
   __shared__ uint16_t s_unsq[256];
   unsqueeze_table(s_unsq);
-  encode_wave<T>(a, blockIdx.x, s_x, s_unsq);
+  encode_wave<T, kFull>(a, blockIdx.x, s_x, s_unsq);
 }
 
 // ---------------------------------------------------------------------------
@@ -792,7 +800,8 @@ __device__ __forceinline__ bool decode_block_add(R& r, int minexp, T acc[64], co
   } else {
     r.skip(2);
     delta = 0;
-    while (r.get(1)) {
+#pragma unroll 1
+    while (r.get(1)) {  // (rare: a long escalation; kept as a loop)
       if (++delta > P) return false;
     }
     emax = (int)r.get((uint32_t)EB) - FT<T>::BIAS;
@@ -1306,7 +1315,10 @@ __global__ __launch_bounds__(64) void k_bpack(BatchArgs b) {
 // host launchers
 template <class T> hipError_t launch_encode(const EncArgs<T>& a, hipStream_t s) {
   const uint64_t wgs = (a.g.nblocks + 63) / 64;
-  hipLaunchKernelGGL(k_encode<T>, dim3((uint32_t)wgs), dim3(64), 0, s, a);
+  // every block full and every row aligned: the kernel without edge paths
+  const bool full = a.g.nx % 4 == 0 && a.g.ny % 4 == 0 && a.g.nz % 4 == 0 && a.g.rows_aligned;
+  if (full) hipLaunchKernelGGL((k_encode<T, true>), dim3((uint32_t)wgs), dim3(64), 0, s, a);
+  else hipLaunchKernelGGL((k_encode<T, false>), dim3((uint32_t)wgs), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 hipError_t launch_scan(const ScanArgs& a, hipStream_t s) {
