@@ -859,8 +859,9 @@ __device__ __forceinline__ void stage_span(const uint32_t* payload, const Span& 
 // decode the wave's 64 blocks [64 w, 64 w + 64) of a field: x~ = in (or +0)
 // plus components [0, ncomp) of the given streams, left to right.  Every lane
 // runs the component loop (the staging copies are shared); false on a
-// malformed stream.
-template <class T, bool kStaged, bool kBox = false>
+// malformed stream.  kFull: every block of the field is full and rows are
+// aligned (all dimensions multiples of 4): no per-lane edge paths.
+template <class T, bool kStaged, bool kBox = false, bool kFull = false>
 __device__ __forceinline__ bool decode_wave(const Geo& g, const uint8_t* const* s, const uint32_t* const* aux,
                                             const uint64_t* words, const int* minexp, int ncomp, uint32_t relmask,
                                             const T* in, T* out, uint64_t w, const uint8_t* sq, uint32_t* stage,
@@ -868,7 +869,12 @@ __device__ __forceinline__ bool decode_wave(const Geo& g, const uint8_t* const* 
   const uint32_t lane = threadIdx.x;
   const uint64_t blk = w * 64 + lane;
   bool active = blk < g.nblocks;
-  const BlockPos bp = block_pos(g, active ? blk : 0);
+  BlockPos bp = block_pos(g, active ? blk : 0);
+  if constexpr (kFull) {
+    bp.vx = 4;
+    bp.vy = 4;
+    bp.vz = 4;
+  }
   if constexpr (kBox) {  // only this row's blocks in the box are decoded (each by
                          // one workgroup); the wave still stages its chunks,
                          // whose bit offsets locate every block
@@ -878,6 +884,7 @@ __device__ __forceinline__ bool decode_wave(const Geo& g, const uint8_t* const* 
   T acc[64];
   if (in && active) {
     if constexpr (kBox) load_box(in, *box, bp, acc);
+    else if constexpr (kFull) load_rows<T, 16>(in, g, opaque_pos(bp), 0, true, acc);
     else load_block(in, g, opaque_pos(bp), acc);
   } else {
 #pragma unroll
@@ -976,18 +983,25 @@ __device__ __forceinline__ bool decode_wave(const Geo& g, const uint8_t* const* 
   }
   // the block position is recomputed here rather than kept in registers
   if (active && ok) {
-    if constexpr (kBox) store_box(out, *box, block_pos(g, opaque(w) * 64 + lane), acc);
-    else store_block(out, g, block_pos(g, opaque(w) * 64 + lane), acc);
+    if constexpr (kBox) {
+      store_box(out, *box, block_pos(g, opaque(w) * 64 + lane), acc);
+    } else if constexpr (kFull) {
+      const BlockPos bo = block_pos(g, opaque(w) * 64 + lane);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) store_row(out, g, bo, r, acc + 4 * r, true);
+    } else {
+      store_block(out, g, block_pos(g, opaque(w) * 64 + lane), acc);
+    }
   }
   return ok || !active;
 }
 
-template <class T, bool kStaged>
+template <class T, bool kStaged, bool kFull>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_decode(DecArgs<T> a) {
   __shared__ uint8_t s_squeeze[256];
   __shared__ uint32_t s_stage[kStaged ? kStageWords + 3 : 1];
   squeeze_table(s_squeeze);
-  if (!decode_wave<T, kStaged>(a.g, a.s, a.aux, a.words, a.minexp, a.ncomp, a.relmask, a.in, a.out, blockIdx.x,
+  if (!decode_wave<T, kStaged, false, kFull>(a.g, a.s, a.aux, a.words, a.minexp, a.ncomp, a.relmask, a.in, a.out, blockIdx.x,
                                s_squeeze, s_stage))
     atomicOr(a.status, 1u);
 }
@@ -1337,8 +1351,16 @@ template <class T> hipError_t launch_pack(const PackArgs& a, hipStream_t s) {
 uint64_t stage_words() { return kStageWords; }
 template <class T> hipError_t launch_decode(const DecArgs<T>& a, uint64_t max_span, hipStream_t s) {
   const uint64_t wgs = (a.g.nblocks + 63) / 64;
-  if (max_span <= kStageWords) hipLaunchKernelGGL((k_decode<T, true>), dim3((uint32_t)wgs), dim3(64), 0, s, a);
-  else hipLaunchKernelGGL((k_decode<T, false>), dim3((uint32_t)wgs), dim3(64), 0, s, a);
+  const dim3 grid((uint32_t)wgs), wg(64);
+  // every block full and every row aligned: the kernel without edge paths
+  const bool full = a.g.nx % 4 == 0 && a.g.ny % 4 == 0 && a.g.nz % 4 == 0 && a.g.rows_aligned;
+  if (max_span <= kStageWords) {
+    if (full) hipLaunchKernelGGL((k_decode<T, true, true>), grid, wg, 0, s, a);
+    else hipLaunchKernelGGL((k_decode<T, true, false>), grid, wg, 0, s, a);
+  } else {
+    if (full) hipLaunchKernelGGL((k_decode<T, false, true>), grid, wg, 0, s, a);
+    else hipLaunchKernelGGL((k_decode<T, false, false>), grid, wg, 0, s, a);
+  }
   return hipGetLastError();
 }
 template <class T>
