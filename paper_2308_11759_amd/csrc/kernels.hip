@@ -263,6 +263,15 @@ __device__ __forceinline__ BlockPos opaque_pos(BlockPos b) {
   b.z0 = opaque(b.z0);
   return b;
 }
+// also the valid extents, so that the edge paths' per-lane conditions are
+// re-derived where used instead of living across a loop as lane masks
+__device__ __forceinline__ BlockPos opaque_ext(BlockPos b) {
+  b = opaque_pos(b);
+  b.vx = opaque(b.vx);
+  b.vy = opaque(b.vy);
+  b.vz = opaque(b.vz);
+  return b;
+}
 
 // a + v * scale where v * scale is exact: one fused multiply-add equals the
 // plain sum of the (exact) product
@@ -418,7 +427,7 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
       // the loop into 64 registers
       const XLds<T> XL{opaque(s_x), lane};
       const T* const tin = a.first ? nullptr : a.xt_in;
-      const BlockPos bq = opaque_pos(bp);  // row addresses are recomputed, not held
+      const BlockPos bq = kFull ? opaque_pos(bp) : opaque_ext(bp);  // row addresses are recomputed, not held
       bool feasible = false;
       uint32_t cb = 0;
       if (p >= 1 && p <= P) {
