@@ -77,6 +77,28 @@ def load_traffic(kernel, workload):
     return e.get("bytes_per_launch")
 
 
+# vector ALU issue rate: 1024 SIMDs (256 CUs x 4), one wave64 instruction per
+# SIMD every 4 cycles at 2.4 GHz
+VALU_WAVE_INSTR_PER_S = 1024 * 2.4e9 / 4
+
+
+def load_valu_instructions(kernel, workload):
+    """VALU wave-instructions per launch counted by rocprofv3 --pmc
+    (SQ_INSTS_VALU), committed under profiles/; null when the kernel sources
+    changed since."""
+    p = os.path.join(ROOT, "profiles", "instructions.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        t = json.load(open(p))
+    except ValueError:
+        return None
+    e = t.get(workload, {}).get(kernel)
+    if not e or e.get("source_sha") != source_sha():
+        return None
+    return e.get("valu_instr_per_launch")
+
+
 def cpu_baseline(x, taus, planes):
     """The oracle as it stands, single-threaded, on a z-slab of the same field."""
     from oracle import driver
@@ -418,6 +440,11 @@ def main():
                 "traffic_gbs": traffic / 1e9 / (dk["avg_launch_ms"] / 1e3) if traffic else None,
                 "traffic_frac": traffic / 1e9 / (dk["avg_launch_ms"] / 1e3) / HBM_PEAK_GBS if traffic else None,
                 "algorithmic_bytes_per_launch": algo[dom] / launches, "avg_launch_ms": dk["avg_launch_ms"]}
+    # the vector ALUs' share of the launch: counted VALU instructions at the
+    # issue rate over the live launch time (the kernels are VALU-bound below
+    # the HBM roof)
+    vi = load_valu_instructions(dom, args.workload)
+    roofline["valu_issue_frac"] = vi / VALU_WAVE_INSTR_PER_S / (dk["avg_launch_ms"] / 1e3) if vi else None
 
     comp_ms = sum(kern.get(k, {}).get("ms_per_step", 0.0) for k in
                   ("k_encode_" + tname, "k_scan", "k_pack_" + tname))
