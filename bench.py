@@ -344,7 +344,7 @@ def main():
         return bench_served(args)
 
     import torch
-    from paper_2308_11759_amd import pmc
+    from paper_2308_11759_amd import inputs, pmc
 
     shape, dt, seed, n, taufn, noise = WORKLOADS[args.workload]
     log("generating %s" % args.workload)
@@ -570,6 +570,7 @@ def main():
         "lossless": lossless,
         "cast_codec": cast,
         "rate_distortion": rdist,
+        "lag1_autocorrelation_xyz": [round(v, 4) for v in inputs.lag1_autocorrelation(x)],
         "rates_bits_per_value": [round(8.0 * m["bytes"] / N, 3) for m in info],
         "linf": [m["linf"] for m in info],
         "accuracy_gain": gain,

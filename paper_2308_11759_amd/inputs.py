@@ -143,13 +143,16 @@ def query_trace(nfields, rate_qps, nqueries, seed=7, tol_lo=1e-5, tol_hi=1e-1):
 def lag1_autocorrelation(f):
     """Per-axis lag-1 autocorrelation (x, y, z), to place a field against the
     paper's smooth (> 0.95) / rough (< 0.79) split."""
-    g = f.astype(np.float64) - float(np.mean(f))
+    g = f.astype(np.float64)
+    g -= float(np.mean(g))
     var = float(np.mean(g * g))
     out = []
     for axis in (2, 1, 0):
-        a = np.take(g, range(0, g.shape[axis] - 1), axis=axis)
-        b = np.take(g, range(1, g.shape[axis]), axis=axis)
-        out.append(float(np.mean(a * b)) / var if var > 0 else 1.0)
+        lo = [slice(None)] * 3
+        hi = [slice(None)] * 3
+        lo[axis] = slice(0, g.shape[axis] - 1)
+        hi[axis] = slice(1, g.shape[axis])
+        out.append(float(np.mean(g[tuple(lo)] * g[tuple(hi)])) / var if var > 0 else 1.0)
     return out
 
 
