@@ -446,12 +446,15 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
         T dv[64];
         const T scale = dequantize_block(q, emax, dv);
         double ea = 0.0;
+        // rows of x~_{i-1} in flight together: eight in the full-field
+        // kernel (registers to spare), four where the edge paths need them
+        constexpr int RB = kFull ? 8 : 4;
 #pragma unroll
-        for (int r0 = 0; r0 < 16; r0 += 4) {
-          T tr[16];
-          load_rows<T, 4>(tin, a.g, bq, r0, wfull, tr);  // four rows in flight
+        for (int r0 = 0; r0 < 16; r0 += RB) {
+          T tr[4 * RB];
+          load_rows<T, RB>(tin, a.g, bq, r0, wfull, tr);
 #pragma unroll
-          for (int k = 0; k < 4; ++k) {
+          for (int k = 0; k < RB; ++k) {
             const int r = r0 + k;
             T row[4];
 #pragma unroll
