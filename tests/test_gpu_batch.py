@@ -145,3 +145,33 @@ def test_full_batched_config():
             checked += 1
     say("  %d fields bit-exact against the oracle; Eq. (1) on all %d" % (checked, len(xs)))
     torch.cuda.synchronize()
+
+
+def test_full_field_kernels_match_edge_path_kernels():
+    """A field whose dimensions are multiples of 4 takes the encoder and
+    decoder instantiations without edge paths when compressed on its own,
+    and the general ones inside a batch: both give the oracle's streams, and
+    x~_k agrees bit for bit."""
+    import torch
+    from paper_2308_11759_amd import pmc
+    ctx = pmc.Context(0)
+    for shape, dt in (((32, 48, 64), np.float32), ((24, 16, 40), np.float64)):
+        x = inputs.spectral_field(shape, seed=77, dtype=dt)
+        r = float(x.max() - x.min())
+        taus = [r * 4.0 ** -i for i in range(1, 6)]
+        comps, meta = driver.compress(x, taus)
+        xd = torch.from_numpy(x).to("cuda:0")
+        single = ctx.compress(xd, taus)
+        odd = inputs.spectral_field((5, 7, 9), seed=78, dtype=dt)  # a ragged neighbour in the batch
+        oddd = torch.from_numpy(odd).to("cuda:0")
+        ro = float(odd.max() - odd.min())
+        batch = ctx.batch([(x.shape, xd.dtype), (odd.shape, oddd.dtype)], [taus, [ro * 4.0 ** -i for i in range(1, 4)]])
+        stores = batch.compress([xd, oddd])
+        for i in range(len(taus)):
+            assert np.array_equal(single.stream(i).cpu().numpy(), comps[i]), (shape, i)
+            assert np.array_equal(stores[0].stream(i).cpu().numpy(), comps[i]), (shape, i)
+        for k in range(1, len(taus) + 1):
+            want = driver.reconstruct(comps, k, x.shape, x.dtype)
+            assert np.array_equal(ctx.retrieve(single, k).cpu().numpy(), want), (shape, k)
+        say("  %s %s: full-field and edge-path kernels agree with the oracle" % (shape, np.dtype(dt).name))
+    torch.cuda.synchronize()
