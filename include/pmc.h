@@ -17,6 +17,10 @@
  *    once their kernels are enqueued unless stated otherwise.
  *  - Fields are dense, C order, x fastest: element (x, y, z) is at
  *    x + nx * (y + ny * z).  Lower-dimensional data use extents of 1.
+ *    Field pointers given to pmc_compress, pmc_batch_compress, pmc_retrieve,
+ *    pmc_refine and pmc_server_submit must be 16-byte aligned (every PyTorch
+ *    allocation is):
+ *    rows move as 16-byte pieces; others give PMC_E_ARG.
  *  - Return value: PMC_OK (0) or a negative pmc_status; the context keeps a
  *    message for pmc_last_error.  On error no output is valid.
  *  - One context per host thread.

@@ -353,6 +353,7 @@ pmc_status pmc_batch_compress(pmc_batch* b, const void* const* d_x, void* d_ws, 
   for (int i = 0; i < b->nf; ++i) {
     out[i] = nullptr;
     if (!d_x[i]) return fail(ctx, PMC_E_ARG, "field %d: null input", i);
+    if (!aligned16(d_x[i])) return fail(ctx, PMC_E_ARG, "field %d: input not 16-byte aligned", i);
   }
   if (ws_bytes < b->ws_total)
     return fail(ctx, PMC_E_NOMEM, "workspace too small: need %llu bytes", (unsigned long long)b->ws_total);

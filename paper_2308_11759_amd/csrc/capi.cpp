@@ -340,6 +340,7 @@ pmc_status pmc_compress(pmc_ctx* ctx, const pmc_field* f, const void* d_x, int n
   Geo g;
   if (!make_geo(f, &g)) return fail(ctx, PMC_E_ARG, "bad field");
   if (!d_x || !tau || !out || !d_streams) return fail(ctx, PMC_E_ARG, "null argument");
+  if (!aligned16(d_x)) return fail(ctx, PMC_E_ARG, "d_x must be 16-byte aligned");
   if (n < 1 || n > kMaxComps) return fail(ctx, PMC_E_ARG, "n must be in [1, %d]", kMaxComps);
   for (int i = 0; i < n; ++i) {
     if (!(tau[i] > 0.0) || !std::isfinite(tau[i])) return fail(ctx, PMC_E_ARG, "tau[%d] must be > 0 and finite", i);
@@ -670,6 +671,7 @@ pmc_status pmc_retrieve_box(pmc_ctx* ctx, const pmc_store* s, int k, const uint6
 pmc_status pmc_retrieve(pmc_ctx* ctx, const pmc_store* s, int k, void* d_out, void* d_ws, size_t ws_bytes) {
   if (!ctx) return PMC_E_ARG;
   if (!s || !d_out) return fail(ctx, PMC_E_ARG, "null argument");
+  if (!aligned16(d_out)) return fail(ctx, PMC_E_ARG, "d_out must be 16-byte aligned");
   if (k < 1 || k > s->n) return fail(ctx, PMC_E_ARG, "k must be in [1, %d]", s->n);
   return decode_range(ctx, s, 0, k, nullptr, d_out, d_ws, ws_bytes);
 }
@@ -678,6 +680,7 @@ pmc_status pmc_refine(pmc_ctx* ctx, const pmc_store* s, int k_from, int k_to, vo
                       size_t ws_bytes) {
   if (!ctx) return PMC_E_ARG;
   if (!s || !d_inout) return fail(ctx, PMC_E_ARG, "null argument");
+  if (!aligned16(d_inout)) return fail(ctx, PMC_E_ARG, "d_inout must be 16-byte aligned");
   if (k_from < 0 || k_to > s->n || k_from > k_to) return fail(ctx, PMC_E_ARG, "bad component range");
   if (k_from == k_to) return PMC_OK;
   return decode_range(ctx, s, k_from, k_to, k_from == 0 ? nullptr : d_inout, d_inout, d_ws, ws_bytes);

@@ -15,6 +15,9 @@ struct ProfRec {
   hipEvent_t start, stop;
 };
 
+// device fields are read and written with 16-byte row accesses
+inline bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
 struct pmc_ctx {
   int device = 0;
   hipStream_t stream = nullptr;

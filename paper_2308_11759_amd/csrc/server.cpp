@@ -427,6 +427,7 @@ pmc_status pmc_server_submit(pmc_server* sv, int field_id, double tol, void* d_o
   if (!sv || !ticket) return PMC_E_ARG;
   std::lock_guard<std::mutex> lk(sv->mu);
   if (field_id < 0 || field_id >= (int)sv->fields.size()) return fail(sv->ctx, PMC_E_ARG, "unknown field");
+  if (d_out && !aligned16(d_out)) return fail(sv->ctx, PMC_E_ARG, "d_out must be 16-byte aligned");
   int k = 0;
   if (pmc_select_k(sv->fields[field_id], tol, 0, &k) != PMC_OK)
     return fail(sv->ctx, PMC_E_UNREACHABLE, "tolerance below the last component's");

@@ -260,6 +260,15 @@ def test_error_paths(ctx):
     assert ei.value.status == pmc.E_NOMEM
     store = ctx.compress(xd, [0.1, 0.01])
     assert store.select_k(1e-9) is None
+    # field pointers off the 16-byte grid are refused on the host, before any launch
+    shifted = torch.empty(x.size + 1, dtype=torch.float32, device="cuda:0")[1:].view(x.shape)
+    shifted.copy_(xd)
+    with pytest.raises(pmc.PmcError) as ei:
+        ctx.compress(shifted, [0.1])
+    assert ei.value.status == pmc.E_ARG
+    with pytest.raises(pmc.PmcError) as ei:
+        ctx.retrieve(store, 1, out=shifted)
+    assert ei.value.status == pmc.E_ARG
     # corrupted header -> rejected on the host
     blob = bytearray(store.serialize())
     hdr_off = (48 + 64 * 2 + 255) & ~255
