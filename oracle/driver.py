@@ -83,6 +83,8 @@ def compress(x, taus, codec=None):
         xt = xt + xi                            # partial-sum update (left-to-right sum)
         m = dict(st)
         m["tau"] = tau
+        if "linf" in st:
+            m["encoder_linf"] = st["linf"]      # the codec's own largest accepted block error
         m["linf"] = measured_error(x, xt)
         comps.append(y)
         meta.append(m)

@@ -23,11 +23,17 @@
  * Parity status of each function (see the tests that pin them):
  *   negabinary            pinned: textbook base(-2) digit sum, exhaustive int16
  *   fwd/inv lift          pinned: closed forms (constant, ramp), matrix bound
+ *   inverse pass order    pinned: hand-derived single-coefficient inverse
  *   permutation           pinned: sequency order property
+ *   minexp                pinned: exact floor(log2 tau) (rationals), incl.
+ *                          tau not a power of two and subnormal tau
  *   plane coder           pinned: hand-derived golden encodings, lossless at
  *                          p = P, closed-form bit count
- *   block acceptance      pinned: Eq. (1) bound, monotone error (invariants)
- *   stream layout         pinned: hand-derived golden stream of a tiny field
+ *   block acceptance      pinned: Eq. (1) bound, monotone error (invariants);
+ *                          coded-before-empty and the raw payload (residual
+ *                          bits) by hand-derived cases
+ *   stream layout         pinned: hand-derived golden streams (one chunk, two
+ *                          chunks, a partial block with edge replication)
  *   rates / bit counts    parity unpinned against the paper (the paper prints
  *                          rates only for an unnamed field)
  *
@@ -35,10 +41,19 @@
  * gcc defines >> on negative signed integers as an arithmetic shift, which is
  * the floor(x / 2) the lifting steps need.
  */
+#include <float.h>
 #include <stdint.h>
 #include <string.h>
 #include <math.h>
 #include <stdlib.h>
+
+/* The float64 dequantisation below forms q * 2^s exactly in long double and
+ * rounds once to double; that needs a significand of at least 64 bits (x87
+ * extended precision).  Where long double is binary64 the product would be
+ * rounded twice, so refuse to build there. */
+#if LDBL_MANT_DIG < 64
+#error "pmc_oracle.c needs a long double with a 64-bit significand (x87 extended precision)"
+#endif
 
 enum { ORC_F32 = 1, ORC_F64 = 2 };
 enum {

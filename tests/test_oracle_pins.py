@@ -410,7 +410,10 @@ def test_driver_bound_monotone_and_partial_sums():
             assert m["linf"] <= taus[i]
             assert m["linf"] <= prev
             assert m["nmiss"] == 0
-            assert m["linf"] == m["linf"]  # encoder block errors agree below
+            # the encoder's decode-for-verify and the decoder agree: the
+            # largest block error the encoder accepted is the measured error
+            # of the decoded x~_i
+            assert m["encoder_linf"] == m["linf"]
             prev = m["linf"]
         xt_prev = np.zeros_like(x)
         for k in range(1, n + 1):
