@@ -10,9 +10,10 @@ prescribed tau_i and the measured error max|x - x~_i| (Sec. 4.3, last
 paragraph), evaluated in float64.
 
 Codecs plug in through ``encode(e, tau, x, xt) -> (y, stats)`` and
-``decode(y, shape, dtype) -> x_i``: the block codec of the C oracle, and the
-scalar cast-to-float32 "compressor" of Sec. 3, which turns Alg. 1 into the
-classical multi-component floating-point expansion.
+``decode(y, shape, dtype) -> x_i``: the block-transform codec and the
+prediction codec of the C oracle, and the scalar cast-to-float32
+"compressor" of Sec. 3, which turns Alg. 1 into the classical
+multi-component floating-point expansion.
 """
 import math
 
@@ -28,6 +29,19 @@ class BlockCodec:
 
     def encode(self, e, tau, x, xt):
         return lib.encode(e, x, xt, tau)
+
+    def decode(self, y, shape, dtype):
+        return lib.decode(y, shape, dtype)
+
+
+class PredictionCodec:
+    """The prediction-and-quantisation codec (codec 1) of pmc_oracle.c: a
+    second error-bounded compressor behind the same driver (Sec. 6.2)."""
+
+    name = "prediction"
+
+    def encode(self, e, tau, x, xt):
+        return lib.encode(e, x, xt, tau, codec=1)
 
     def decode(self, y, shape, dtype):
         return lib.decode(y, shape, dtype)

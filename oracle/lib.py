@@ -87,6 +87,21 @@ def load():
     lib.orc_stream_cap.restype = ctypes.c_uint64
     lib.orc_encode.argtypes = [P(Field), vp, vp, vp, ctypes.c_double, u8p, ctypes.c_uint64, u64p, P(Stats)]
     lib.orc_encode.restype = ctypes.c_int
+    lib.orc_encode_codec.argtypes = [P(Field), ctypes.c_int, vp, vp, vp, ctypes.c_double, u8p, ctypes.c_uint64,
+                                     u64p, P(Stats)]
+    lib.orc_encode_codec.restype = ctypes.c_int
+    lib.orc_lorenzo_fwd.argtypes = [i64p, ctypes.c_int, ctypes.c_int]
+    lib.orc_lorenzo_inv.argtypes = [i64p, ctypes.c_int, ctypes.c_int]
+    lib.orc_zigzag.argtypes = [ctypes.c_int64, ctypes.c_int]
+    lib.orc_zigzag.restype = ctypes.c_uint64
+    lib.orc_unzigzag.argtypes = [ctypes.c_uint64, ctypes.c_int]
+    lib.orc_unzigzag.restype = ctypes.c_int64
+    lib.orc_encode_one_block_pq.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, ctypes.c_double, u8p,
+                                            ctypes.c_uint64, u64p, ip, ip, dp, dp]
+    lib.orc_encode_one_block_pq.restype = ctypes.c_int
+    lib.orc_decode_one_block_pq.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, u8p, ctypes.c_uint64,
+                                            dp, u64p]
+    lib.orc_decode_one_block_pq.restype = ctypes.c_int
     lib.orc_stream_info.argtypes = [u8p, ctypes.c_uint64, P(Field), dp, u64p, u64p]
     lib.orc_stream_info.restype = ctypes.c_int
     lib.orc_decode.argtypes = [u8p, ctypes.c_uint64, P(Field), vp]
@@ -241,13 +256,65 @@ def decode_one_block(buf, nbits, tau, dtype, d):
     return m, out, used.value
 
 
+def lorenzo_fwd(q, d, P):
+    a = np.array(q, dtype=np.int64).copy()
+    load().orc_lorenzo_fwd(_ptr(a, ctypes.c_int64), d, P)
+    return a
+
+
+def lorenzo_inv(r, d, P):
+    a = np.array(r, dtype=np.int64).copy()
+    load().orc_lorenzo_inv(_ptr(a, ctypes.c_int64), d, P)
+    return a
+
+
+def zigzag(r, P):
+    return load().orc_zigzag(int(r), P)
+
+
+def unzigzag(z, P):
+    return load().orc_unzigzag(int(z), P)
+
+
+def encode_one_block_pq(e, x, xt, tau, dtype, d):
+    """Codec 1 on one whole block; returns dict(buf, nbits, mode, delta, err, xi, miss)."""
+    B = 4 ** d
+    e = np.ascontiguousarray(e, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    xt = np.ascontiguousarray(xt, dtype=np.float64)
+    assert e.size == B and x.size == B and xt.size == B
+    cap = 1200
+    buf = np.zeros(cap, dtype=np.uint8)
+    nbits = ctypes.c_uint64(0)
+    mode, delta = ctypes.c_int(0), ctypes.c_int(0)
+    err = ctypes.c_double(0)
+    xi = np.zeros(B, dtype=np.float64)
+    rc = load().orc_encode_one_block_pq(dtype_code(dtype), d, _ptr(e, ctypes.c_double), _ptr(x, ctypes.c_double),
+                                        _ptr(xt, ctypes.c_double), float(tau), _ptr(buf, ctypes.c_uint8), cap,
+                                        ctypes.byref(nbits), ctypes.byref(mode), ctypes.byref(delta),
+                                        ctypes.byref(err), _ptr(xi, ctypes.c_double))
+    assert rc in (0, 1), rc
+    return dict(buf=buf, nbits=nbits.value, mode=mode.value, delta=delta.value, err=err.value, xi=xi,
+                miss=rc == 1)
+
+
+def decode_one_block_pq(buf, nbits, tau, dtype, d):
+    buf = np.ascontiguousarray(buf, dtype=np.uint8)
+    out = np.zeros(4 ** d, dtype=np.float64)
+    used = ctypes.c_uint64(0)
+    m = load().orc_decode_one_block_pq(dtype_code(dtype), d, float(tau), _ptr(buf, ctypes.c_uint8), nbits,
+                                       _ptr(out, ctypes.c_double), ctypes.byref(used))
+    return m, out, used.value
+
+
 def stream_cap(shape, dtype):
     f = make_field(shape, dtype)
     return int(load().orc_stream_cap(ctypes.byref(f)))
 
 
-def encode(e, x, xt, tau):
+def encode(e, x, xt, tau, codec=0):
     """y = C(e, tau) for one component; e = x - xt already computed (the residual step of Alg. 1).
+    codec 0: the block-transform codec; 1: prediction and quantisation.
 
     Returns (stream bytes as np.uint8 array, stats dict)."""
     assert e.dtype == x.dtype == xt.dtype and e.shape == x.shape == xt.shape
@@ -259,8 +326,8 @@ def encode(e, x, xt, tau):
     out = np.zeros(cap, dtype=np.uint8)
     nbytes = ctypes.c_uint64(0)
     st = Stats()
-    rc = load().orc_encode(ctypes.byref(f), e.ctypes.data, x.ctypes.data, xt.ctypes.data, float(tau),
-                           _ptr(out, ctypes.c_uint8), cap, ctypes.byref(nbytes), ctypes.byref(st))
+    rc = load().orc_encode_codec(ctypes.byref(f), int(codec), e.ctypes.data, x.ctypes.data, xt.ctypes.data,
+                                 float(tau), _ptr(out, ctypes.c_uint8), cap, ctypes.byref(nbytes), ctypes.byref(st))
     if rc != OK:
         raise RuntimeError("oracle encode failed: %d" % rc)
     stats = {k: getattr(st, k) for k, _ in Stats._fields_}

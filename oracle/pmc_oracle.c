@@ -600,21 +600,236 @@ static int decode_block(bitr* r, int dtype, int d, int minexp, double* out) {
   return ORC_CODED;
 }
 
+/* ================================================================== */
+/* Codec 1: prediction and uniform quantisation on the same blocks.    */
+/* The paper's driver works with any error-bounded lossy compressor    */
+/* (Sec. 6.2) and names prediction-based ones beside the transform     */
+/* codecs (Sec. 5, compressor list).  This one is written from the     */
+/* general recipe of such codecs: quantise the residual to integer     */
+/* multiples of a bin h, predict each integer from its neighbours,     */
+/* and code the prediction errors.  Readings (format version 1,        */
+/* codec 1):                                                           */
+/*   h = 2 tau, halved per escalation step: h_d = h * 2^-d, 0 <= d <= 63 */
+/*   q = rint(e * (1/h_d)) in double (1/h computed once, scaled by 2^d); */
+/*     a block is feasible only while every |e * (1/h_d)| < 2^(P-2)      */
+/*   decoded value = fl_T(fl_double(q * h_d))                           */
+/*   prediction: the block-local Lorenzo predictor of q (the mixed     */
+/*     first difference along each of the d axes, samples outside the  */
+/*     block taken as 0), in wrapping P-bit integers; it is used only  */
+/*     when it needs fewer bits than q itself (ties: q itself)         */
+/*   coding: zigzag z = 2r for r >= 0, -2r - 1 for r < 0 (P-bit), a   */
+/*     common width w = bit length of the largest z, then all B values */
+/*     in w bits each, local index order, LSB first                   */
+/*   block header: 1 nonempty, 0 coded (1 raw), d ones and a zero, one */
+/*     bit "predicted", w in 6 bits, then the B values                */
+/*   acceptance: as codec 0, with d in place of the plane escalation;  */
+/*     raw = the residual's IEEE bits                                 */
+/* ================================================================== */
+#define PQ_MAX_DELTA 63
+
+static uint64_t zigzag(int64_t r, int P) {
+  uint64_t u = (uint64_t)r;
+  uint64_t sign = r < 0 ? pmask(P) : 0;  /* all ones when negative */
+  return ((u << 1) ^ sign) & pmask(P);
+}
+static int64_t unzigzag(uint64_t z, int P) {
+  uint64_t mag = z >> 1;
+  uint64_t v = (z & 1u) ? ~mag : mag;  /* -(m) - 1 = ~m */
+  return wrapP((int64_t)(v & pmask(P)), P);
+}
+
+/* Lorenzo prediction errors of q in place: along every axis, each sample
+ * minus its predecessor on the line (0 before the first), so that after all
+ * d axes each entry is the mixed difference of q at that point */
+void orc_lorenzo_fwd(int64_t* q, int d, int P) {
+  int B = block_size(d);
+  for (int axis = 0; axis < d; axis++) {
+    int stride = 1 << (2 * axis);
+    for (int l = B - 1; l >= 0; l--)
+      if (local_coord(l, axis) > 0) q[l] = subw(q[l], q[l - stride], P);
+  }
+}
+/* inverse: running sums along every axis (z first, then y, then x; the
+ * order does not matter for wrapping integer sums) */
+void orc_lorenzo_inv(int64_t* r, int d, int P) {
+  int B = block_size(d);
+  for (int axis = d - 1; axis >= 0; axis--) {
+    int stride = 1 << (2 * axis);
+    for (int l = 0; l < B; l++)
+      if (local_coord(l, axis) > 0) r[l] = addw(r[l], r[l - stride], P);
+  }
+}
+
+static int bit_length(uint64_t v) {
+  int n = 0;
+  while (v) { n++; v >>= 1; }
+  return n;
+}
+
+/* the integers of a block at escalation d: 0 if some |e / h_d| is too large */
+static int pq_quantize_block(const double* e, int B, int P, double inv0, int delta, int64_t* q) {
+  double inv = ldexp(inv0, delta);
+  double lim = ldexp(1.0, P - 2);
+  for (int l = 0; l < B; l++) {
+    double t = e[l] * inv;
+    if (!(fabs(t) < lim)) return 0;
+    q[l] = (int64_t)rint(t);
+  }
+  return 1;
+}
+
+/* code of a quantised block: predicted flag, width, values (zigzag) */
+static void pq_code(const int64_t* q, int d, int P, int* pred, int* w, uint64_t* z) {
+  int B = block_size(d);
+  int64_t r[64];
+  uint64_t zp[64], zq[64], mp = 0, mq = 0;
+  for (int l = 0; l < B; l++) r[l] = q[l];
+  orc_lorenzo_fwd(r, d, P);
+  for (int l = 0; l < B; l++) {
+    zp[l] = zigzag(r[l], P);
+    zq[l] = zigzag(q[l], P);
+    if (zp[l] > mp) mp = zp[l];
+    if (zq[l] > mq) mq = zq[l];
+  }
+  int wp = bit_length(mp), wq = bit_length(mq);
+  *pred = wp < wq;
+  *w = *pred ? wp : wq;
+  for (int l = 0; l < B; l++) z[l] = *pred ? zp[l] : zq[l];
+}
+
+static uint64_t pq_bits(int d, int delta, int w) {
+  return 2u + (uint64_t)(delta + 1) + 1u + 6u + (uint64_t)block_size(d) * (uint64_t)w;
+}
+
+static void pq_values(const int64_t* q, int B, double h0, int delta, int dtype, double* out) {
+  double h = ldexp(h0, -delta);
+  for (int l = 0; l < B; l++) {
+    double v = (double)q[l] * h;
+    out[l] = dtype == ORC_F32 ? (double)(float)v : v;
+  }
+}
+
+static block_result encode_block_pq(bitw* w, int dtype, int d, const double* e, const double* x,
+                                    const double* xt, const int* valid, double tau, double* xi) {
+  int B = block_size(d), P = prec_bits(dtype);
+  block_result res = {ORC_EMPTY, 0, 0, 0, 0.0, 0};
+  double zero[64] = {0};
+  double err_before = block_err(x, xt, zero, valid, B, dtype);
+  double h0 = 2.0 * tau, inv0 = 1.0 / h0;
+  int allzero = 1;
+  for (int l = 0; l < B; l++)
+    if (!is_zero_bits(e[l])) allzero = 0;
+  for (int l = 0; l < B; l++) xi[l] = 0.0;
+  int64_t q[64];
+  uint64_t z[64];
+  int pred = 0, width = 0;
+  if (!allzero) {
+    int delta = 0;
+    for (;;) {
+      int feasible = delta <= PQ_MAX_DELTA && pq_quantize_block(e, B, P, inv0, delta, q);
+      if (feasible) {
+        pq_code(q, d, P, &pred, &width, z);
+        feasible = pq_bits(d, delta, width) <= raw_bits(dtype, d);
+      }
+      if (feasible) {
+        double dv[64];
+        pq_values(q, B, h0, delta, dtype, dv);
+        double ea = block_err(x, xt, dv, valid, B, dtype);
+        if (ea <= tau && ea <= err_before) {
+          res.mode = ORC_CODED; res.delta = delta;
+          for (int l = 0; l < B; l++) xi[l] = dv[l];
+          break;
+        }
+      }
+      if (err_before <= tau) { res.mode = ORC_EMPTY; break; }
+      if (!feasible) { res.mode = ORC_RAW; break; }
+      delta++;
+    }
+  }
+  if (res.mode == ORC_RAW)
+    for (int l = 0; l < B; l++) xi[l] = e[l];
+  res.err = res.mode == ORC_EMPTY ? err_before : block_err(x, xt, xi, valid, B, dtype);
+  res.miss = (res.err <= tau && res.err <= err_before) ? 0 : 1;
+
+  if (res.mode == ORC_EMPTY) {
+    put_bit(w, 0);
+  } else if (res.mode == ORC_RAW) {
+    put_bit(w, 1);
+    put_bit(w, 1);
+    for (int l = 0; l < B; l++) {
+      if (dtype == ORC_F32) {
+        float f = (float)e[l];
+        uint32_t b;
+        memcpy(&b, &f, 4);
+        put_bits(w, b, 32);
+      } else {
+        uint64_t b;
+        memcpy(&b, &e[l], 8);
+        put_bits(w, b, 64);
+      }
+    }
+  } else {
+    put_bit(w, 1);
+    put_bit(w, 0);
+    for (int t = 0; t < res.delta; t++) put_bit(w, 1);
+    put_bit(w, 0);
+    put_bit(w, (unsigned)pred);
+    put_bits(w, (uint64_t)width, 6);
+    for (int l = 0; l < B; l++) put_bits(w, z[l], width);
+  }
+  return res;
+}
+
+static int decode_block_pq(bitr* r, int dtype, int d, double tau, double* out) {
+  int B = block_size(d), P = prec_bits(dtype);
+  for (int l = 0; l < B; l++) out[l] = 0.0;
+  if (!get_bit(r)) return ORC_EMPTY;
+  if (get_bit(r)) {
+    for (int l = 0; l < B; l++) {
+      if (dtype == ORC_F32) {
+        uint32_t b = (uint32_t)get_bits(r, 32);
+        float f;
+        memcpy(&f, &b, 4);
+        out[l] = (double)f;
+      } else {
+        uint64_t b = get_bits(r, 64);
+        memcpy(&out[l], &b, 8);
+      }
+    }
+    return ORC_RAW;
+  }
+  int delta = 0;
+  while (get_bit(r)) {
+    delta++;
+    if (delta > PQ_MAX_DELTA || r->overrun) return ORC_E_CORRUPT;
+  }
+  int pred = (int)get_bit(r);
+  int width = (int)get_bits(r, 6);
+  if (width > P || r->overrun) return ORC_E_CORRUPT;
+  int64_t q[64];
+  for (int l = 0; l < B; l++) q[l] = unzigzag(get_bits(r, width), P);
+  if (pred) orc_lorenzo_inv(q, d, P);
+  pq_values(q, B, 2.0 * tau, delta, dtype, out);
+  return ORC_CODED;
+}
+
+/* exported for tests */
+uint64_t orc_zigzag(int64_t r, int P) { return zigzag(r, P); }
+int64_t orc_unzigzag(uint64_t z, int P) { return unzigzag(z, P); }
+
 /* ------------------------------------------------------------------ */
 /* stream header (64 bytes, little-endian)                             */
-/*  0 u32 magic   4 u16 version  6 u8 dtype  7 u8 d                    */
+/*  0 u32 magic   4 u8 version   5 u8 codec  6 u8 dtype  7 u8 d       */
 /*  8 u64 nx     16 u64 ny      24 u64 nz                              */
 /* 32 f64 tau    40 i32 minexp  44 u32 chunk blocks                    */
 /* 48 u64 nchunks                56 u64 payload words (32-bit)          */
 /* then nchunks u32 chunk start offsets (in words, from payload start), */
 /* then the payload; every chunk starts on a 32-bit word boundary.     */
 /* ------------------------------------------------------------------ */
-static void wr_u16(uint8_t* p, uint16_t v) { p[0] = (uint8_t)v; p[1] = (uint8_t)(v >> 8); }
 static void wr_u32(uint8_t* p, uint32_t v) { for (int i = 0; i < 4; i++) p[i] = (uint8_t)(v >> (8 * i)); }
 static void wr_u64(uint8_t* p, uint64_t v) { for (int i = 0; i < 8; i++) p[i] = (uint8_t)(v >> (8 * i)); }
 static uint32_t rd_u32(const uint8_t* p) { uint32_t v = 0; for (int i = 0; i < 4; i++) v |= (uint32_t)p[i] << (8 * i); return v; }
 static uint64_t rd_u64(const uint8_t* p) { uint64_t v = 0; for (int i = 0; i < 8; i++) v |= (uint64_t)p[i] << (8 * i); return v; }
-static uint16_t rd_u16(const uint8_t* p) { return (uint16_t)(p[0] | (p[1] << 8)); }
 
 /* worst-case stream bytes for a field */
 uint64_t orc_stream_cap(const orc_field* f) {
@@ -630,12 +845,15 @@ uint64_t orc_stream_cap(const orc_field* f) {
  * x and xt = x~_{i-1} (Alg. 1, Sec. 4.1; Eq. (1), Sec. 4.3).  e must be
  * x - xt computed in the field type by the caller (the residual step of Alg. 1).
  */
-int orc_encode(const orc_field* f, const void* e, const void* x, const void* xt, double tau,
-               uint8_t* out, uint64_t cap, uint64_t* nbytes, orc_stats* st) {
+int orc_encode_codec(const orc_field* f, int codec, const void* e, const void* x, const void* xt, double tau,
+                     uint8_t* out, uint64_t cap, uint64_t* nbytes, orc_stats* st) {
   geom g;
   int rc = make_geom(f, &g);
   if (rc != ORC_OK) return rc;
   if (!(tau > 0.0) || !isfinite(tau)) return ORC_E_ARG;
+  if (codec != 0 && codec != 1) return ORC_E_ARG;
+  /* codec 1 keeps every bin h_d normal and 1 / (2 tau) finite */
+  if (codec == 1 && !(tau >= ldexp(1.0, -960) && tau <= ldexp(1.0, 1000))) return ORC_E_ARG;
   memset(st, 0, sizeof(*st));
   int B = g.B;
   int minexp = orc_minexp(tau);
@@ -662,7 +880,8 @@ int orc_encode(const orc_field* f, const void* e, const void* x, const void* xt,
         tb[l] = load_val(xt, idx, f->dtype);
         valid[l] = sample_valid(f, &g, b, l);
       }
-      block_result res = encode_block(&w, f->dtype, f->d, eb, xb, tb, valid, tau, minexp, xi);
+      block_result res = codec == 0 ? encode_block(&w, f->dtype, f->d, eb, xb, tb, valid, tau, minexp, xi)
+                                    : encode_block_pq(&w, f->dtype, f->d, eb, xb, tb, valid, tau, xi);
       if (res.mode == ORC_EMPTY) st->nempty++;
       else if (res.mode == ORC_RAW) st->nraw++;
       else st->ncoded++;
@@ -676,7 +895,8 @@ int orc_encode(const orc_field* f, const void* e, const void* x, const void* xt,
   uint64_t words = (w.pos + 31) / 32;
   uint8_t* h = out;
   wr_u32(h + 0, ORC_MAGIC);
-  wr_u16(h + 4, ORC_VERSION);
+  h[4] = (uint8_t)ORC_VERSION;
+  h[5] = (uint8_t)codec;
   h[6] = (uint8_t)f->dtype;
   h[7] = (uint8_t)f->d;
   wr_u64(h + 8, f->dims[0]);
@@ -693,11 +913,17 @@ int orc_encode(const orc_field* f, const void* e, const void* x, const void* xt,
   return ORC_OK;
 }
 
+/* codec 0, the block-transform codec */
+int orc_encode(const orc_field* f, const void* e, const void* x, const void* xt, double tau,
+               uint8_t* out, uint64_t cap, uint64_t* nbytes, orc_stats* st) {
+  return orc_encode_codec(f, 0, e, x, xt, tau, out, cap, nbytes, st);
+}
+
 /* parse and validate a stream header; fills f and the payload extents */
 int orc_stream_info(const uint8_t* s, uint64_t nbytes, orc_field* f, double* tau,
                     uint64_t* nchunks, uint64_t* words) {
   if (nbytes < ORC_HEADER_BYTES) return ORC_E_CORRUPT;
-  if (rd_u32(s) != ORC_MAGIC || rd_u16(s + 4) != ORC_VERSION) return ORC_E_CORRUPT;
+  if (rd_u32(s) != ORC_MAGIC || s[4] != ORC_VERSION || s[5] > 1) return ORC_E_CORRUPT;
   f->dtype = s[6];
   f->d = s[7];
   f->dims[0] = rd_u64(s + 8);
@@ -730,6 +956,7 @@ int orc_decode(const uint8_t* s, uint64_t nbytes, const orc_field* expect, void*
   geom g;
   make_geom(&f, &g);
   int minexp = orc_minexp(tau);
+  int codec = s[5];
   const uint8_t* index = s + ORC_HEADER_BYTES;
   const uint8_t* payload = index + 4 * nchunks;
   for (uint64_t c = 0; c < nchunks; c++) {
@@ -739,7 +966,7 @@ int orc_decode(const uint8_t* s, uint64_t nbytes, const orc_field* expect, void*
     bitr r = {payload, end * 32, start * 32, 0};
     for (uint64_t b = c * ORC_CHUNK_BLOCKS; b < (c + 1) * ORC_CHUNK_BLOCKS && b < g.nblocks; b++) {
       double v[64];
-      int m = decode_block(&r, f.dtype, f.d, minexp, v);
+      int m = codec == 0 ? decode_block(&r, f.dtype, f.d, minexp, v) : decode_block_pq(&r, f.dtype, f.d, tau, v);
       if (m < 0 || r.overrun) return ORC_E_CORRUPT;
       for (int l = 0; l < g.B; l++)
         if (sample_valid(&f, &g, b, l)) store_val(out, sample_index(&f, &g, b, l), v[l], f.dtype);
@@ -763,6 +990,31 @@ int orc_encode_one_block(int dtype, int d, const double* e, const double* x, con
   *p = res.p;
   *err = res.err;
   return res.miss ? 1 : 0;
+}
+
+/* the same for codec 1 (tests): delta receives the escalation count */
+int orc_encode_one_block_pq(int dtype, int d, const double* e, const double* x, const double* xt,
+                            double tau, uint8_t* buf, uint64_t cap_bytes, uint64_t* nbits,
+                            int* mode, int* delta, double* err, double* xi) {
+  bitw w = {buf, cap_bytes * 8, 0, 0};
+  memset(buf, 0, (size_t)cap_bytes);
+  int valid[64];
+  for (int l = 0; l < 64; l++) valid[l] = 1;
+  block_result res = encode_block_pq(&w, dtype, d, e, x, xt, valid, tau, xi);
+  if (w.overflow) return ORC_E_NOMEM;
+  *nbits = w.pos;
+  *mode = res.mode;
+  *delta = res.delta;
+  *err = res.err;
+  return res.miss ? 1 : 0;
+}
+int orc_decode_one_block_pq(int dtype, int d, double tau, const uint8_t* buf, uint64_t nbits,
+                            double* out, uint64_t* used) {
+  bitr r = {buf, nbits, 0, 0};
+  int m = decode_block_pq(&r, dtype, d, tau, out);
+  *used = r.pos;
+  if (r.overrun) return ORC_E_CORRUPT;
+  return m;
 }
 
 /* decode a single block (tests) */
