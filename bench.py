@@ -99,169 +99,229 @@ def load_valu_instructions(kernel, workload):
     return e.get("valu_instr_per_launch")
 
 
-def cpu_baseline(x, taus, planes):
-    """The oracle as it stands, single-threaded, on a z-slab of the same field."""
-    from oracle import driver
-    xs = np.ascontiguousarray(x[:planes])
+def cpu_baseline(x, taus, planes, pool_planes):
+    """The oracle as it stands on a z-slab of the same field: on all host
+    cores (its serial driver over independent chunk-aligned sub-slabs on a
+    thread pool, the unchanged serial code per sub-slab) and on one core.
+    Work per value is the bench step's: compress n components, retrieve
+    k = 1..n from scratch."""
+    from oracle import driver, pool
     n = len(taus)
-    t0 = time.perf_counter()
-    comps, meta = driver.compress(xs, taus)
-    for k in range(1, n + 1):
-        driver.reconstruct(comps, k, xs.shape, xs.dtype)
-    dt = time.perf_counter() - t0
-    gbs = xs.nbytes * (1 + n) / dt / 1e9
-    return {"value": gbs, "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": "z-slab %dx%dx%d of the same field (%d values), compress %d components + retrieve "
-                      "k=1..%d, %.1f s" % (xs.shape[0], xs.shape[1], xs.shape[2], xs.size, n, n, dt)}
+
+    def one(xs):
+        comps, meta = driver.compress(xs, taus)
+        for k in range(1, n + 1):
+            driver.reconstruct(comps, k, xs.shape, xs.dtype)
+
+    res = None
+    if pool_planes > 0:
+        xs = np.ascontiguousarray(x[:pool_planes])
+        sub = pool.slab_planes(xs.shape)
+        parts = pool.slabs(xs.shape, sub)
+        cores = min(os.cpu_count() or 1, len(parts))
+        from concurrent.futures import ThreadPoolExecutor
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(max_workers=cores) as ex:
+            list(ex.map(lambda zz: one(np.ascontiguousarray(xs[zz[0]:zz[1]])), parts))
+        dt = time.perf_counter() - t0
+        res = {"value": xs.nbytes * (1 + n) / dt / 1e9, "unit": "GB/s", "cores": cores, "kind": "oracle",
+               "sample": "z-slab %dx%dx%d of the same field (%d values) as %d independent %d-plane slabs on %d "
+                         "threads, compress %d components + retrieve k=1..%d, %.1f s" %
+                         (xs.shape[0], xs.shape[1], xs.shape[2], xs.size, len(parts), sub, cores, n, n, dt)}
+    if planes > 0:
+        xs = np.ascontiguousarray(x[:planes])
+        t0 = time.perf_counter()
+        one(xs)
+        dt = time.perf_counter() - t0
+        single = {"value": xs.nbytes * (1 + n) / dt / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
+                  "sample": "z-slab %dx%dx%d of the same field (%d values), compress %d components + retrieve "
+                            "k=1..%d, %.1f s" % (xs.shape[0], xs.shape[1], xs.shape[2], xs.size, n, n, dt)}
+        if res is None:
+            return single
+        res["single_core"] = single
+    return res
 
 
-def bench_batched(args):
+def batched_measure(ctx, nfields, steps, warmup):
     """256 fields, edges log-uniform in [16, 256] per axis, f32/f64 alternating,
     6 components, tau_i = range_f * 4^-i: one tuned graph per call vs a loop
-    of single-field compressions."""
+    of single-field compressions (the same kernels, one pmc_compress each)."""
     import torch
-    from paper_2308_11759_amd import inputs, pmc
-    dev = torch.device("cuda", 0)
-    shapes = inputs.batched_shapes(args.fields)
-    log("generating %d fields" % len(shapes))
+    from paper_2308_11759_amd import inputs
+    dev = ctx.device
+    shapes = inputs.batched_shapes(nfields)
+    log("batched: generating %d fields" % len(shapes))
     xs, taus = [], []
     for f, (shape, is32) in enumerate(shapes):
         xh = inputs.spectral_field(shape, seed=100 + f, dtype=np.float32 if is32 else np.float64)
         r = float(xh.max()) - float(xh.min())
         xs.append(torch.from_numpy(xh).to(dev))
         taus.append([r * 4.0 ** -i for i in range(1, 7)])
-        if f % 32 == 31:
-            log("  %d fields" % (f + 1))
     total = sum(x.numel() * x.element_size() for x in xs)
     nval = sum(x.numel() for x in xs)
-    ctx = pmc.Context(0)
     batch = ctx.batch([(tuple(x.shape), x.dtype) for x in xs], taus)
     streams = torch.empty_like(batch.streams)
-    log("tuning (%d schedules)" % 12)
+    log("batched: tuning (12 schedules)")
     gm, order, tms = batch.tune(xs)
-    log("tuned: grid x%d, order %d, graph %.3f ms" % (gm, order, tms))
-    for _ in range(args.warmup):
+    log("batched: tuned grid x%d, order %d, graph %.3f ms" % (gm, order, tms))
+    for _ in range(warmup):
         batch.compress(xs, streams=streams)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         stores = batch.compress(xs, streams=streams)
     torch.cuda.synchronize()
-    t_batch = (time.perf_counter() - t0) / args.steps
-    # baseline: one pmc_compress per field
+    t_batch = (time.perf_counter() - t0) / steps
     outs = [torch.empty(ctx.compress_sizes(x, 6)[1] * 6, dtype=torch.uint8, device=dev) for x in xs]
     for x, t, o in zip(xs, taus, outs):
         ctx.compress(x, t, streams=o)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         singles = [ctx.compress(x, t, streams=o) for x, t, o in zip(xs, taus, outs)]
     torch.cuda.synchronize()
-    t_loop = (time.perf_counter() - t0) / args.steps
+    t_loop = (time.perf_counter() - t0) / steps
     same = all(bool(torch.equal(a.stream(i), b.stream(i))) for a, b in zip(stores, singles) for i in range(6))
     sbytes = sum(m["bytes"] for st in stores for m in st.info)
-    rec = {"metric": "batched compress GB/s (256 mixed fields, 6 comps)", "value": total / t_batch / 1e9,
+    res = {"fields": len(xs), "values": nval, "bytes": total, "components": 6, "steps": steps,
+           "schedule": {"grid_mult": gm, "order": order}, "tuned_graph_ms": tms,
+           "ms_per_call": t_batch * 1e3, "gbs": total / t_batch / 1e9,
+           "per_field_loop_ms": t_loop * 1e3, "per_field_loop_gbs": total / t_loop / 1e9,
+           "speedup_vs_loop": t_loop / t_batch, "identical_to_single_field": same,
+           "rate_bits_per_value": 8.0 * sbytes / nval}
+    del stores, singles, outs, streams, batch, xs
+    return res
+
+
+def bench_batched(args):
+    from paper_2308_11759_amd import pmc
+    ctx = pmc.Context(0)
+    b = batched_measure(ctx, args.fields, args.steps, args.warmup)
+    rec = {"metric": "batched compress GB/s (256 mixed fields, 6 comps)", "value": b["gbs"],
            "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-           "ms_per_step": t_batch * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "ms_per_step": b["ms_per_call"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32+f64", "data": "synthetic",
-           "config": {"workload": "batched_256", "fields": len(xs), "values": nval, "components": 6,
-                      "schedule": {"grid_mult": gm, "order": order}},
-           "per_field_loop_gbs": total / t_loop / 1e9, "speedup_vs_loop": t_loop / t_batch,
-           "identical_to_single_field": same, "rate_bits_per_value": 8.0 * sbytes / nval}
+           "config": {"workload": "batched_256", "fields": b["fields"], "values": b["values"], "components": 6,
+                      "schedule": b["schedule"]},
+           "per_field_loop_gbs": b["per_field_loop_gbs"], "speedup_vs_loop": b["speedup_vs_loop"],
+           "identical_to_single_field": b["identical_to_single_field"],
+           "rate_bits_per_value": b["rate_bits_per_value"]}
     print(json.dumps(rec))
 
 
-def bench_served(args):
-    """64 stored fields (edge log-uniform 64..384, f32/f64 alternating, 10
-    components, tau_i = range * 10^(-i/2)); open-loop Poisson queries (field
-    uniform, tolerance log-uniform in [1e-5, 1e-1] * range).  Served form:
-    the library's request loop (continuous batching, device partial-sum cache,
-    64 GB budget).  Plain form: the same trace, first come first served, one
-    Alg. 2 retrieval from scratch per query."""
-    import threading
+def build_served_store(ctx):
+    """64 stored fields: cubic, edge log-uniform in [64, 384], f32/f64
+    alternating, 10 components, tau_i = range * 10^(-i/2)."""
     import torch
-    from paper_2308_11759_amd import inputs, pmc
-    dev = torch.device("cuda", 0)
-    ctx = pmc.Context(0)
+    from paper_2308_11759_amd import inputs
     shapes = inputs.served_shapes(64)
     stores, ranges, nbytes = [], [], []
-    log("building the store: %d fields" % len(shapes))
+    log("served: building the store of %d fields" % len(shapes))
     for f, (shape, is32) in enumerate(shapes):
         xh = inputs.spectral_field(shape, seed=200 + f, dtype=np.float32 if is32 else np.float64)
         r = float(xh.max()) - float(xh.min())
-        x = torch.from_numpy(xh).to(dev)
+        x = torch.from_numpy(xh).to(ctx.device)
         taus = [r * 10.0 ** (-i / 2.0) for i in range(1, 11)]
         stores.append(ctx.compress(x, taus))
         ranges.append(r)
         nbytes.append(x.numel() * x.element_size())
         del x, xh
-        if f % 8 == 7:
-            log("  %d fields stored" % (f + 1))
+        if f % 16 == 15:
+            log("served:   %d fields stored" % (f + 1))
     torch.cuda.synchronize()
-    results = {}
-    rates = [int(v) for v in args.rates.split(",")]
-    for lam in rates:
-        trace = inputs.query_trace(len(stores), lam, args.queries, seed=7 + lam)
-        trace = [(t, f, rel * ranges[f]) for t, f, rel in trace]
-        # served
-        srv = pmc.Server(ctx, arena_bytes=args.arena_gb << 30, budget_bytes=args.arena_gb << 30, max_batch=64)
-        for st in stores:
-            srv.add(st)
-        tickets = [None] * len(trace)
-        lat = [None] * len(trace)
-        t0 = time.perf_counter()
+    return stores, ranges, nbytes
 
-        def submitter():
-            for i, (ta, f, tol) in enumerate(trace):
-                d = t0 + ta - time.perf_counter()
-                if d > 0:
-                    time.sleep(d)
-                tickets[i] = srv.submit(f, tol)
 
-        th = threading.Thread(target=submitter)
-        th.start()
-        done = 0
-        while done < len(trace):
-            progressed = False
-            for i in range(len(trace)):
-                if lat[i] is None and tickets[i] is not None:
-                    d, st, l = srv.poll(tickets[i])
-                    if d:
-                        assert st == pmc.OK, st
-                        lat[i] = l
-                        srv.release(tickets[i])
-                        done += 1
-                        progressed = True
-            if not progressed:
-                time.sleep(0.0002)
-        th.join()
-        makespan = time.perf_counter() - t0
-        sstats = srv.stats()
-        srv.close()
-        out_bytes = sum(nbytes[f] for _, f, _ in trace)
-        served = {"p50_ms": 1e3 * float(np.percentile(lat, 50)), "p99_ms": 1e3 * float(np.percentile(lat, 99)),
-                  "gbs": out_bytes / makespan / 1e9, "makespan_s": makespan,
-                  "hits": sstats["hits"], "partial": sstats["partial"], "misses": sstats["misses"],
-                  "steps": sstats["steps"], "max_queue": sstats["max_queue"]}
-        # plain: FIFO, one retrieval from scratch per query
-        outs = [torch.empty(st.shape, dtype=st.dtype, device=dev) for st in stores]
-        plat = []
-        t0 = time.perf_counter()
-        for ta, f, tol in trace:
-            d = t0 + ta - time.perf_counter()
+def served_measure(ctx, stores, ranges, nbytes, lam, nqueries, arena_gb):
+    """One open-loop Poisson trace (field uniform, tolerance log-uniform in
+    [1e-5, 1e-1] * range) replayed twice on the same GPU.  Served: the
+    library's request loop (continuous batching, device partial-sum cache,
+    HBM budget = arena).  Plain: first come first served, one Alg. 2 retrieval
+    from scratch per query.  Both latencies run from the trace's scheduled
+    arrival on the library's clock to completion, so a submitter running late
+    counts against both forms alike."""
+    import threading
+    import torch
+    from paper_2308_11759_amd import inputs, pmc
+    trace = inputs.query_trace(len(stores), lam, nqueries, seed=7 + lam)
+    trace = [(t, f, rel * ranges[f]) for t, f, rel in trace]
+    out_bytes = sum(nbytes[f] for _, f, _ in trace)
+    # served
+    srv = pmc.Server(ctx, arena_bytes=arena_gb << 30, budget_bytes=arena_gb << 30, max_batch=64)
+    for st in stores:
+        srv.add(st)
+    tickets = [None] * len(trace)
+    lat = [None] * len(trace)
+    t0 = pmc.clock() + 0.05
+
+    def submitter():
+        for i, (ta, f, tol) in enumerate(trace):
+            d = t0 + ta - pmc.clock()
             if d > 0:
                 time.sleep(d)
-            k = stores[f].select_k(tol)
-            ctx.retrieve(stores[f], k, out=outs[f])
-            torch.cuda.synchronize()
-            plat.append(time.perf_counter() - (t0 + ta))
-        pmake = time.perf_counter() - t0
-        plain = {"p50_ms": 1e3 * float(np.percentile(plat, 50)), "p99_ms": 1e3 * float(np.percentile(plat, 99)),
-                 "gbs": out_bytes / pmake / 1e9, "makespan_s": pmake}
-        del outs
-        results[str(lam)] = {"served": served, "plain": plain}
-        log("lambda %d: served p50 %.2f ms p99 %.2f ms | plain p50 %.2f ms p99 %.2f ms" %
-            (lam, served["p50_ms"], served["p99_ms"], plain["p50_ms"], plain["p99_ms"]))
+            tickets[i] = srv.submit(f, tol, arrival=t0 + ta)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    outstanding = set()
+    nsub = 0
+    done = 0
+    while done < len(trace):
+        while nsub < len(trace) and tickets[nsub] is not None:
+            outstanding.add(nsub)
+            nsub += 1
+        finished = []
+        for i in outstanding:
+            d, st, l = srv.poll(tickets[i])
+            if d:
+                assert st == pmc.OK, st
+                lat[i] = l
+                srv.release(tickets[i])
+                finished.append(i)
+        for i in finished:
+            outstanding.discard(i)
+        done += len(finished)
+        if not finished:
+            time.sleep(0.0005)
+    th.join()
+    makespan = pmc.clock() - t0
+    sstats = srv.stats()
+    srv.close()
+    served = {"p50_ms": 1e3 * float(np.percentile(lat, 50)), "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+              "gbs": out_bytes / makespan / 1e9, "makespan_s": makespan,
+              "hits": sstats["hits"], "partial": sstats["partial"], "misses": sstats["misses"],
+              "steps": sstats["steps"], "max_queue": sstats["max_queue"]}
+    # plain: FIFO, one retrieval from scratch per query
+    outs = [torch.empty(st.shape, dtype=st.dtype, device=ctx.device) for st in stores]
+    plat = []
+    torch.cuda.synchronize()
+    t0 = pmc.clock() + 0.05
+    for ta, f, tol in trace:
+        d = t0 + ta - pmc.clock()
+        if d > 0:
+            time.sleep(d)
+        k = stores[f].select_k(tol)
+        ctx.retrieve(stores[f], k, out=outs[f])
+        torch.cuda.synchronize()
+        plat.append(pmc.clock() - (t0 + ta))
+    pmake = pmc.clock() - t0
+    plain = {"p50_ms": 1e3 * float(np.percentile(plat, 50)), "p99_ms": 1e3 * float(np.percentile(plat, 99)),
+             "gbs": out_bytes / pmake / 1e9, "makespan_s": pmake}
+    del outs
+    log("served %d QPS, %d queries: served p50 %.3f ms p99 %.3f ms | plain p50 %.3f ms p99 %.3f ms" %
+        (lam, nqueries, served["p50_ms"], served["p99_ms"], plain["p50_ms"], plain["p99_ms"]))
+    return {"rate_qps": lam, "queries": nqueries, "latency_from": "scheduled arrival", "served": served,
+            "plain": plain}
+
+
+def bench_served(args):
+    from paper_2308_11759_amd import pmc
+    ctx = pmc.Context(0)
+    stores, ranges, nbytes = build_served_store(ctx)
+    rates = [int(v) for v in args.rates.split(",")]
+    results = {}
+    for lam in rates:
+        results[str(lam)] = served_measure(ctx, stores, ranges, nbytes, lam, args.queries, args.arena_gb)
     top = results[str(rates[-1])]
     rec = {"metric": "query p99 latency, served vs plain (64 fields, 10 comps)",
            "value": top["served"]["p99_ms"], "unit": "ms", "n_gpus": 1, "steps": args.queries, "warmup": 0,
@@ -322,14 +382,20 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="bulk_512_f32", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-planes", type=int, default=16, help="z-planes of the oracle sample (0 = skip)")
+    ap.add_argument("--cpu-planes", type=int, default=16, help="z-planes of the one-core oracle sample (0 = skip)")
+    ap.add_argument("--cpu-pool-planes", type=int, default=64,
+                    help="z-planes of the all-cores oracle sample (0 = skip)")
     ap.add_argument("--literal", action="store_true", help="one decode pass per component (literal Alg. 2)")
     ap.add_argument("--refine-reps", type=int, default=3,
                     help="repetitions of the incremental refine chain k = 1..n timed after the steps (0 = skip)")
     ap.add_argument("--fields", type=int, default=256, help="batched workload: number of fields")
-    ap.add_argument("--queries", type=int, default=2000, help="served workload: queries per arrival rate")
+    ap.add_argument("--queries", type=int, default=10000, help="served workload: queries per arrival rate")
     ap.add_argument("--rates", default="200,500,1000,2000", help="served workload: arrival rates (QPS)")
     ap.add_argument("--arena-gb", type=int, default=64, help="served workload: cache arena and budget")
+    ap.add_argument("--served-rate", type=int, default=2000,
+                    help="default workload: arrival rate of the served sub-measurement (0 = skip)")
+    ap.add_argument("--batched-fields", type=int, default=256,
+                    help="default workload: fields of the batched sub-measurement (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run three 512 MiB device-to-device copies (scale for rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -508,6 +574,22 @@ def main():
             lossless = {"components": len(ltaus), "first_exact_k": first, "tau_first_exact": ltaus[first - 1],
                         "bytes": nbytes, "ratio": N * s / nbytes}
         del lstore, lstreams
+        # a schedule aimed at the lossless end: three components, the last
+        # below every float32 difference (2^-150), the middle one where the
+        # residual is left with few bits (picked on an oracle sample of the
+        # same field from 2^-a, 2^-b with a in 8..14, b in 26..36)
+        ttaus = [2.0 ** -8, 2.0 ** -32, 2.0 ** -150]
+        lws, lcap = ctx.compress_sizes(xd, 3)
+        lstreams = torch.empty(lcap * 3, dtype=torch.uint8, device=dev)
+        tstore = ctx.compress(xd, ttaus, streams=lstreams)
+        exact = bool(torch.equal(ctx.retrieve(tstore, 3, out=out), xd))
+        tbytes = sum(m["bytes"] for m in tstore.info)
+        targeted = {"taus": ttaus, "exact_at_3": exact, "bytes": tbytes, "ratio": N * s / tbytes,
+                    "rates_bits_per_value": [round(8.0 * m["bytes"] / N, 3) for m in tstore.info]}
+        if lossless is None:
+            lossless = {}
+        lossless["targeted_schedule"] = targeted
+        del tstore, lstreams
 
     # the second compressor (Sec. 3's float32 cast) on float64 fields: three
     # components, timed; x~_3 must equal x for normal values
@@ -533,6 +615,47 @@ def main():
     if args.steps > 0 and args.refine_reps > 0 and args.workload.startswith("bulk"):
         rdist = rate_distortion(ctx, xd, rng, 24 if dt == np.float32 else 48, out)
 
+    # the second codec (prediction and quantisation) behind the same driver,
+    # on the same field and schedule: one step = compress + retrieve k = 1..n
+    pred = None
+    if args.steps > 0 and args.refine_reps > 0 and args.workload.startswith("bulk"):
+        ctx.set_option(pmc.OPT_CODEC, pmc.CODEC_PREDICTION)
+        pstreams = torch.empty(cap1 * n, dtype=torch.uint8, device=dev)
+        pstore = ctx.compress(xd, taus, streams=pstreams)
+        for k in range(1, n + 1):
+            ctx.retrieve(pstore, k, out=out)
+        torch.cuda.synchronize()
+        err = float((xd.double() - out.double()).abs().max())
+        assert err == pstore.info[n - 1]["linf"] <= taus[n - 1]
+        reps = 5
+        ctx.set_option(pmc.OPT_PROFILE, 1)
+        ctx.prof_read(reset=True)
+        ev8, ev9 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev8.record()
+        for _ in range(reps):
+            pstore = ctx.compress(xd, taus, streams=pstreams)
+            for k in range(1, n + 1):
+                ctx.retrieve(pstore, k, out=out)
+        ev9.record()
+        torch.cuda.synchronize()
+        pprof = ctx.prof_read(reset=True)
+        ctx.set_option(pmc.OPT_PROFILE, 0)
+        ctx.set_option(pmc.OPT_CODEC, pmc.CODEC_TRANSFORM)
+        pms = ev8.elapsed_time(ev9) / reps
+        pk = {name: {"launches_per_step": l / reps, "ms_per_step": m / reps, "avg_launch_ms": m / max(l, 1)}
+              for name, (l, m) in pprof.items()}
+        penc = sum(pk.get(kk, {}).get("ms_per_step", 0.0) for kk in ("k_encode_pq_" + tname, "k_scan",
+                                                                      "k_pack_" + tname))
+        pdec = pk.get("k_decode_pq_" + tname, {}).get("ms_per_step", 0.0)
+        pred = {"ms_per_step": pms, "gbs": N * s * (1 + n) / (pms / 1e3) / 1e9,
+                "compress_gbs": N * s / (penc / 1e3) / 1e9 if penc else None,
+                "retrieve_all_k_gbs": N * s * n / (pdec / 1e3) / 1e9 if pdec else None,
+                "rates_bits_per_value": [round(8.0 * m["bytes"] / N, 3) for m in pstore.info],
+                "linf": [m["linf"] for m in pstore.info],
+                "escalated_blocks": [m["nesc"] for m in pstore.info], "raw_blocks": [m["nraw"] for m in pstore.info],
+                "kernels": pk}
+        del pstore, pstreams
+
     if args.copy_calibration:
         src = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
@@ -542,9 +665,25 @@ def main():
         del src, dst
 
     cpu = None
-    if args.cpu_planes > 0:
-        log("oracle baseline on %d z-planes" % args.cpu_planes)
-        cpu = cpu_baseline(x, taus, args.cpu_planes)
+    if args.cpu_planes > 0 or args.cpu_pool_planes > 0:
+        log("oracle baseline on %d z-planes (all cores) and %d (one core)" % (args.cpu_pool_planes, args.cpu_planes))
+        cpu = cpu_baseline(x, taus, args.cpu_planes, args.cpu_pool_planes)
+
+    # the other half of the headline metric, on the same GPU: many fields
+    # coded in one captured launch (batched), and progressive-retrieval
+    # queries served with continuous batching against plain retrieval
+    batched = served = None
+    if args.workload == "bulk_512_f32" and args.steps > 0 and (args.batched_fields > 0 or args.served_rate > 0):
+        del store, streams, out
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        if args.batched_fields > 0:
+            batched = batched_measure(ctx, args.batched_fields, steps=5, warmup=2)
+        if args.served_rate > 0:
+            sstores, sranges, snbytes = build_served_store(ctx)
+            served = served_measure(ctx, sstores, sranges, snbytes, args.served_rate, args.queries, args.arena_gb)
+            served["fields"] = len(sstores)
+            del sstores
 
     rec = {
         "metric": "compress/retrieve GB/s (%d^3 %s, %d comps)" % (x.shape[0], "f32" if dt == np.float32 else "f64", n),
@@ -569,6 +708,7 @@ def main():
         "region_retrieval": region,
         "lossless": lossless,
         "cast_codec": cast,
+        "prediction_codec": pred,
         "rate_distortion": rdist,
         "lag1_autocorrelation_xyz": [round(v, 4) for v in inputs.lag1_autocorrelation(x)],
         "rates_bits_per_value": [round(8.0 * m["bytes"] / N, 3) for m in info],
@@ -577,6 +717,8 @@ def main():
         "kernels": kern,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched": batched,
+        "served": served,
     }
     print(json.dumps(rec))
 

@@ -48,7 +48,8 @@ typedef enum {
 
 typedef enum { PMC_F32 = 1, PMC_F64 = 2 } pmc_dtype;
 
-/* A 3-D field: extents (x fastest) and element type. */
+/* A 3-D field: extents (x fastest) and element type.  Every call accepts at
+ * most 2^36 values and 2^32 blocks of 4x4x4 (PMC_E_ARG beyond). */
 typedef struct {
   uint64_t nx, ny, nz;
   int32_t dtype; /* pmc_dtype */
@@ -72,10 +73,25 @@ const char* pmc_last_error(const pmc_ctx* ctx);
  *    per component (x~ read and written each time), the literal Alg. 2 loop.
  *    Both give bit-identical results.
  *  PMC_OPT_SYNC_CHECK (default 0): decode calls synchronise the stream and
- *    report PMC_E_CORRUPT when a kernel found a malformed stream. */
+ *    report PMC_E_CORRUPT when a kernel found a malformed stream.  With 0 the
+ *    calls only enqueue work and return PMC_OK; a block whose stream does
+ *    not parse is then written as quiet NaNs instead of being left as it
+ *    was. */
 /*  PMC_OPT_PROFILE (default 0): bracket every kernel launch with HIP events
- *    on the context stream; pmc_prof_read returns the per-kernel totals. */
-enum { PMC_OPT_FUSED_DECODE = 1, PMC_OPT_SYNC_CHECK = 2, PMC_OPT_PROFILE = 3 };
+ *    on the context stream; pmc_prof_read returns the per-kernel totals.
+ *  PMC_OPT_CODEC (default 0): the compressor C / D that pmc_compress puts
+ *    behind the multi-component driver, which works with any error-bounded
+ *    lossy compressor (Sec. 6.2):
+ *      0  the zfp-style block-transform codec (stream format version 1),
+ *      1  prediction and uniform quantisation on the same 4x4x4 blocks (a
+ *         prediction-based compressor, Sec. 5): residuals quantised to
+ *         multiples of 2 tau (halved per escalation step), a block-local
+ *         Lorenzo predictor where it narrows the code, zigzag values at one
+ *         width per block; tolerances must lie in [2^-960, 2^1000].
+ *    The codec is recorded in every stream header (byte 5) and in the
+ *    store; retrieval, refinement, region retrieval, serialisation and the
+ *    server follow it.  Batches (pmc_batch_*) use codec 0. */
+enum { PMC_OPT_FUSED_DECODE = 1, PMC_OPT_SYNC_CHECK = 2, PMC_OPT_PROFILE = 3, PMC_OPT_CODEC = 4 };
 pmc_status pmc_ctx_set_option(pmc_ctx* ctx, int option, int value);
 
 /* Per-kernel launch count and summed duration (milliseconds, from HIP events)
@@ -104,7 +120,7 @@ pmc_status pmc_range(pmc_ctx* ctx, const pmc_field* f, const void* d_x, void* d_
  * bytes of device scratch.  Sums are float64 in a fixed order, so a result
  * repeats bit for bit.  Synchronises the context's stream.  Errors:
  * PMC_E_ARG (null pointer, bad field), PMC_E_NOMEM (workspace too small),
- * PMC_E_HIP. */
+ * PMC_E_DEVICE. */
 size_t pmc_stats_ws_bytes(void);
 pmc_status pmc_accuracy_gain(pmc_ctx* ctx, const pmc_field* f, const void* d_x, const void* d_xt, double rate,
                              void* d_ws, size_t ws_bytes, double out[3]);
@@ -122,7 +138,7 @@ pmc_status pmc_accuracy_gain(pmc_ctx* ctx, const pmc_field* f, const void* d_x, 
  * d_ws: at least 256 bytes of device scratch.  pmc_cast_retrieve writes
  * x~_k = (...((+0 + y_1) + y_2) ...) + y_k, 0 <= k <= 32, in the field's type
  * (enqueued only).  Non-finite input gives unspecified errors.  Errors:
- * PMC_E_ARG, PMC_E_NOMEM, PMC_E_HIP. */
+ * PMC_E_ARG, PMC_E_NOMEM, PMC_E_DEVICE. */
 pmc_status pmc_cast_compress(pmc_ctx* ctx, const pmc_field* f, const void* d_x, int n, float* d_comps, void* d_ws,
                              size_t ws_bytes, double* linf);
 pmc_status pmc_cast_retrieve(pmc_ctx* ctx, const pmc_field* f, const float* d_comps, int k, void* d_out);
@@ -148,6 +164,8 @@ pmc_status pmc_compress(pmc_ctx* ctx, const pmc_field* f, const void* d_x, int n
 /* Per-component metadata (arrays of store n entries; any may be NULL). */
 pmc_status pmc_store_info(const pmc_store* s, int* n, double* tau, double* linf, uint64_t* bytes,
                           uint64_t* nraw, uint64_t* nesc);
+/* The codec of a store's components (PMC_OPT_CODEC's values). */
+pmc_status pmc_store_codec(const pmc_store* s, int* codec);
 /* Block counts of component i (0-based): counts[0..4] = empty, coded, raw,
  * escalated (coded with more planes than the tolerance alone asks for) and
  * tolerance misses. */
@@ -194,8 +212,13 @@ pmc_status pmc_retrieve_box(pmc_ctx* ctx, const pmc_store* s, int k, const uint6
  * host_buf == NULL only *used is set to the size needed. */
 pmc_status pmc_store_serialize(pmc_ctx* ctx, const pmc_store* s, void* host_buf, size_t cap, size_t* used);
 /* Rebuild a store from a serialised blob, uploading its streams into
- * d_streams (capacity cap, caller-owned; see pmc_store_device_bytes).  Stream
- * headers and chunk indexes are validated on the host (PMC_E_CORRUPT). */
+ * d_streams (capacity cap, caller-owned).  pmc_store_device_bytes validates
+ * the blob on the host (sizes with checked arithmetic, every stream header
+ * and chunk index; PMC_E_CORRUPT otherwise) and reports the device bytes a
+ * store needs: the per-block indexes, the streams and a 256-byte status word.
+ * pmc_store_deserialize validates the same way, uploads, rebuilds the
+ * per-block indexes on the device and synchronises; a payload that does not
+ * parse gives PMC_E_CORRUPT and no store. */
 pmc_status pmc_store_device_bytes(const void* host_buf, size_t size, size_t* need);
 pmc_status pmc_store_deserialize(pmc_ctx* ctx, const void* host_buf, size_t size, void* d_streams, size_t cap,
                                  pmc_store** out);
@@ -256,7 +279,16 @@ pmc_status pmc_server_create(pmc_ctx* ctx, size_t hbm_budget, void* d_arena, siz
 pmc_status pmc_server_add(pmc_server* s, const pmc_store* store, int* field_id);
 /* PMC_E_UNREACHABLE when tol is below the field's last tolerance */
 pmc_status pmc_server_submit(pmc_server* s, int field_id, double tol, void* d_out, uint64_t* ticket);
-/* latency_s = completion - submission in seconds (-1 while running) */
+/* Seconds on the monotonic clock the server measures latencies with. */
+double pmc_clock(void);
+/* As pmc_server_submit, with the query's arrival time given on pmc_clock()'s
+ * clock (e.g. its scheduled time in an arrival trace): the latency counts
+ * from there, so time spent before the call (a submitter running late) is
+ * included.  arrival <= 0, or later than the call, means the call itself. */
+pmc_status pmc_server_submit_at(pmc_server* s, int field_id, double tol, void* d_out, double arrival,
+                                uint64_t* ticket);
+/* latency_s = completion - arrival in seconds (-1 while running); arrival is
+ * the submission, or the time given to pmc_server_submit_at */
 pmc_status pmc_server_poll(pmc_server* s, uint64_t ticket, int* done, pmc_status* st, double* latency_s);
 /* device address of a finished query's x~_k; source: 0 decoded from scratch,
  * 1 refined from a cached partial sum, 2 copied from the cache */

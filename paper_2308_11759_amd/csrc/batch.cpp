@@ -160,6 +160,7 @@ pmc_status pmc_batch_plan(pmc_ctx* ctx, int nf, const pmc_field* fields, const i
   if (!ctx) return PMC_E_ARG;
   if (!out || !fields || !n || !tau || nf < 1) return fail(ctx, PMC_E_ARG, "bad batch arguments");
   *out = nullptr;
+  if (ctx->codec != 0) return fail(ctx, PMC_E_ARG, "batches use the block-transform codec (PMC_OPT_CODEC 0)");
   pmc_batch* b = new pmc_batch();
   b->ctx = ctx;
   b->nf = nf;
@@ -380,7 +381,7 @@ pmc_status pmc_batch_compress(pmc_batch* b, const void* const* d_x, void* d_ws, 
   if (flags & (FLAG_INDEX | FLAG_OVERFLOW)) return fail(ctx, PMC_E_NOMEM, "a stream exceeds its capacity");
   for (int i = 0; i < b->nf; ++i)
     out[i] = store_from_meta(&b->f[i], b->g[i], b->n[i], b->tau[i].data(), b->minexp[i].data(),
-                             hm.data() + b->meta_first[i], streams + b->region_off[i]);
+                             hm.data() + b->meta_first[i], streams + b->region_off[i], 0);
   if (misses) return fail(ctx, PMC_E_BOUND, "%llu blocks missed their tolerance", misses);
   return PMC_OK;
 }

@@ -39,13 +39,20 @@ bool make_geo(const pmc_field* f, Geo* g) {
   if (!f || f->nx < 1 || f->ny < 1 || f->nz < 1) return false;
   if (f->dtype != PMC_F32 && f->dtype != PMC_F64) return false;
   if (f->nx > (1ull << 40) || f->ny > (1ull << 40) || f->nz > (1ull << 40)) return false;
+  // at most 2^36 values and 2^32 blocks (so every size below fits 64 bits and
+  // every grid fits the launch limits), checked without wrapping
+  uint64_t nxy = 0, n = 0, bxy = 0, nb = 0;
+  if (__builtin_mul_overflow(f->nx, f->ny, &nxy) || __builtin_mul_overflow(nxy, f->nz, &n) || n > (1ull << 36))
+    return false;
   g->nx = f->nx;
   g->ny = f->ny;
   g->nz = f->nz;
   g->nbx = (f->nx + 3) / 4;
   g->nby = (f->ny + 3) / 4;
   g->nbz = (f->nz + 3) / 4;
-  g->nblocks = g->nbx * g->nby * g->nbz;
+  if (__builtin_mul_overflow(g->nbx, g->nby, &bxy) || __builtin_mul_overflow(bxy, g->nbz, &nb) || nb > (1ull << 32))
+    return false;
+  g->nblocks = nb;
   g->nchunks = (g->nblocks + 15) / 16;
   g->rows_aligned = (f->nx % 4) == 0;
   g->pad = 0;
@@ -108,11 +115,12 @@ uint64_t stream_cap_one(const Geo& g, int dtype) {
 uint64_t aux_bytes(const Geo& g) { return align256(4 * g.nblocks); }
 
 pmc_store* store_from_meta(const pmc_field* f, const Geo& g, int n, const double* tau, const int* minexp,
-                           const CompMeta* hm, const uint8_t* d_base) {
+                           const CompMeta* hm, const uint8_t* d_base, int codec) {
   pmc_store* s = new pmc_store();
   s->f = *f;
   s->g = g;
   s->n = n;
+  s->codec = codec;
   s->d_base = d_base;
   const uint64_t auxb = aux_bytes(g);
   for (int i = 0; i < n; ++i) {
@@ -202,6 +210,10 @@ pmc_status pmc_ctx_set_option(pmc_ctx* ctx, int option, int value) {
   if (option == PMC_OPT_FUSED_DECODE) ctx->fused_decode = value ? 1 : 0;
   else if (option == PMC_OPT_SYNC_CHECK) ctx->sync_check = value ? 1 : 0;
   else if (option == PMC_OPT_PROFILE) ctx->profile = value ? 1 : 0;
+  else if (option == PMC_OPT_CODEC) {
+    if (value != 0 && value != 1) return fail(ctx, PMC_E_ARG, "codec must be 0 or 1");
+    ctx->codec = value;
+  }
   else return fail(ctx, PMC_E_ARG, "unknown option %d", option);
   return PMC_OK;
 }
@@ -342,9 +354,13 @@ pmc_status pmc_compress(pmc_ctx* ctx, const pmc_field* f, const void* d_x, int n
   if (!d_x || !tau || !out || !d_streams) return fail(ctx, PMC_E_ARG, "null argument");
   if (!aligned16(d_x)) return fail(ctx, PMC_E_ARG, "d_x must be 16-byte aligned");
   if (n < 1 || n > kMaxComps) return fail(ctx, PMC_E_ARG, "n must be in [1, %d]", kMaxComps);
+  const int codec = ctx->codec;
   for (int i = 0; i < n; ++i) {
     if (!(tau[i] > 0.0) || !std::isfinite(tau[i])) return fail(ctx, PMC_E_ARG, "tau[%d] must be > 0 and finite", i);
     if (i > 0 && !(tau[i] < tau[i - 1])) return fail(ctx, PMC_E_ARG, "tau must be strictly decreasing");
+    // the prediction codec keeps every bin 2 tau 2^-d normal and 1 / (2 tau) finite
+    if (codec == 1 && !(tau[i] >= std::ldexp(1.0, -960) && tau[i] <= std::ldexp(1.0, 1000)))
+      return fail(ctx, PMC_E_ARG, "tau[%d] outside [2^-960, 2^1000], the prediction codec's range", i);
   }
   WsLayout w = ws_layout(f, g, n);
   if (!d_ws || ws_bytes < w.total)
@@ -391,6 +407,7 @@ pmc_status pmc_compress(pmc_ctx* ctx, const pmc_field* f, const void* d_x, int n
     pa.streams = (uint8_t*)d_streams;
     pa.g = g;
     pa.tau = tau[i];
+    pa.codec = codec;
     if (f->dtype == PMC_F32) {
       EncArgs<float> a{};
       a.x = (const float*)d_x;
@@ -406,9 +423,11 @@ pmc_status pmc_compress(pmc_ctx* ctx, const pmc_field* f, const void* d_x, int n
       a.aux = (uint32_t*)((uint8_t*)d_streams + i * auxb);
       a.meta = meta + i;
       a.berr = (double*)(ws + w.berr);
+      a.h0 = 2.0 * tau[i];
+      a.inv0 = 1.0 / a.h0;
       {
-        ProfScope ps(ctx, "k_encode_f32");
-        e = launch_encode<float>(a, ctx->stream);
+        ProfScope ps(ctx, codec == 0 ? "k_encode_f32" : "k_encode_pq_f32");
+        e = launch_encode<float>(a, codec, ctx->stream);
       }
       if (e != hipSuccess) return hipfail(ctx, e, "encode");
       {
@@ -436,9 +455,11 @@ pmc_status pmc_compress(pmc_ctx* ctx, const pmc_field* f, const void* d_x, int n
       a.aux = (uint32_t*)((uint8_t*)d_streams + i * auxb);
       a.meta = meta + i;
       a.berr = (double*)(ws + w.berr);
+      a.h0 = 2.0 * tau[i];
+      a.inv0 = 1.0 / a.h0;
       {
-        ProfScope ps(ctx, "k_encode_f64");
-        e = launch_encode<double>(a, ctx->stream);
+        ProfScope ps(ctx, codec == 0 ? "k_encode_f64" : "k_encode_pq_f64");
+        e = launch_encode<double>(a, codec, ctx->stream);
       }
       if (e != hipSuccess) return hipfail(ctx, e, "encode");
       {
@@ -472,7 +493,7 @@ pmc_status pmc_compress(pmc_ctx* ctx, const pmc_field* f, const void* d_x, int n
     for (int i = 0; i < n; ++i) need = align256(need) + hm[i].stream_bytes;
     return fail(ctx, PMC_E_NOMEM, "stream capacity too small: need %llu bytes", need);
   }
-  pmc_store* s = store_from_meta(f, g, n, tau, minexp.data(), hm.data(), (const uint8_t*)d_streams);
+  pmc_store* s = store_from_meta(f, g, n, tau, minexp.data(), hm.data(), (const uint8_t*)d_streams, codec);
   *out = s;
   if (misses) return fail(ctx, PMC_E_BOUND, "%llu blocks missed their tolerance", misses);
   return PMC_OK;
@@ -489,6 +510,12 @@ pmc_status pmc_store_info(const pmc_store* s, int* n, double* tau, double* linf,
     if (nraw) nraw[i] = s->nraw[i];
     if (nesc) nesc[i] = s->nesc[i];
   }
+  return PMC_OK;
+}
+
+pmc_status pmc_store_codec(const pmc_store* s, int* codec) {
+  if (!s || !codec) return PMC_E_ARG;
+  *codec = s->codec;
   return PMC_OK;
 }
 
@@ -553,36 +580,22 @@ static pmc_status decode_range(pmc_ctx* ctx, const pmc_store* s, int k0, int k1,
     for (int i = i0; i < i1; ++i) span = std::max(span, s->max_span[i]);
     if (s->f.dtype == PMC_F32) {
       DecArgs<float> a{};
-      for (int i = i0; i < i1; ++i) {
-        a.s[i - i0] = s->d_base + s->offset[i];
-        a.aux[i - i0] = (const uint32_t*)(s->d_base + s->aux_offset[i]);
-        a.words[i - i0] = s->words[i];
-        a.minexp[i - i0] = s->minexp[i];
-        if (i > 0) a.relmask |= 1u << (i - i0);  // residual components
-      }
-      a.ncomp = i1 - i0;
+      fill_decode_args(s, i0, i1, a);
       a.in = (const float*)in;
       a.out = (float*)d_out;
       a.g = s->g;
       a.status = status;
-      ProfScope ps(ctx, "k_decode_f32");
-      e = launch_decode<float>(a, span, ctx->stream);
+      ProfScope ps(ctx, s->codec == 0 ? "k_decode_f32" : "k_decode_pq_f32");
+      e = launch_decode<float>(a, span, s->codec, ctx->stream);
     } else {
       DecArgs<double> a{};
-      for (int i = i0; i < i1; ++i) {
-        a.s[i - i0] = s->d_base + s->offset[i];
-        a.aux[i - i0] = (const uint32_t*)(s->d_base + s->aux_offset[i]);
-        a.words[i - i0] = s->words[i];
-        a.minexp[i - i0] = s->minexp[i];
-        if (i > 0) a.relmask |= 1u << (i - i0);  // residual components
-      }
-      a.ncomp = i1 - i0;
+      fill_decode_args(s, i0, i1, a);
       a.in = (const double*)in;
       a.out = (double*)d_out;
       a.g = s->g;
       a.status = status;
-      ProfScope ps(ctx, "k_decode_f64");
-      e = launch_decode<double>(a, span, ctx->stream);
+      ProfScope ps(ctx, s->codec == 0 ? "k_decode_f64" : "k_decode_pq_f64");
+      e = launch_decode<double>(a, span, s->codec, ctx->stream);
     }
     if (e != hipSuccess) return hipfail(ctx, e, "decode");
     in = d_out;
@@ -626,34 +639,20 @@ pmc_status pmc_retrieve_box(pmc_ctx* ctx, const pmc_store* s, int k, const uint6
     for (int i = i0; i < i1; ++i) span = std::max(span, s->max_span[i]);
     if (s->f.dtype == PMC_F32) {
       DecArgs<float> a{};
-      for (int i = i0; i < i1; ++i) {
-        a.s[i - i0] = s->d_base + s->offset[i];
-        a.aux[i - i0] = (const uint32_t*)(s->d_base + s->aux_offset[i]);
-        a.words[i - i0] = s->words[i];
-        a.minexp[i - i0] = s->minexp[i];
-        if (i > 0) a.relmask |= 1u << (i - i0);
-      }
-      a.ncomp = i1 - i0;
+      fill_decode_args(s, i0, i1, a);
       a.in = (const float*)in;
       a.out = (float*)d_out;
       a.g = s->g;
       a.status = status;
-      e = launch_decode_box<float>(a, b, span, ctx->stream);
+      e = launch_decode_box<float>(a, b, span, s->codec, ctx->stream);
     } else {
       DecArgs<double> a{};
-      for (int i = i0; i < i1; ++i) {
-        a.s[i - i0] = s->d_base + s->offset[i];
-        a.aux[i - i0] = (const uint32_t*)(s->d_base + s->aux_offset[i]);
-        a.words[i - i0] = s->words[i];
-        a.minexp[i - i0] = s->minexp[i];
-        if (i > 0) a.relmask |= 1u << (i - i0);
-      }
-      a.ncomp = i1 - i0;
+      fill_decode_args(s, i0, i1, a);
       a.in = (const double*)in;
       a.out = (double*)d_out;
       a.g = s->g;
       a.status = status;
-      e = launch_decode_box<double>(a, b, span, ctx->stream);
+      e = launch_decode_box<double>(a, b, span, s->codec, ctx->stream);
     }
     if (e != hipSuccess) return hipfail(ctx, e, "decode");
     in = d_out;
@@ -687,7 +686,7 @@ pmc_status pmc_refine(pmc_ctx* ctx, const pmc_store* s, int k_from, int k_to, vo
 }
 
 // ---- persistence -----------------------------------------------------------
-// blob: u32 "PMCS", u32 version, u32 n, u32 0 | u64 nx ny nz, i32 dtype, i32 0 |
+// blob: u32 "PMCS", u32 version, u32 n, u32 codec | u64 nx ny nz, i32 dtype, i32 0 |
 //       n x {f64 tau, f64 linf, u64 bytes, nempty, ncoded, nraw, nesc, nmiss} |
 //       (256-aligned) streams, each on a 256-byte boundary of the region
 static const uint32_t kBlobMagic = 0x53434D50u;
@@ -705,7 +704,7 @@ pmc_status pmc_store_serialize(pmc_ctx* ctx, const pmc_store* s, void* host_buf,
   if (cap < total) return fail(ctx, PMC_E_NOMEM, "need %llu bytes", (unsigned long long)total);
   uint8_t* b = (uint8_t*)host_buf;
   std::memset(b, 0, total);
-  uint32_t h32[4] = {kBlobMagic, 1u, (uint32_t)s->n, 0u};
+  uint32_t h32[4] = {kBlobMagic, 1u, (uint32_t)s->n, (uint32_t)s->codec};
   std::memcpy(b, h32, 16);
   uint64_t dims[3] = {s->f.nx, s->f.ny, s->f.nz};
   std::memcpy(b + 16, dims, 24);
@@ -738,6 +737,7 @@ pmc_status pmc_store_serialize(pmc_ctx* ctx, const pmc_store* s, void* host_buf,
 
 struct BlobView {
   int n;
+  int codec;
   pmc_field f;
   std::vector<uint64_t> rec;  // 8 words per component
   uint64_t region_off, region_bytes;
@@ -751,6 +751,8 @@ static bool parse_blob(const void* host_buf, size_t size, BlobView* v) {
   if (h32[0] != kBlobMagic || h32[1] != 1u) return false;
   int n = (int)h32[2];
   if (n < 1 || n > kMaxComps) return false;
+  if (h32[3] > 1u) return false;
+  v->codec = (int)h32[3];
   if (size < blob_header_bytes(n)) return false;
   v->n = n;
   uint64_t dims[3];
@@ -764,22 +766,30 @@ static bool parse_blob(const void* host_buf, size_t size, BlobView* v) {
   v->f.reserved = 0;
   v->rec.resize(8ull * n);
   std::memcpy(v->rec.data(), b + 48, 64ull * n);
-  uint64_t region = 0;
-  for (int i = 0; i < n; ++i) region = align256(region) + v->rec[8 * i + 2];
+  // the streams follow the header, each on a 256-byte boundary; every running
+  // sum is checked against the blob size before it is formed, so no sum wraps
   v->region_off = blob_header_bytes(n);
+  const uint64_t avail = size - v->region_off;
+  uint64_t region = 0;
+  for (int i = 0; i < n; ++i) {
+    const uint64_t bytes = v->rec[8 * i + 2];
+    region = align256(region);
+    if (region > avail || bytes > avail - region) return false;
+    region += bytes;
+  }
   v->region_bytes = region;
-  if (v->region_off + region > size) return false;
   return true;
 }
 
 // host-side validation of one stream (header fields and chunk index)
-static bool check_stream(const uint8_t* p, uint64_t bytes, const pmc_field* f, const Geo& g, double tau,
+static bool check_stream(const uint8_t* p, uint64_t bytes, const pmc_field* f, const Geo& g, double tau, int codec,
                          uint64_t* words, uint64_t* max_span) {
   if (bytes < 64) return false;
   uint32_t h[16];
   std::memcpy(h, p, 64);
   if (h[0] != kStreamMagic) return false;
-  if ((h[1] & 0xFFFF) != kStreamVersion || ((h[1] >> 16) & 0xFF) != (uint32_t)f->dtype || (h[1] >> 24) != 3u)
+  if ((h[1] & 0xFF) != kStreamVersion || ((h[1] >> 8) & 0xFF) != (uint32_t)codec ||
+      ((h[1] >> 16) & 0xFF) != (uint32_t)f->dtype || (h[1] >> 24) != 3u)
     return false;
   uint64_t nx = h[2] | ((uint64_t)h[3] << 32), ny = h[4] | ((uint64_t)h[5] << 32), nz = h[6] | ((uint64_t)h[7] << 32);
   if (nx != f->nx || ny != f->ny || nz != f->nz) return false;
@@ -789,7 +799,10 @@ static bool check_stream(const uint8_t* p, uint64_t bytes, const pmc_field* f, c
   if (!(t == tau) || (int32_t)h[10] != floor_log2(tau) || h[11] != 16u) return false;
   uint64_t nch = h[12] | ((uint64_t)h[13] << 32), w = h[14] | ((uint64_t)h[15] << 32);
   if (nch != g.nchunks) return false;
-  if (bytes != 64 + 4 * nch + 4 * w) return false;
+  // bytes = 64 + 4 nch + 4 w, compared without forming a sum that could wrap
+  if (bytes < 64 || nch > (bytes - 64) / 4) return false;
+  const uint64_t rest = bytes - 64 - 4 * nch;
+  if (rest % 4 != 0 || w != rest / 4 || w > 0xFFFFFFFFull) return false;
   const uint32_t* idx = (const uint32_t*)(p + 64);
   uint64_t prev = 0;
   for (uint64_t c = 0; c < nch; ++c) {
@@ -807,11 +820,41 @@ static bool check_stream(const uint8_t* p, uint64_t bytes, const pmc_field* f, c
   return true;
 }
 
+// every stream of a parsed blob: strictly decreasing positive tolerances and
+// a valid header and chunk index; words / spans per component on success
+static bool check_blob_streams(const BlobView& v, const Geo& g, const uint8_t* region, std::vector<uint64_t>* words,
+                               std::vector<uint64_t>* spans) {
+  uint64_t off = 0;
+  double prev = 0.0;
+  for (int i = 0; i < v.n; ++i) {
+    const uint64_t* r = &v.rec[8 * i];
+    double tau;
+    std::memcpy(&tau, &r[0], 8);
+    off = align256(off);
+    uint64_t w = 0, span = 0;
+    if (!(tau > 0.0) || !std::isfinite(tau) || (i > 0 && !(tau < prev)) ||
+        !check_stream(region + off, r[2], &v.f, g, tau, v.codec, &w, &span))
+      return false;
+    if (words) words->push_back(w);
+    if (spans) spans->push_back(span);
+    prev = tau;
+    off += r[2];
+  }
+  return true;
+}
+
+// device bytes of a store rebuilt from a blob: the block indexes, the
+// streams, and one 256-byte status word at the end
+static uint64_t device_bytes(const BlobView& v, const Geo& g) {
+  return v.n * aux_bytes(g) + align256(v.region_bytes) + 256;
+}
+
 pmc_status pmc_store_device_bytes(const void* host_buf, size_t size, size_t* need) {
   BlobView v;
   Geo g;
   if (!need || !parse_blob(host_buf, size, &v) || !make_geo(&v.f, &g)) return PMC_E_CORRUPT;
-  *need = v.n * aux_bytes(g) + align256(v.region_bytes);
+  if (!check_blob_streams(v, g, (const uint8_t*)host_buf + v.region_off, nullptr, nullptr)) return PMC_E_CORRUPT;
+  *need = device_bytes(v, g);
   return PMC_OK;
 }
 
@@ -825,13 +868,16 @@ pmc_status pmc_store_deserialize(pmc_ctx* ctx, const void* host_buf, size_t size
   Geo g;
   if (!make_geo(&v.f, &g)) return fail(ctx, PMC_E_CORRUPT, "bad field in blob");
   const uint64_t auxb = aux_bytes(g);
-  const uint64_t need = v.n * auxb + align256(v.region_bytes);
+  const uint64_t need = device_bytes(v, g);
   if (cap < need) return fail(ctx, PMC_E_NOMEM, "need %llu bytes", (unsigned long long)need);
   const uint8_t* region = (const uint8_t*)host_buf + v.region_off;
+  std::vector<uint64_t> words, spans;
+  if (!check_blob_streams(v, g, region, &words, &spans)) return fail(ctx, PMC_E_CORRUPT, "malformed stream");
   pmc_store* s = new pmc_store();
   s->f = v.f;
   s->g = g;
   s->n = v.n;
+  s->codec = v.codec;
   s->d_base = (const uint8_t*)d_streams;
   uint64_t off = 0;
   for (int i = 0; i < v.n; ++i) {
@@ -840,33 +886,30 @@ pmc_status pmc_store_deserialize(pmc_ctx* ctx, const void* host_buf, size_t size
     std::memcpy(&tau, &r[0], 8);
     std::memcpy(&linf, &r[1], 8);
     off = align256(off);
-    uint64_t words = 0, span = 0;
-    if (!(tau > 0.0) || !std::isfinite(tau) || (i > 0 && !(tau < s->tau[i - 1])) ||
-        !check_stream(region + off, r[2], &v.f, g, tau, &words, &span)) {
-      delete s;
-      return fail(ctx, PMC_E_CORRUPT, "component %d: malformed stream", i);
-    }
     s->tau.push_back(tau);
     s->linf.push_back(linf);
     s->minexp.push_back(floor_log2(tau));
     s->bytes.push_back(r[2]);
     s->offset.push_back(v.n * auxb + off);
     s->aux_offset.push_back(i * auxb);
-    s->words.push_back(words);
+    s->words.push_back(words[i]);
     s->nempty.push_back(r[3]);
     s->ncoded.push_back(r[4]);
     s->nraw.push_back(r[5]);
     s->nesc.push_back(r[6]);
     s->nmiss.push_back(r[7]);
-    s->max_span.push_back(span);
+    s->max_span.push_back(spans[i]);
     off += r[2];
   }
   hipError_t e = hipSetDevice(ctx->device);
   uint8_t* base = (uint8_t*)d_streams;
+  // one status word after the streams: set by the index rebuild when a
+  // chunk's payload does not parse
+  unsigned int* status = (unsigned int*)(base + need - 256);
+  if (e == hipSuccess) e = launch_fill64((unsigned long long*)status, 1, 0ull, ctx->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(base + v.n * auxb, region, v.region_bytes, hipMemcpyHostToDevice, ctx->stream);
-  // rebuild the per-block index of every stream; a malformed payload leaves
-  // offsets the decoder rejects (it bounds every offset by its chunk)
+  // rebuild the per-block index of every stream
   for (int i = 0; i < v.n && e == hipSuccess; ++i) {
     AuxArgs a{};
     a.s = base + s->offset[i];
@@ -874,13 +917,20 @@ pmc_status pmc_store_deserialize(pmc_ctx* ctx, const void* host_buf, size_t size
     a.words = s->words[i];
     a.minexp = s->minexp[i];
     a.g = g;
-    a.status = nullptr;
-    e = s->f.dtype == PMC_F32 ? launch_aux<float>(a, ctx->stream) : launch_aux<double>(a, ctx->stream);
+    a.status = status;
+    e = s->f.dtype == PMC_F32 ? launch_aux<float>(a, s->codec, ctx->stream)
+                              : launch_aux<double>(a, s->codec, ctx->stream);
   }
+  unsigned int h = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&h, status, 4, hipMemcpyDeviceToHost, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) {
     delete s;
     return hipfail(ctx, e, "stream upload");
+  }
+  if (h) {
+    delete s;
+    return fail(ctx, PMC_E_CORRUPT, "a chunk's payload does not parse");
   }
   *out = s;
   return PMC_OK;

@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace pmc {
 
 constexpr int kVals = 64;         // values per block
@@ -62,6 +64,19 @@ constexpr Order make_order() {
   return o;
 }
 constexpr Order kOrder = make_order();
+
+// a copy the compiler cannot prove equal to the original: recomputing the
+// residual from such copies stops common-subexpression elimination from
+// keeping a 64-value array alive across the whole kernel, and a value used
+// inside a loop through such a copy is not hoisted out of it
+template <class T> __device__ __forceinline__ T opaque(T v) {
+  __asm__ volatile("" : "+v"(v));
+  return v;
+}
+template <class T> __device__ __forceinline__ T* opaque(T* p) {
+  __asm__ volatile("" : "+v"(p));
+  return p;
+}
 
 // ---------------------------------------------------------------------------
 // wrapping integer helpers (two's complement P-bit words)
@@ -810,6 +825,192 @@ template <class T, class R> __device__ __forceinline__ bool block_skip(R& r, int
   if (emax < 2 - FT<T>::BIAS || p < 1 || p > P) return false;
   uint32_t n = 0;
   for (int t = 0; t < p; ++t) (void)plane_read(r, n, sq);
+  return true;
+}
+
+// ===========================================================================
+// Codec 1: prediction and uniform quantisation on the same 4x4x4 blocks (a
+// second error-bounded compressor behind the multi-component driver, Sec.
+// 6.2; prediction-based compressors, Sec. 5).  Per block and escalation step
+// d: bin h_d = 2 tau 2^-d, q = rint(e / h_d) (as e * (1 / h_d) in double),
+// the block-local Lorenzo prediction error of q (mixed first differences
+// along x, y, z in wrapping P-bit integers) when it is narrower than q, and
+// the zigzag values at one width w per block.  Block header: nonempty, coded
+// / raw, d in unary, a "predicted" bit, w in 6 bits; then 64 x w bits.
+constexpr int kPqMaxDelta = 63;
+
+template <class S> __device__ __forceinline__ typename std::make_unsigned<S>::type zigzag(S r) {
+  typedef typename std::make_unsigned<S>::type W;
+  return ((W)r << 1) ^ (W)(r >> (8 * sizeof(S) - 1));
+}
+template <class S> __device__ __forceinline__ S unzigzag(typename std::make_unsigned<S>::type z) {
+  typedef typename std::make_unsigned<S>::type W;
+  return (S)((z >> 1) ^ ((W)0 - (z & 1u)));
+}
+
+// Lorenzo prediction errors in place: each sample minus its predecessor along
+// x, then along y, then along z (wrapping); the mixed difference of q
+template <class S> __device__ __forceinline__ void lorenzo_fwd(S q[64]) {
+#pragma unroll
+  for (int l = 63; l >= 0; --l)
+    if (l & 3) q[l] = wsub(q[l], q[l - 1]);
+#pragma unroll
+  for (int l = 63; l >= 0; --l)
+    if ((l >> 2) & 3) q[l] = wsub(q[l], q[l - 4]);
+#pragma unroll
+  for (int l = 63; l >= 0; --l)
+    if (l >> 4) q[l] = wsub(q[l], q[l - 16]);
+}
+// its inverse: running sums along z, y and x (wrapping)
+template <class S> __device__ __forceinline__ void lorenzo_inv(S q[64]) {
+#pragma unroll
+  for (int l = 16; l < 64; ++l) q[l] = wadd(q[l], q[l - 16]);
+#pragma unroll
+  for (int l = 0; l < 64; ++l)
+    if ((l >> 2) & 3) q[l] = wadd(q[l], q[l - 4]);
+#pragma unroll
+  for (int l = 0; l < 64; ++l)
+    if (l & 3) q[l] = wadd(q[l], q[l - 1]);
+}
+
+template <class U> __device__ __forceinline__ uint32_t bit_length(U v) {
+  if constexpr (sizeof(U) == 4) return v ? 32u - (uint32_t)__builtin_clz(v) : 0u;
+  else return v ? 64u - (uint32_t)__builtin_clzll(v) : 0u;
+}
+
+// q of a residual block at escalation d: false when some |e * inv_d| is not
+// below 2^(P-2) (too wide to code; also NaN)
+template <class T>
+__device__ __forceinline__ bool pq_quantize(const T e[64], double inv0, int delta, typename FT<T>::S q[64]) {
+  typedef typename FT<T>::S S;
+  const double inv = __builtin_ldexp(inv0, delta);
+  const double lim = (double)((typename FT<T>::U)1 << (FT<T>::P - 2));
+  bool ok = true;
+#pragma unroll
+  for (int l = 0; l < 64; ++l) {
+    const double t = (double)opaque(e[l]) * inv;  // converted here, each candidate (not held as doubles)
+    ok = ok && __builtin_fabs(t) < lim;
+    q[l] = ok ? (S)__builtin_rint(t) : (S)0;
+  }
+  return ok;
+}
+
+// width and choice of a quantised block: the zigzag width of q itself and
+// of its Lorenzo prediction errors; the predicted form only when narrower.
+// Each prediction error is formed from its (up to) eight corner samples, the
+// same mixed difference the separable passes give, so q stays as it is and
+// no second array is held.
+template <class S> __device__ __forceinline__ uint32_t pq_width(const S q[64], bool& pred) {
+  typedef typename std::make_unsigned<S>::type W;
+  W mq = 0, mp = 0;
+#pragma unroll
+  for (int l = 0; l < 64; ++l) {
+    const int x = l & 3, y = (l >> 2) & 3, z = l >> 4;
+    W r = (W)q[l];
+    if (x) r -= (W)q[l - 1];
+    if (y) r -= (W)q[l - 4];
+    if (z) r -= (W)q[l - 16];
+    if (x && y) r += (W)q[l - 5];
+    if (x && z) r += (W)q[l - 17];
+    if (y && z) r += (W)q[l - 20];
+    if (x && y && z) r -= (W)q[l - 21];
+    const W zq = zigzag(q[l]), zp = zigzag((S)r);
+    mq = zq > mq ? zq : mq;
+    mp = zp > mp ? zp : mp;
+  }
+  const uint32_t wq = bit_length(mq), wp = bit_length(mp);
+  pred = wp < wq;
+  return pred ? wp : wq;
+}
+
+template <class T> __device__ __forceinline__ uint32_t pq_bits(int delta, uint32_t w) {
+  return 2u + (uint32_t)(delta + 1) + 1u + 6u + 64u * w;
+}
+
+// emit a coded block of codec 1 (its header bits included)
+template <class T>
+__device__ __forceinline__ void pq_emit(LdsBits& w, typename FT<T>::S q[64], int delta, bool pred, uint32_t width) {
+  typedef typename FT<T>::U U;
+  w.put(1, 2);  // nonempty, coded
+  for (int t = 0; t < delta; ++t) w.put(1, 1);
+  w.put(0, 1);
+  w.put(pred ? 1u : 0u, 1);
+  w.put(width, 6);
+  if (pred) lorenzo_fwd(q);
+#pragma unroll
+  for (int l = 0; l < 64; ++l) {
+    const U z = zigzag(q[l]);
+    if constexpr (sizeof(U) == 4) w.put(z, width);
+    else w.put64(z, width);
+  }
+}
+
+// Alg. 2 for one block of codec 1: acc += x_i (left to right)
+template <class T, class R>
+__device__ __forceinline__ bool pq_decode_add(R& r, double h0, T acc[64]) {
+  typedef typename FT<T>::U U;
+  typedef typename FT<T>::S S;
+  constexpr int P = FT<T>::P;
+  const uint32_t h = r.peek32();
+  if (!(h & 1u)) {  // empty
+    r.skip(1);
+    return true;
+  }
+  if (h & 2u) {  // raw block
+    r.skip(2);
+#pragma unroll
+    for (int l = 0; l < 64; ++l) acc[l] = acc[l] + from_raw((U)r.get64((uint32_t)P), (T)0);
+    return true;
+  }
+  int delta = (int)__builtin_ctz(~(h >> 2) | 0x40000000u);
+  uint32_t pred, width;
+  if (3 + delta + 7 <= 32) {
+    pred = (h >> (3 + delta)) & 1u;
+    width = (h >> (4 + delta)) & 63u;
+    r.skip((uint32_t)(3 + delta + 7));
+  } else {
+    r.skip(2);
+    delta = 0;
+#pragma unroll 1
+    while (r.get(1)) {
+      if (++delta > kPqMaxDelta) return false;
+    }
+    pred = r.get(1);
+    width = r.get(6);
+  }
+  if (width > (uint32_t)P) return false;  // a P-bit zigzag value needs at most P bits
+  S q[64];
+#pragma unroll
+  for (int l = 0; l < 64; ++l) {
+    U z;
+    if constexpr (sizeof(U) == 4) z = width ? r.get(width) : 0u;
+    else z = width ? (U)r.get64nz(width) : (U)0;
+    q[l] = unzigzag<S>(z);
+  }
+  if (pred) lorenzo_inv(q);
+  const double hd = __builtin_ldexp(h0, -delta);
+#pragma unroll
+  for (int l = 0; l < 64; ++l) acc[l] = acc[l] + (T)((double)q[l] * hd);
+  return true;
+}
+
+// advance over one block of codec 1 without reconstructing it
+template <class T, class R> __device__ __forceinline__ bool pq_block_skip(R& r) {
+  constexpr int P = FT<T>::P;
+  if (!r.get(1)) return true;
+  if (r.get(1)) {
+    for (int l = 0; l < 64; ++l) r.get64((uint32_t)P);
+    return true;
+  }
+  int delta = 0;
+#pragma unroll 1
+  while (r.get(1)) {
+    if (++delta > kPqMaxDelta) return false;
+  }
+  r.get(1);
+  const uint32_t width = r.get(6);
+  if (width > (uint32_t)P) return false;  // a P-bit zigzag value needs at most P bits
+  for (int l = 0; l < 64; ++l) r.get64(width);
   return true;
 }
 

@@ -25,6 +25,7 @@ struct pmc_ctx {
   int fused_decode = 1;
   int sync_check = 0;
   int profile = 0;
+  int codec = 0;  // the codec pmc_compress uses: 0 block transform, 1 prediction
   std::vector<std::string> prof_names;
   std::vector<uint64_t> prof_launches;
   std::vector<double> prof_ms;
@@ -36,6 +37,7 @@ struct pmc_store {
   pmc_field f{};
   pmc::Geo g{};
   int n = 0;
+  int codec = 0;  // 0 block transform, 1 prediction (every component of a store)
   std::vector<double> tau, linf;
   std::vector<int> minexp;
   std::vector<uint64_t> bytes, offset, aux_offset, words, nempty, ncoded, nraw, nesc, nmiss;
@@ -55,7 +57,19 @@ uint64_t stream_cap_one(const pmc::Geo& g, int dtype);
 uint64_t aux_bytes(const pmc::Geo& g);
 // a store from per-component device results (offsets relative to d_base)
 pmc_store* store_from_meta(const pmc_field* f, const pmc::Geo& g, int n, const double* tau, const int* minexp,
-                           const pmc::CompMeta* hm, const uint8_t* d_base);
+                           const pmc::CompMeta* hm, const uint8_t* d_base, int codec);
+// the decode arguments of components [i0, i1) of a store
+template <class A> void fill_decode_args(const pmc_store* s, int i0, int i1, A& a) {
+  for (int i = i0; i < i1; ++i) {
+    a.s[i - i0] = s->d_base + s->offset[i];
+    a.aux[i - i0] = (const uint32_t*)(s->d_base + s->aux_offset[i]);
+    a.words[i - i0] = s->words[i];
+    a.minexp[i - i0] = s->minexp[i];
+    a.step[i - i0] = 2.0 * s->tau[i];
+    if (i > 0) a.relmask |= 1u << (i - i0);  // residual components
+  }
+  a.ncomp = i1 - i0;
+}
 
 inline hipEvent_t prof_event(pmc_ctx* c) {
   if (!c->prof_pool.empty()) {

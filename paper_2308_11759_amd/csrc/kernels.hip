@@ -245,17 +245,6 @@ __device__ __forceinline__ void load_rows(const T* f, const Geo& g, const BlockP
   }
 }
 
-// a copy the compiler cannot prove equal to the original: recomputing the
-// residual from such copies stops common-subexpression elimination from
-// keeping a 64-value array alive across the whole kernel
-template <class T> __device__ __forceinline__ T opaque(T v) {
-  __asm__ volatile("" : "+v"(v));
-  return v;
-}
-template <class T> __device__ __forceinline__ T* opaque(T* p) {
-  __asm__ volatile("" : "+v"(p));
-  return p;
-}
 
 __device__ __forceinline__ BlockPos opaque_pos(BlockPos b) {
   b.x0 = opaque(b.x0);
@@ -342,9 +331,45 @@ __device__ __forceinline__ void load_block_lds(const T* __restrict__ f, const Ge
 // the caller guarantees that every block is full and rows are aligned (all
 // three dimensions multiples of 4), so the per-lane edge paths compile away
 // and their conditions hold no registers.
-template <class T, bool kFull = false>
+// the candidate check of a codec-1 block: x~_i = x~_{i-1} + x_i row by row
+// in the field precision, each integer q = rint(e * inv_d) formed again and
+// turned into q * h_d as its row comes (so no array of integers or decoded
+// values is held across the check), the rows stored as they come (a
+// rejected candidate is overwritten later), and the largest |x - x~_i| in
+// double over the block's valid samples
+template <class T, bool kFull>
+__device__ __forceinline__ double check_rows_pq(const EncArgs<T>& a, const XLds<T>& XL, const T* tin,
+                                                const BlockPos& bq, bool wfull, uint64_t vmask,
+                                                const T e[64], double inv, double h) {
+  double ea = 0.0;
+  constexpr int RB = kFull ? 8 : 4;
+#pragma unroll
+  for (int r0 = 0; r0 < 16; r0 += RB) {
+    T tr[4 * RB];
+    load_rows<T, RB>(tin, a.g, bq, r0, wfull, tr);
+#pragma unroll
+    for (int k = 0; k < RB; ++k) {
+      const int r = r0 + k;
+      T row[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int l = 4 * r + t;
+        const typename FT<T>::S q = (typename FT<T>::S)__builtin_rint((double)opaque(e[l]) * inv);
+        row[t] = tr[4 * k + t] + (T)((double)q * h);  // x~_{i-1} + x_i in the field precision
+        ea = nmax(ea, masked_abs(vmask, l, (double)XL.at(l) - (double)row[t]));
+      }
+      if (!a.last) store_row(a.xt_out, a.g, bq, r, row, wfull);
+    }
+  }
+  return ea;
+}
+
+// kCodec: 0 the block-transform codec, 1 prediction and quantisation (its
+// residual block stays in registers for the candidates and the emission)
+template <class T, bool kFull = false, int kCodec = 0>
 __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T* s_x, const uint16_t* unsq) {
   typedef typename FT<T>::U U;
+  typedef typename FT<T>::S S;
   constexpr int P = FT<T>::P;
   constexpr int CAP = chunk_cap_words<T>();
   // LDS: the block's x values while deciding; once x is dead the same bytes
@@ -397,7 +422,9 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
     }
     if (a.first) xmax = maxabs;  // x - (+0) has the magnitude of x
     emax = block_emax<T>(maxabs);
-    if (active && maxabs != 0) forward_coeffs<T>(e, emax, u);
+    if constexpr (kCodec == 0) {
+      if (active && maxabs != 0) forward_coeffs<T>(e, emax, u);
+    }
   }
   // the error before this component, max |x - x~_{i-1}| in double over the
   // block's samples: the previous component left it per block; for the first
@@ -430,47 +457,67 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
       const BlockPos bq = kFull ? opaque_pos(bp) : opaque_ext(bp);  // row addresses are recomputed, not held
       bool feasible = false;
       uint32_t cb = 0;
-      if (p >= 1 && p <= P) {
-        cb = 2u + (uint32_t)(delta + 1) + (uint32_t)FT<T>::EBITS + planes_cost_reg<T>(u, p);
-        feasible = cb <= (uint32_t)FT<T>::RAW_BITS;
-      }
-      if (feasible) {
-        const U m = plane_mask<U>(P, p);
-        // decode, add and check one row at a time; x~_i rows are stored as
-        // they come (a rejected candidate is overwritten below)
-        typename FT<T>::S c[64], q[64];
+      if constexpr (kCodec == 0) {
+        if (p >= 1 && p <= P) {
+          cb = 2u + (uint32_t)(delta + 1) + (uint32_t)FT<T>::EBITS + planes_cost_reg<T>(u, p);
+          feasible = cb <= (uint32_t)FT<T>::RAW_BITS;
+        }
+        if (feasible) {
+          const U m = plane_mask<U>(P, p);
+          // decode, add and check one row at a time; x~_i rows are stored as
+          // they come (a rejected candidate is overwritten below)
+          S c[64], q[64];
 #pragma unroll
-        for (int r = 0; r < 64; ++r) c[r] = from_nb<T>(u[r] & m);  // the top p planes
-        inverse_zy_ints<T>(c, q);
-        inverse_x<T>(q);
-        T dv[64];
-        const T scale = dequantize_block(q, emax, dv);
-        double ea = 0.0;
-        // rows of x~_{i-1} in flight together: eight in the full-field
-        // kernel (registers to spare), four where the edge paths need them
-        constexpr int RB = kFull ? 8 : 4;
+          for (int r = 0; r < 64; ++r) c[r] = from_nb<T>(u[r] & m);  // the top p planes
+          inverse_zy_ints<T>(c, q);
+          inverse_x<T>(q);
+          T dv[64];
+          const T scale = dequantize_block(q, emax, dv);
+          double ea = 0.0;
+          // rows of x~_{i-1} in flight together: eight in the full-field
+          // kernel (registers to spare), four where the edge paths need them
+          constexpr int RB = kFull ? 8 : 4;
 #pragma unroll
-        for (int r0 = 0; r0 < 16; r0 += RB) {
-          T tr[4 * RB];
-          load_rows<T, RB>(tin, a.g, bq, r0, wfull, tr);
+          for (int r0 = 0; r0 < 16; r0 += RB) {
+            T tr[4 * RB];
+            load_rows<T, RB>(tin, a.g, bq, r0, wfull, tr);
 #pragma unroll
-          for (int k = 0; k < RB; ++k) {
-            const int r = r0 + k;
-            T row[4];
+            for (int k = 0; k < RB; ++k) {
+              const int r = r0 + k;
+              T row[4];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-              const int l = 4 * r + t;
-              row[t] = fma_exact(dv[l], scale, tr[4 * k + t]);  // x~_{i-1} + x_i in the field precision
-              ea = nmax(ea, masked_abs(vmask, l, (double)XL.at(l) - (double)row[t]));
+              for (int t = 0; t < 4; ++t) {
+                const int l = 4 * r + t;
+                row[t] = fma_exact(dv[l], scale, tr[4 * k + t]);  // x~_{i-1} + x_i in the field precision
+                ea = nmax(ea, masked_abs(vmask, l, (double)XL.at(l) - (double)row[t]));
+              }
+              if (!a.last) store_row(a.xt_out, a.g, bq, r, row, wfull);
             }
-            if (!a.last) store_row(a.xt_out, a.g, bq, r, row, wfull);
+          }
+          if (ea <= a.tau && ea <= eb) {
+            mode = MODE_CODED;
+            nbits = cb;
+            err = ea;
+            break;
           }
         }
-        if (ea <= a.tau && ea <= eb) {
-          mode = MODE_CODED;
-          nbits = cb;
-          err = ea;
-          break;
+      } else {
+        // bin 2 tau 2^-delta; the block's integers, its code width, its size
+        S q[64];
+        if (delta <= kPqMaxDelta && pq_quantize<T>(e, a.inv0, delta, q)) {
+          bool pred;
+          cb = pq_bits<T>(delta, pq_width(q, pred));
+          feasible = cb <= (uint32_t)FT<T>::RAW_BITS;
+        }
+        if (feasible) {
+          const double ea = check_rows_pq<T, kFull>(a, XL, tin, bq, wfull, vmask, e, __builtin_ldexp(a.inv0, delta),
+                                                    __builtin_ldexp(a.h0, -delta));
+          if (ea <= a.tau && ea <= eb) {
+            mode = MODE_CODED;
+            nbits = cb;
+            err = ea;
+            break;
+          }
         }
       }
       if (eb <= a.tau) {
@@ -589,12 +636,19 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
 #pragma unroll
           for (int t = 0; t < 4; ++t) w.put64((uint64_t)raw_bits_lo((T)(xr[t] - tr[t])), (uint32_t)P);
         }
-      } else {
+      } else if constexpr (kCodec == 0) {
         w.put(1, 2);  // nonempty, coded
         for (int t = 0; t < delta; ++t) w.put(1, 1);
         w.put(0, 1);
         w.put((uint64_t)(emax + FT<T>::BIAS), (uint32_t)FT<T>::EBITS);
         planes_emit<T>(w, u, p, pw, unsq);
+      } else {
+        // the accepted candidate's integers again (the same arithmetic)
+        S q[64];
+        (void)pq_quantize<T>(e, a.inv0, delta, q);
+        bool pred;
+        const uint32_t width = pq_width(q, pred);
+        pq_emit<T>(w, q, delta, pred, width);
       }
       w.flush();
     }
@@ -617,12 +671,12 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
   }
 }
 
-template <class T, bool kFull>
+template <class T, bool kFull, int kCodec>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1))) void k_encode(EncArgs<T> a) {
   __shared__ T s_x[64 * 64];
   __shared__ uint16_t s_unsq[256];
   unsqueeze_table(s_unsq);
-  encode_wave<T, kFull>(a, blockIdx.x, s_x, s_unsq);
+  encode_wave<T, kFull, kCodec>(a, blockIdx.x, s_x, s_unsq);
 }
 
 // ---------------------------------------------------------------------------
@@ -760,7 +814,7 @@ __global__ __launch_bounds__(64) void k_pack(PackArgs a) {
     uint32_t v = 0;
     switch (lane) {
       case 0: v = kMagic; break;
-      case 1: v = (uint32_t)kVersion | ((uint32_t)FT<T>::CODE << 16) | (3u << 24); break;
+      case 1: v = (uint32_t)kVersion | ((uint32_t)a.codec << 8) | ((uint32_t)FT<T>::CODE << 16) | (3u << 24); break;
       case 2: v = (uint32_t)a.g.nx; break;
       case 3: v = (uint32_t)(a.g.nx >> 32); break;
       case 4: v = (uint32_t)a.g.ny; break;
@@ -873,11 +927,19 @@ __device__ __forceinline__ void stage_span(const uint32_t* payload, const Span& 
 // runs the component loop (the staging copies are shared); false on a
 // malformed stream.  kFull: every block of the field is full and rows are
 // aligned (all dimensions multiples of 4): no per-lane edge paths.
-template <class T, bool kStaged, bool kBox = false, bool kFull = false>
+// one block of one component, codec 0 (minexp) or codec 1 (step = 2 tau)
+template <class T, int kCodec, class R>
+__device__ __forceinline__ bool decode_block_codec(R& r, int minexp, double step, T acc[64], const uint8_t* sq,
+                                                   bool rel) {
+  if constexpr (kCodec == 0) return decode_block_add<T>(r, minexp, acc, sq, rel);
+  else return pq_decode_add<T>(r, step, acc);
+}
+
+template <class T, bool kStaged, bool kBox = false, bool kFull = false, int kCodec = 0>
 __device__ __forceinline__ bool decode_wave(const Geo& g, const uint8_t* const* s, const uint32_t* const* aux,
-                                            const uint64_t* words, const int* minexp, int ncomp, uint32_t relmask,
-                                            const T* in, T* out, uint64_t w, const uint8_t* sq, uint32_t* stage,
-                                            const BoxArgs* box = nullptr) {
+                                            const uint64_t* words, const int* minexp, const double* step, int ncomp,
+                                            uint32_t relmask, const T* in, T* out, uint64_t w, const uint8_t* sq,
+                                            uint32_t* stage, const BoxArgs* box = nullptr) {
   const uint32_t lane = threadIdx.x;
   const uint64_t blk = w * 64 + lane;
   bool active = blk < g.nblocks;
@@ -954,7 +1016,7 @@ __device__ __forceinline__ bool decode_wave(const Geo& g, const uint8_t* const* 
           LBits r;
           r.init(stage + cur_base, start - s0 + (off >> 5), stop - s0, cur_cap);
           r.skip((uint32_t)(off & 31));
-          ok = decode_block_add<T>(r, minexp[i], acc, sq, (relmask >> i) & 1u) && !r.bad();
+          ok = decode_block_codec<T, kCodec>(r, minexp[i], step[i], acc, sq, (relmask >> i) & 1u) && !r.bad();
         }
       }
       if (i + 1 < ncomp && !pre) {  // staged after this component, into the whole buffer's first half or all of it
@@ -990,11 +1052,17 @@ __device__ __forceinline__ bool decode_wave(const Geo& g, const uint8_t* const* 
       GBits r;
       r.init(payload, (uint32_t)(start + (off >> 5)), (uint32_t)stop);
       r.skip((uint32_t)(off & 31));
-      ok = decode_block_add<T>(r, minexp[i], acc, sq, (relmask >> i) & 1u) && !r.bad();
+      ok = decode_block_codec<T, kCodec>(r, minexp[i], step[i], acc, sq, (relmask >> i) & 1u) && !r.bad();
     }
   }
+  // a block whose stream did not parse is written as quiet NaNs, so the
+  // output never keeps stale memory (the status word reports it as well)
+  if (active && !ok) {
+#pragma unroll
+    for (int l = 0; l < 64; ++l) acc[l] = (T)__builtin_nan("");
+  }
   // the block position is recomputed here rather than kept in registers
-  if (active && ok) {
+  if (active) {
     if constexpr (kBox) {
       store_box(out, *box, block_pos(g, opaque(w) * 64 + lane), acc);
     } else if constexpr (kFull) {
@@ -1008,13 +1076,13 @@ __device__ __forceinline__ bool decode_wave(const Geo& g, const uint8_t* const* 
   return ok || !active;
 }
 
-template <class T, bool kStaged, bool kFull>
+template <class T, bool kStaged, bool kFull, int kCodec>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_decode(DecArgs<T> a) {
   __shared__ uint8_t s_squeeze[256];
   __shared__ uint32_t s_stage[kStaged ? kStageWords + 3 : 1];
   squeeze_table(s_squeeze);
-  if (!decode_wave<T, kStaged, false, kFull>(a.g, a.s, a.aux, a.words, a.minexp, a.ncomp, a.relmask, a.in, a.out, blockIdx.x,
-                               s_squeeze, s_stage))
+  if (!decode_wave<T, kStaged, false, kFull, kCodec>(a.g, a.s, a.aux, a.words, a.minexp, a.step, a.ncomp, a.relmask,
+                                                     a.in, a.out, blockIdx.x, s_squeeze, s_stage))
     atomicOr(a.status, 1u);
 }
 
@@ -1023,7 +1091,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
 // exit.  a.in / a.out are box arrays (a.in: the box after earlier components).
 // A wave whose blocks span several box rows (narrow fields) is staged once
 // per row, and each row's workgroup decodes only that row's blocks.
-template <class T, bool kStaged>
+template <class T, bool kStaged, int kCodec>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_decode_box(
     DecArgs<T> a, BoxArgs b) {
   __shared__ uint8_t s_squeeze[256];
@@ -1036,14 +1104,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
   const uint64_t w = b.row_first / 64 + i;
   if (w > b.row_last / 64) return;  // uniform over the workgroup
   squeeze_table(s_squeeze);
-  if (!decode_wave<T, kStaged, true>(a.g, a.s, a.aux, a.words, a.minexp, a.ncomp, a.relmask, a.in, a.out, w,
-                                     s_squeeze, s_stage, &b))
+  if (!decode_wave<T, kStaged, true, false, kCodec>(a.g, a.s, a.aux, a.words, a.minexp, a.step, a.ncomp, a.relmask,
+                                                    a.in, a.out, w, s_squeeze, s_stage, &b))
     atomicOr(a.status, 1u);
 }
 
 // many retrieval queries in one launch: wave w belongs to the query q with
 // wave_prefix[q] <= w < wave_prefix[q + 1]
-template <class T, bool kStaged>
+template <class T, bool kStaged, int kCodec>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_decode_queries(ServeArgs a) {
   __shared__ uint8_t s_squeeze[256];
   __shared__ uint32_t s_stage[kStaged ? kStageWords + 3 : 1];
@@ -1056,13 +1124,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     else hi = mid;
   }
   const QueryDev& q = a.q[lo];
-  if (!decode_wave<T, kStaged>(q.g, q.s, q.aux, q.words, q.minexp, q.ncomp, q.relmask, reinterpret_cast<const T*>(q.in),
-                               reinterpret_cast<T*>(q.out), w - a.wave_prefix[lo], s_squeeze, s_stage))
+  if (!decode_wave<T, kStaged, false, false, kCodec>(q.g, q.s, q.aux, q.words, q.minexp, q.step, q.ncomp, q.relmask,
+                                                     reinterpret_cast<const T*>(q.in), reinterpret_cast<T*>(q.out),
+                                                     w - a.wave_prefix[lo], s_squeeze, s_stage))
     atomicOr(a.status, 1u);
 }
 
 // per-block bit offsets of a stream written elsewhere: parse each chunk
-template <class T>
+template <class T, int kCodec>
 __global__ __launch_bounds__(64) void k_aux(AuxArgs a) {
   __shared__ uint8_t s_squeeze[256];
   squeeze_table(s_squeeze);
@@ -1079,7 +1148,7 @@ __global__ __launch_bounds__(64) void k_aux(AuxArgs a) {
   const uint64_t b0 = chunk * kChunkBlocks, b1 = min<uint64_t>(a.g.nblocks, b0 + kChunkBlocks);
   for (uint64_t blk = b0; blk < b1; ++blk) {
     a.aux[blk] = ok ? (uint32_t)r.consumed((uint32_t)start) : 0u;
-    if (ok) ok = block_skip<T>(r, a.minexp, s_squeeze) && !r.bad();
+    if (ok) ok = (kCodec == 0 ? block_skip<T>(r, a.minexp, s_squeeze) : pq_block_skip<T>(r)) && !r.bad();
   }
   if (!ok && a.status) atomicOr(a.status, 1u);
 }
@@ -1339,12 +1408,18 @@ __global__ __launch_bounds__(64) void k_bpack(BatchArgs b) {
 
 // ---------------------------------------------------------------------------
 // host launchers
-template <class T> hipError_t launch_encode(const EncArgs<T>& a, hipStream_t s) {
+template <class T> hipError_t launch_encode(const EncArgs<T>& a, int codec, hipStream_t s) {
   const uint64_t wgs = (a.g.nblocks + 63) / 64;
   // every block full and every row aligned: the kernel without edge paths
   const bool full = a.g.nx % 4 == 0 && a.g.ny % 4 == 0 && a.g.nz % 4 == 0 && a.g.rows_aligned;
-  if (full) hipLaunchKernelGGL((k_encode<T, true>), dim3((uint32_t)wgs), dim3(64), 0, s, a);
-  else hipLaunchKernelGGL((k_encode<T, false>), dim3((uint32_t)wgs), dim3(64), 0, s, a);
+  const dim3 grid((uint32_t)wgs), wg(64);
+  if (codec == 0) {
+    if (full) hipLaunchKernelGGL((k_encode<T, true, 0>), grid, wg, 0, s, a);
+    else hipLaunchKernelGGL((k_encode<T, false, 0>), grid, wg, 0, s, a);
+  } else {
+    if (full) hipLaunchKernelGGL((k_encode<T, true, 1>), grid, wg, 0, s, a);
+    else hipLaunchKernelGGL((k_encode<T, false, 1>), grid, wg, 0, s, a);
+  }
   return hipGetLastError();
 }
 hipError_t launch_scan(const ScanArgs& a, hipStream_t s) {
@@ -1361,33 +1436,51 @@ template <class T> hipError_t launch_pack(const PackArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 uint64_t stage_words() { return kStageWords; }
-template <class T> hipError_t launch_decode(const DecArgs<T>& a, uint64_t max_span, hipStream_t s) {
+template <class T, int kCodec> void launch_decode_codec(const DecArgs<T>& a, uint64_t max_span, hipStream_t s) {
   const uint64_t wgs = (a.g.nblocks + 63) / 64;
   const dim3 grid((uint32_t)wgs), wg(64);
   // every block full and every row aligned: the kernel without edge paths
   const bool full = a.g.nx % 4 == 0 && a.g.ny % 4 == 0 && a.g.nz % 4 == 0 && a.g.rows_aligned;
   if (max_span <= kStageWords) {
-    if (full) hipLaunchKernelGGL((k_decode<T, true, true>), grid, wg, 0, s, a);
-    else hipLaunchKernelGGL((k_decode<T, true, false>), grid, wg, 0, s, a);
+    if (full) hipLaunchKernelGGL((k_decode<T, true, true, kCodec>), grid, wg, 0, s, a);
+    else hipLaunchKernelGGL((k_decode<T, true, false, kCodec>), grid, wg, 0, s, a);
   } else {
-    if (full) hipLaunchKernelGGL((k_decode<T, false, true>), grid, wg, 0, s, a);
-    else hipLaunchKernelGGL((k_decode<T, false, false>), grid, wg, 0, s, a);
+    if (full) hipLaunchKernelGGL((k_decode<T, false, true, kCodec>), grid, wg, 0, s, a);
+    else hipLaunchKernelGGL((k_decode<T, false, false, kCodec>), grid, wg, 0, s, a);
   }
+}
+template <class T> hipError_t launch_decode(const DecArgs<T>& a, uint64_t max_span, int codec, hipStream_t s) {
+  if (codec == 0) launch_decode_codec<T, 0>(a, max_span, s);
+  else launch_decode_codec<T, 1>(a, max_span, s);
   return hipGetLastError();
 }
 template <class T>
-hipError_t launch_decode_box(const DecArgs<T>& a, const BoxArgs& b, uint64_t max_span, hipStream_t s) {
+hipError_t launch_decode_box(const DecArgs<T>& a, const BoxArgs& b, uint64_t max_span, int codec, hipStream_t s) {
   const uint64_t rows = (b.bhi[1] - b.blo[1]) * (b.bhi[2] - b.blo[2]);
   const uint64_t wgs = rows * b.waves_per_row;
   if (wgs == 0) return hipSuccess;
-  if (max_span <= kStageWords) hipLaunchKernelGGL((k_decode_box<T, true>), dim3((uint32_t)wgs), dim3(64), 0, s, a, b);
-  else hipLaunchKernelGGL((k_decode_box<T, false>), dim3((uint32_t)wgs), dim3(64), 0, s, a, b);
+  const dim3 grid((uint32_t)wgs), wg(64);
+  const bool staged = max_span <= kStageWords;
+  if (codec == 0) {
+    if (staged) hipLaunchKernelGGL((k_decode_box<T, true, 0>), grid, wg, 0, s, a, b);
+    else hipLaunchKernelGGL((k_decode_box<T, false, 0>), grid, wg, 0, s, a, b);
+  } else {
+    if (staged) hipLaunchKernelGGL((k_decode_box<T, true, 1>), grid, wg, 0, s, a, b);
+    else hipLaunchKernelGGL((k_decode_box<T, false, 1>), grid, wg, 0, s, a, b);
+  }
   return hipGetLastError();
 }
-template <class T> hipError_t launch_decode_queries(const ServeArgs& a, uint64_t max_span, hipStream_t s) {
+template <class T> hipError_t launch_decode_queries(const ServeArgs& a, uint64_t max_span, int codec, hipStream_t s) {
   if (a.nwaves == 0) return hipSuccess;
-  if (max_span <= kStageWords) hipLaunchKernelGGL((k_decode_queries<T, true>), dim3(a.nwaves), dim3(64), 0, s, a);
-  else hipLaunchKernelGGL((k_decode_queries<T, false>), dim3(a.nwaves), dim3(64), 0, s, a);
+  const dim3 grid(a.nwaves), wg(64);
+  const bool staged = max_span <= kStageWords;
+  if (codec == 0) {
+    if (staged) hipLaunchKernelGGL((k_decode_queries<T, true, 0>), grid, wg, 0, s, a);
+    else hipLaunchKernelGGL((k_decode_queries<T, false, 0>), grid, wg, 0, s, a);
+  } else {
+    if (staged) hipLaunchKernelGGL((k_decode_queries<T, true, 1>), grid, wg, 0, s, a);
+    else hipLaunchKernelGGL((k_decode_queries<T, false, 1>), grid, wg, 0, s, a);
+  }
   return hipGetLastError();
 }
 // ---------------------------------------------------------------------------
@@ -1529,9 +1622,10 @@ template hipError_t launch_cast_encode<double>(const double*, uint64_t, int, flo
 template hipError_t launch_cast_decode<float>(const float*, uint64_t, int, float*, hipStream_t);
 template hipError_t launch_cast_decode<double>(const float*, uint64_t, int, double*, hipStream_t);
 
-template <class T> hipError_t launch_aux(const AuxArgs& a, hipStream_t s) {
+template <class T> hipError_t launch_aux(const AuxArgs& a, int codec, hipStream_t s) {
   const uint64_t wgs = (a.g.nchunks + 63) / 64;
-  hipLaunchKernelGGL(k_aux<T>, dim3((uint32_t)wgs), dim3(64), 0, s, a);
+  if (codec == 0) hipLaunchKernelGGL((k_aux<T, 0>), dim3((uint32_t)wgs), dim3(64), 0, s, a);
+  else hipLaunchKernelGGL((k_aux<T, 1>), dim3((uint32_t)wgs), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 template <class T> hipError_t launch_range(const T* x, uint64_t n, unsigned long long* out, hipStream_t s) {
@@ -1568,20 +1662,20 @@ hipError_t launch_fill64(unsigned long long* p, uint64_t n, unsigned long long v
 
 template hipError_t launch_encode_batch<float>(const BatchArgs&, uint32_t, hipStream_t);
 template hipError_t launch_encode_batch<double>(const BatchArgs&, uint32_t, hipStream_t);
-template hipError_t launch_encode<float>(const EncArgs<float>&, hipStream_t);
-template hipError_t launch_encode<double>(const EncArgs<double>&, hipStream_t);
+template hipError_t launch_encode<float>(const EncArgs<float>&, int, hipStream_t);
+template hipError_t launch_encode<double>(const EncArgs<double>&, int, hipStream_t);
 template hipError_t launch_pack<float>(const PackArgs&, hipStream_t);
 template hipError_t launch_pack<double>(const PackArgs&, hipStream_t);
-template hipError_t launch_decode<float>(const DecArgs<float>&, uint64_t, hipStream_t);
-template hipError_t launch_decode<double>(const DecArgs<double>&, uint64_t, hipStream_t);
-template hipError_t launch_decode_queries<float>(const ServeArgs&, uint64_t, hipStream_t);
-template hipError_t launch_decode_queries<double>(const ServeArgs&, uint64_t, hipStream_t);
-template hipError_t launch_aux<float>(const AuxArgs&, hipStream_t);
-template hipError_t launch_aux<double>(const AuxArgs&, hipStream_t);
+template hipError_t launch_decode<float>(const DecArgs<float>&, uint64_t, int, hipStream_t);
+template hipError_t launch_decode<double>(const DecArgs<double>&, uint64_t, int, hipStream_t);
+template hipError_t launch_decode_queries<float>(const ServeArgs&, uint64_t, int, hipStream_t);
+template hipError_t launch_decode_queries<double>(const ServeArgs&, uint64_t, int, hipStream_t);
+template hipError_t launch_aux<float>(const AuxArgs&, int, hipStream_t);
+template hipError_t launch_aux<double>(const AuxArgs&, int, hipStream_t);
 template hipError_t launch_range<float>(const float*, uint64_t, unsigned long long*, hipStream_t);
 template hipError_t launch_range<double>(const double*, uint64_t, unsigned long long*, hipStream_t);
-template hipError_t launch_decode_box<float>(const DecArgs<float>&, const BoxArgs&, uint64_t, hipStream_t);
-template hipError_t launch_decode_box<double>(const DecArgs<double>&, const BoxArgs&, uint64_t, hipStream_t);
+template hipError_t launch_decode_box<float>(const DecArgs<float>&, const BoxArgs&, uint64_t, int, hipStream_t);
+template hipError_t launch_decode_box<double>(const DecArgs<double>&, const BoxArgs&, uint64_t, int, hipStream_t);
 template hipError_t launch_sum_sq<float>(const float*, const float*, double, uint64_t, double*, double*, hipStream_t);
 template hipError_t launch_sum_sq<double>(const double*, const double*, double, uint64_t, double*, double*,
                                           hipStream_t);

@@ -55,6 +55,7 @@ template <class T> struct EncArgs {
   uint32_t* aux;   // per block: bit offset of the block inside its chunk
   CompMeta* meta;  // this component's entry
   double* berr;    // per block: max error before this component (read unless first), after it (written unless last)
+  double h0, inv0;  // codec 1: the bin 2 tau and its reciprocal (computed on the host)
 };
 
 // chunk offsets are an exclusive scan of chunk word counts, done in tiles of
@@ -83,6 +84,7 @@ struct PackArgs {
   uint8_t* streams;
   Geo g;
   double tau;
+  int codec;  // written into the stream header
 };
 
 template <class T> struct DecArgs {
@@ -90,6 +92,7 @@ template <class T> struct DecArgs {
   const uint32_t* aux[kMaxDecode];  // per-block bit offsets inside the chunk
   uint64_t words[kMaxDecode];      // payload words of each stream
   int minexp[kMaxDecode];
+  double step[kMaxDecode];  // codec 1: the bin 2 tau of each component
   int ncomp;
   uint32_t relmask;  // bit i: component i is a residual (not a store's first), planes counted from its first non-empty one
   const T* in;  // x~ to continue from; NULL = +0
@@ -116,6 +119,7 @@ struct QueryDev {
   const uint32_t* aux[kMaxComps];
   uint64_t words[kMaxComps];
   int minexp[kMaxComps];
+  double step[kMaxComps];  // codec 1: the bin 2 tau of each component
   int ncomp;
   uint32_t relmask;  // as DecArgs::relmask
   int dtype;
@@ -182,16 +186,18 @@ hipError_t launch_batch_scan(const BatchArgs& tiles, uint32_t nfields, hipStream
 hipError_t launch_batch_pack(const BatchArgs& quads, hipStream_t s);
 hipError_t launch_batch_init(const FieldDev* fields, uint32_t nfields, hipStream_t s);
 
-template <class T> hipError_t launch_encode(const EncArgs<T>& a, hipStream_t s);
+// codec: 0 the block-transform codec, 1 prediction and quantisation
+template <class T> hipError_t launch_encode(const EncArgs<T>& a, int codec, hipStream_t s);
 hipError_t launch_scan(const ScanArgs& a, hipStream_t s);
-template <class T> hipError_t launch_aux(const AuxArgs& a, hipStream_t s);
+template <class T> hipError_t launch_aux(const AuxArgs& a, int codec, hipStream_t s);
 // max_span: the largest word span of a wave's four chunks over the decoded
 // streams; spans up to the LDS staging capacity use the staged kernel
-template <class T> hipError_t launch_decode_queries(const ServeArgs& a, uint64_t max_span, hipStream_t s);
+template <class T> hipError_t launch_decode_queries(const ServeArgs& a, uint64_t max_span, int codec, hipStream_t s);
 template <class T> hipError_t launch_pack(const PackArgs& a, hipStream_t s);
-template <class T> hipError_t launch_decode(const DecArgs<T>& a, uint64_t max_span, hipStream_t s);
+template <class T> hipError_t launch_decode(const DecArgs<T>& a, uint64_t max_span, int codec, hipStream_t s);
 // components [0, a.ncomp) of the blocks meeting the box, written to a.out as the box alone
-template <class T> hipError_t launch_decode_box(const DecArgs<T>& a, const BoxArgs& b, uint64_t max_span, hipStream_t s);
+template <class T>
+hipError_t launch_decode_box(const DecArgs<T>& a, const BoxArgs& b, uint64_t max_span, int codec, hipStream_t s);
 uint64_t stage_words();  // capacity of the decoder's LDS staging buffer, in words
 template <class T> hipError_t launch_range(const T* x, uint64_t n, unsigned long long* out, hipStream_t s);
 hipError_t launch_fill64(unsigned long long* p, uint64_t n, unsigned long long v, hipStream_t s);

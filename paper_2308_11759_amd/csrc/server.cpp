@@ -114,6 +114,7 @@ struct Step {
 };
 
 constexpr int kMaxInflight = 4;
+constexpr int kGroups = 4;  // (float32, float64) x (block transform, prediction)
 
 }  // namespace
 
@@ -123,7 +124,8 @@ struct pmc_server {
   uint8_t* arena_base = nullptr;
   uint64_t arena_bytes = 0, budget = 0;
   int max_batch = 64;
-  // device tables: kMaxInflight slots of [2 x max_batch QueryDev | 2 x (max_batch+1) prefixes | status]
+  // device tables: kMaxInflight slots of [kGroups x max_batch QueryDev | kGroups x (max_batch+1) prefixes |
+  // status]; a group per (element type, codec), each decoded by one launch
   uint64_t table_slot_bytes = 0;
   void* host_tables = nullptr;  // pinned staging, same layout
   bool slot_busy[kMaxInflight] = {false, false, false, false};
@@ -225,12 +227,19 @@ bool launch_step(pmc_server* sv) {
   const uint64_t step_id = ++sv->step_counter;
   uint8_t* htab = (uint8_t*)sv->host_tables + slot * sv->table_slot_bytes;
   uint8_t* dtab = sv->arena_base + slot * sv->table_slot_bytes;
-  QueryDev* hq[2] = {(QueryDev*)htab, (QueryDev*)htab + sv->max_batch};
-  uint32_t* hpre[2] = {(uint32_t*)(htab + 2 * sv->max_batch * sizeof(QueryDev)),
-                       (uint32_t*)(htab + 2 * sv->max_batch * sizeof(QueryDev)) + (sv->max_batch + 1)};
-  uint32_t nq[2] = {0, 0}, nw[2] = {0, 0};
-  uint64_t span[2] = {0, 0};  // largest decode-wave span of the step's streams, per type
-  hpre[0][0] = hpre[1][0] = 0;
+  QueryDev* hq[kGroups];
+  uint32_t* hpre[kGroups];
+  uint32_t nq[kGroups], nw[kGroups];
+  uint64_t span[kGroups];  // largest decode-wave span of the step's streams, per group
+  uint32_t* const pre0 = (uint32_t*)(htab + kGroups * sv->max_batch * sizeof(QueryDev));
+  for (int t = 0; t < kGroups; ++t) {
+    hq[t] = (QueryDev*)htab + t * sv->max_batch;
+    hpre[t] = pre0 + t * (sv->max_batch + 1);
+    hpre[t][0] = 0;
+    nq[t] = nw[t] = 0;
+    span[t] = 0;
+  }
+  uint32_t admitted = 0;
   Step st{};
   st.id = step_id;
   st.table_slot = slot;
@@ -240,7 +249,7 @@ bool launch_step(pmc_server* sv) {
     uint64_t bytes;
   };
   std::vector<CopyJob> copies;
-  while (!sv->pending.empty() && nq[0] + nq[1] < (uint32_t)sv->max_batch) {
+  while (!sv->pending.empty() && admitted < (uint32_t)sv->max_batch) {
     const uint64_t qi = sv->pending.front();
     Query& q = sv->queries[qi];
     const pmc_store* s = sv->fields[q.field];
@@ -260,7 +269,7 @@ bool launch_step(pmc_server* sv) {
     }
     sv->pending.pop_front();
     void* out = q.out ? q.out : (void*)(sv->arena_base + q.slot_off);
-    const int t = s->f.dtype == PMC_F32 ? 0 : 1;
+    const int t = (s->f.dtype == PMC_F32 ? 0 : 1) + 2 * s->codec;
     QueryDev& d = hq[t][nq[t]];
     std::memset(&d, 0, sizeof(d));
     const int ci = find_cache(sv, q.field, q.k, step_id);
@@ -282,6 +291,7 @@ bool launch_step(pmc_server* sv) {
       d.aux[i] = (const uint32_t*)(s->d_base + s->aux_offset[c]);
       d.words[i] = s->words[c];
       d.minexp[i] = s->minexp[c];
+      d.step[i] = 2.0 * s->tau[c];
       if (c > 0) d.relmask |= 1u << i;  // residual components
       span[t] = std::max(span[t], s->max_span[c]);
     }
@@ -292,6 +302,7 @@ bool launch_step(pmc_server* sv) {
     hpre[t][nq[t] + 1] = hpre[t][nq[t]] + waves;
     nw[t] += waves;
     nq[t]++;
+    admitted++;
     // keep the new partial sum if it is not cached yet and there is room
     if (q.source != 2) {
       bool have = false;
@@ -314,16 +325,17 @@ bool launch_step(pmc_server* sv) {
   unsigned int* hstatus = (unsigned int*)(htab + sv->table_slot_bytes - 256);
   *hstatus = 0;
   hipError_t e = hipMemcpyAsync(dtab, htab, sv->table_slot_bytes, hipMemcpyHostToDevice, sv->stream);
-  for (int t = 0; t < 2 && e == hipSuccess; ++t) {
+  for (int t = 0; t < kGroups && e == hipSuccess; ++t) {
     if (!nq[t]) continue;
     ServeArgs a{};
-    a.q = (const QueryDev*)(dtab + (t ? sv->max_batch * sizeof(QueryDev) : 0));
-    a.wave_prefix = (const uint32_t*)(dtab + 2 * sv->max_batch * sizeof(QueryDev)) + t * (sv->max_batch + 1);
+    a.q = (const QueryDev*)dtab + t * sv->max_batch;
+    a.wave_prefix = (const uint32_t*)(dtab + kGroups * sv->max_batch * sizeof(QueryDev)) + t * (sv->max_batch + 1);
     a.nq = nq[t];
     a.nwaves = nw[t];
     a.status = (unsigned int*)(dtab + sv->table_slot_bytes - 256);
-    e = t == 0 ? launch_decode_queries<float>(a, span[t], sv->stream)
-               : launch_decode_queries<double>(a, span[t], sv->stream);
+    const int codec = t / 2;
+    e = t % 2 == 0 ? launch_decode_queries<float>(a, span[t], codec, sv->stream)
+                   : launch_decode_queries<double>(a, span[t], codec, sv->stream);
   }
   for (const CopyJob& c : copies)
     if (e == hipSuccess) e = hipMemcpyAsync(c.dst, c.src, c.bytes, hipMemcpyDeviceToDevice, sv->stream);
@@ -392,7 +404,7 @@ pmc_status pmc_server_create(pmc_ctx* ctx, size_t hbm_budget, void* d_arena, siz
   pmc_server* sv = new pmc_server();
   sv->ctx = ctx;
   sv->max_batch = max_batch;
-  sv->table_slot_bytes = align256(2 * max_batch * sizeof(QueryDev) + 2 * (max_batch + 1) * 4 + 256) + 256;
+  sv->table_slot_bytes = align256(kGroups * max_batch * sizeof(QueryDev) + kGroups * (max_batch + 1) * 4 + 256) + 256;
   const uint64_t tables = kMaxInflight * sv->table_slot_bytes;
   if (arena_bytes < tables + 256) {
     delete sv;
@@ -423,8 +435,16 @@ pmc_status pmc_server_add(pmc_server* sv, const pmc_store* s, int* field_id) {
   return PMC_OK;
 }
 
+double pmc_clock(void) { return std::chrono::duration<double>(clk::now().time_since_epoch()).count(); }
+
 pmc_status pmc_server_submit(pmc_server* sv, int field_id, double tol, void* d_out, uint64_t* ticket) {
+  return pmc_server_submit_at(sv, field_id, tol, d_out, 0.0, ticket);
+}
+
+pmc_status pmc_server_submit_at(pmc_server* sv, int field_id, double tol, void* d_out, double arrival,
+                                uint64_t* ticket) {
   if (!sv || !ticket) return PMC_E_ARG;
+  const clk::time_point now = clk::now();
   std::lock_guard<std::mutex> lk(sv->mu);
   if (field_id < 0 || field_id >= (int)sv->fields.size()) return fail(sv->ctx, PMC_E_ARG, "unknown field");
   if (d_out && !aligned16(d_out)) return fail(sv->ctx, PMC_E_ARG, "d_out must be 16-byte aligned");
@@ -437,7 +457,14 @@ pmc_status pmc_server_submit(pmc_server* sv, int field_id, double tol, void* d_o
   q.field = field_id;
   q.k = k;
   q.out = d_out;
-  q.arrival = clk::now();
+  // the arrival the latency counts from: the caller's (e.g. the scheduled
+  // time of a trace), never later than now; else the submission itself
+  q.arrival = now;
+  if (arrival > 0.0) {
+    const clk::time_point a =
+        clk::time_point(std::chrono::duration_cast<clk::duration>(std::chrono::duration<double>(arrival)));
+    if (a < now) q.arrival = a;
+  }
   sv->queries.push_back(q);
   *ticket = sv->queries.size() - 1;
   sv->pending.push_back(*ticket);

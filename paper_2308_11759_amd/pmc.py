@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libpmc.so")
 
 OK, E_ARG, E_NONFINITE, E_NOMEM, E_CORRUPT, E_UNREACHABLE, E_BOUND, E_DEVICE = 0, -1, -2, -3, -4, -5, -6, -7
 F32, F64 = 1, 2
-OPT_FUSED_DECODE, OPT_SYNC_CHECK, OPT_PROFILE = 1, 2, 3
+OPT_FUSED_DECODE, OPT_SYNC_CHECK, OPT_PROFILE, OPT_CODEC = 1, 2, 3, 4
+CODEC_TRANSFORM, CODEC_PREDICTION = 0, 1
 _NAMES = {0: "OK", -1: "E_ARG", -2: "E_NONFINITE", -3: "E_NOMEM", -4: "E_CORRUPT", -5: "E_UNREACHABLE",
           -6: "E_BOUND", -7: "E_DEVICE"}
 
@@ -65,6 +66,7 @@ SIGNATURES = {
     "pmc_compress": (_int, [_vp, _P(Field), _vp, _int, _P(_dbl), _vp, _sz, _vp, _sz, _P(_vp)]),
     "pmc_store_info": (_int, [_vp, _P(_int), _P(_dbl), _P(_dbl), _P(_u64), _P(_u64), _P(_u64)]),
     "pmc_store_counts": (_int, [_vp, _int, _P(_u64)]),
+    "pmc_store_codec": (_int, [_vp, _P(_int)]),
     "pmc_store_span": (_int, [_vp, _int, _P(_u64), _P(_int)]),
     "pmc_store_field": (_int, [_vp, _P(Field)]),
     "pmc_store_stream": (_int, [_vp, _int, _P(_vp), _P(_u64)]),
@@ -88,6 +90,8 @@ SIGNATURES = {
     "pmc_server_create": (_int, [_vp, _sz, _vp, _sz, _int, _P(_vp)]),
     "pmc_server_add": (_int, [_vp, _vp, _P(_int)]),
     "pmc_server_submit": (_int, [_vp, _int, _dbl, _vp, _P(_u64)]),
+    "pmc_clock": (_dbl, []),
+    "pmc_server_submit_at": (_int, [_vp, _int, _dbl, _vp, _dbl, _P(_u64)]),
     "pmc_server_poll": (_int, [_vp, _u64, _P(_int), _P(_int), _P(_dbl)]),
     "pmc_server_result": (_int, [_vp, _u64, _P(_vp), _P(_int), _P(_int)]),
     "pmc_server_release": (_int, [_vp, _u64]),
@@ -408,6 +412,7 @@ class Server:
                                               self.arena.numel(), int(max_batch), ctypes.byref(h)))
         self.handle = h
         self.stores = []
+        self._outs = {}  # ticket -> caller output tensor of a query not yet done
 
     def add(self, store):
         fid = ctypes.c_int()
@@ -415,10 +420,20 @@ class Server:
         self.stores.append(store)
         return fid.value
 
-    def submit(self, field, tol, out=None):
+    def submit(self, field, tol, out=None, arrival=None):
+        """Queue "field at tolerance tol"; returns a ticket.  With `out` (a
+        device tensor of the field's shape and type) the result is written
+        there: the server keeps a reference to `out` until poll() reports the
+        query done or release() is called, so the caching allocator cannot
+        hand its memory to another tensor while the server still writes it.
+        `arrival` (seconds on clock()) is the time the latency counts from,
+        e.g. a trace's scheduled arrival; default: now."""
         t = ctypes.c_uint64()
         ptr = ctypes.c_void_p(out.data_ptr()) if out is not None else None
-        self.ctx._check(self.lib.pmc_server_submit(self.handle, int(field), float(tol), ptr, ctypes.byref(t)))
+        self.ctx._check(self.lib.pmc_server_submit_at(self.handle, int(field), float(tol), ptr,
+                                                      float(arrival or 0.0), ctypes.byref(t)))
+        if out is not None:
+            self._outs[t.value] = out
         return t.value
 
     def poll(self, ticket):
@@ -426,6 +441,8 @@ class Server:
         d, st, lat = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
         self.ctx._check(self.lib.pmc_server_poll(self.handle, int(ticket), ctypes.byref(d), ctypes.byref(st),
                                                  ctypes.byref(lat)))
+        if d.value:
+            self._outs.pop(int(ticket), None)
         return bool(d.value), st.value, lat.value
 
     def result(self, ticket, field):
@@ -444,6 +461,7 @@ class Server:
 
     def release(self, ticket):
         self.ctx._check(self.lib.pmc_server_release(self.handle, int(ticket)))
+        self._outs.pop(int(ticket), None)
 
     def stats(self):
         s = ServerStats()
@@ -460,6 +478,11 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def clock():
+    """Seconds on the library's monotonic clock (server latencies use it)."""
+    return load().pmc_clock()
 
 
 def np_prod(shape):
@@ -484,7 +507,21 @@ class Store:
         self.shape = tuple(int(s) for s in shape)
         self.dtype = _torch_dtype(f.dtype)
         self.bound_missed = False
-        self.info = self._info()
+        self._info_cache = None  # per-component metadata, read on first use
+
+    @property
+    def info(self):
+        """Per-component metadata (a list of dicts), read from the library on
+        first use (a batch returns many stores; most callers read few)."""
+        if self._info_cache is None:
+            self._info_cache = self._info()
+        return self._info_cache
+
+    @property
+    def codec(self):
+        c = ctypes.c_int()
+        self.ctx._check(self.lib.pmc_store_codec(self.handle, ctypes.byref(c)))
+        return c.value
 
     def _info(self):
         n = ctypes.c_int()

@@ -10,14 +10,14 @@ def align256(v):
     return (v + 255) & ~255
 
 
-def store_blob(x_shape, dtype, comps, meta):
+def store_blob(x_shape, dtype, comps, meta, codec=0):
     """Serialised-store blob (layout of pmc_store_serialize) around streams
     produced by the CPU oracle, so the GPU decoder can be checked on streams
     its own encoder did not write."""
     n = len(comps)
     nz, ny, nx = x_shape
     code = 1 if np.dtype(dtype) == np.float32 else 2
-    head = struct.pack("<IIII", 0x53434D50, 1, n, 0) + struct.pack("<QQQii", nx, ny, nz, code, 0)
+    head = struct.pack("<IIII", 0x53434D50, 1, n, codec) + struct.pack("<QQQii", nx, ny, nz, code, 0)
     for c, m in zip(comps, meta):
         head += struct.pack("<ddQQQQQQ", m["tau"], m["linf"], len(c), m.get("nempty", 0), m.get("ncoded", 0),
                             m.get("nraw", 0), m.get("nesc", 0), m.get("nmiss", 0))
@@ -30,9 +30,9 @@ def store_blob(x_shape, dtype, comps, meta):
     return bytes(blob + region)
 
 
-def oracle_run(x, taus):
-    comps, meta = driver.compress(x, taus)
-    recon = [driver.reconstruct(comps, k, x.shape, x.dtype) for k in range(1, len(comps) + 1)]
+def oracle_run(x, taus, codec=None):
+    comps, meta = driver.compress(x, taus, codec)
+    recon = [driver.reconstruct(comps, k, x.shape, x.dtype, codec) for k in range(1, len(comps) + 1)]
     return comps, meta, recon
 
 

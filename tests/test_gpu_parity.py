@@ -293,11 +293,72 @@ def test_corrupt_payload_is_contained(ctx):
         b = bytearray(blob)
         pos = head + 64 + 4 * nchunks + int(rng.integers(0, first - 64 - 4 * nchunks))
         b[pos] ^= 1 << int(rng.integers(0, 8))
-        s = ctx.deserialize(bytes(b))
+        try:  # the index rebuild on load may already find the chunk malformed
+            s = ctx.deserialize(bytes(b))
+        except pmc.PmcError as e:
+            assert e.status == pmc.E_CORRUPT
+            continue
         try:
             ctx.retrieve(s, 2)
         except pmc.PmcError as e:
             assert e.status == pmc.E_CORRUPT
+
+
+def test_rejected_blocks_are_written_as_nan(ctx):
+    """Without the synchronising check a decode call returns OK at once; a
+    block whose bits do not parse is then written as NaNs, never left as the
+    output held it, and the synchronising check reports it.  The stream is
+    altered in device memory after its per-block index was built, so the
+    decoder itself meets the malformed block: block 15 (the last of chunk 0)
+    gets a coded-block header followed by an escalation count longer than
+    the 32 planes of a float32 block."""
+    import torch
+    from paper_2308_11759_amd import pmc
+    x = inputs.spectral_field((8, 12, 16), seed=6, dtype=np.float32)
+    store = ctx.compress(to_dev(x), [1e-2, 1e-4])
+    nblocks, nchunks = 2 * 3 * 4, 2
+    sv = store.stream(1)
+    clean = sv.clone()
+    # the per-block bit offsets of component 2 sit in front of the streams
+    auxb = (4 * nblocks + 255) & ~255
+    aux = store.streams[auxb:auxb + 4 * nblocks].cpu().numpy().view(np.uint32)
+    bad = clean.cpu().numpy().copy()
+    pay0 = 64 + 4 * nchunks
+    off = int(aux[15])  # chunk 0 starts at payload word 0
+
+    def setbit(b, v):
+        byte, bit = pay0 + b // 8, b % 8
+        bad[byte] = np.uint8((int(bad[byte]) & (0xFF ^ (1 << bit))) | (v << bit))
+
+    setbit(off, 1)
+    setbit(off + 1, 0)
+    for t in range(off + 2, off + 2 + 40):
+        if pay0 + t // 8 < bad.size:
+            setbit(t, 1)
+    try:
+        sv.copy_(torch.from_numpy(bad))
+        ctx.set_option(pmc.OPT_SYNC_CHECK, 0)
+        out = torch.full(x.shape, 7.0, dtype=torch.float32, device="cuda:0")
+        ctx.retrieve(store, 2, out=out)  # returns OK without waiting
+        torch.cuda.synchronize()
+        o = out.cpu().numpy()
+        assert not np.any(o == 7.0)
+        # block 15: block coordinates (bx, by, bz) = (3, 0, 1) of the 4 x 3 x 2 grid
+        blk = o[4:8, 0:4, 12:16]
+        assert np.all(np.isnan(blk))
+        ctx.set_option(pmc.OPT_SYNC_CHECK, 1)
+        with pytest.raises(pmc.PmcError) as ei:
+            ctx.retrieve(store, 2)
+        assert ei.value.status == pmc.E_CORRUPT
+        # the untouched component alone still decodes cleanly
+        one = ctx.retrieve(store, 1).cpu().numpy()
+        assert not np.any(np.isnan(one))
+    finally:
+        sv.copy_(clean)
+        ctx.set_option(pmc.OPT_SYNC_CHECK, 1)
+    # with the stream restored the result is the oracle's again
+    comps, _ = driver.compress(x, [1e-2, 1e-4])
+    assert np.array_equal(ctx.retrieve(store, 2).cpu().numpy(), driver.reconstruct(comps, 2, x.shape, x.dtype))
 
 
 def test_accuracy_gain(ctx):
