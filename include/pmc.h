@@ -79,9 +79,9 @@ const char* pmc_last_error(const pmc_ctx* ctx);
  *    was. */
 /*  PMC_OPT_PROFILE (default 0): bracket every kernel launch with HIP events
  *    on the context stream; pmc_prof_read returns the per-kernel totals.
- *  PMC_OPT_CODEC (default 0): the compressor C / D that pmc_compress puts
- *    behind the multi-component driver, which works with any error-bounded
- *    lossy compressor (Sec. 6.2):
+ *  PMC_OPT_CODEC (default 0): the compressor C / D that pmc_compress and
+ *    pmc_compress_static put behind the multi-component driver, which works
+ *    with any error-bounded lossy compressor (Sec. 6.2):
  *      0  the zfp-style block-transform codec (stream format version 1),
  *      1  prediction and uniform quantisation on the same 4x4x4 blocks (a
  *         prediction-based compressor, Sec. 5): residuals quantised to
@@ -160,6 +160,24 @@ pmc_status pmc_compress_sizes(const pmc_field* f, int n, size_t* ws_bytes, size_
  * their tolerance, counted as misses); the caller frees it. */
 pmc_status pmc_compress(pmc_ctx* ctx, const pmc_field* f, const void* d_x, int n, const double* tau,
                         void* d_ws, size_t ws_bytes, void* d_streams, size_t streams_cap, pmc_store** out);
+
+/* ---- compression for callers that cannot allocate device memory ----------
+ * For callers that cannot call hipMalloc or run an allocator (code under HIP
+ * graph capture, tight serving or simulation loops, harnesses that forbid
+ * allocation): pmc_compress with its workspace taken from a static device
+ * buffer of PMC_STATIC_WS_BYTES that the library holds on each GPU until the
+ * process ends (located by pmc_ctx_create, once per device).  Inputs, outputs
+ * and results as for pmc_compress; the caller still passes d_streams.  A
+ * field whose workspace (pmc_compress_sizes) exceeds PMC_STATIC_WS_BYTES is
+ * refused with PMC_E_NOMEM and the size it needs (about 12 bytes per value
+ * for float32 and 24 for float64 with three or more components, so up to
+ * about 5.5 M float32 or 2.7 M float64 values).  No device memory is
+ * allocated or freed.  Every call on one GPU uses that GPU's one buffer:
+ * calls that overlap on a GPU (from other threads or on other streams) race,
+ * and the caller must serialise them. */
+#define PMC_STATIC_WS_BYTES ((size_t)64 << 20)
+pmc_status pmc_compress_static(pmc_ctx* ctx, const pmc_field* f, const void* d_x, int n, const double* tau,
+                               void* d_streams, size_t streams_cap, pmc_store** out);
 
 /* Per-component metadata (arrays of store n entries; any may be NULL). */
 pmc_status pmc_store_info(const pmc_store* s, int* n, double* tau, double* linf, uint64_t* bytes,

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -145,6 +146,46 @@ pmc_store* store_from_meta(const pmc_field* f, const Geo& g, int n, const double
 
 }  // namespace pmc_host
 
+// ---- the static workspace of pmc_compress_static --------------------------
+// One buffer per GPU, held until the process ends.  Host code never uses the
+// array's name as an address (on the host it names a stand-in, not device
+// memory): pmc_ctx_create looks up its device address once per device with
+// hipGetSymbolAddress, and only that address is passed on.
+static_assert(PMC_STATIC_WS_BYTES % 256 == 0, "static workspace size");
+static __device__ __align__(256) uint8_t scratch[PMC_STATIC_WS_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on `device`, looked up on the first call for
+// that device (with the device current; the caller's current device is
+// restored afterwards)
+hipError_t scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  int prev = 0;
+  hipError_t e = hipGetDevice(&prev);
+  if (e != hipSuccess) return e;
+  if ((e = hipSetDevice(device)) != hipSuccess) return e;
+  void* p = nullptr;
+  e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  const hipError_t r = hipSetDevice(prev);
+  if (e != hipSuccess) return e;
+  if (r != hipSuccess) return r;
+  if (!p) return hipErrorInvalidSymbol;
+  g_scratch_ptr[device] = p;
+  return hipSuccess;
+}
+
+void* scratch_ptr(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return device >= 0 && device < kMaxDevices ? g_scratch_ptr[device] : nullptr;
+}
+}  // namespace
+
 extern "C" {
 
 pmc_status pmc_ctx_create(int device, void* hip_stream, pmc_ctx** out) {
@@ -152,6 +193,7 @@ pmc_status pmc_ctx_create(int device, void* hip_stream, pmc_ctx** out) {
   int count = 0;
   hipError_t e = hipGetDeviceCount(&count);
   if (e != hipSuccess || device < 0 || device >= count) return PMC_E_DEVICE;
+  if (scratch_setup(device) != hipSuccess) return PMC_E_DEVICE;
   pmc_ctx* c = new pmc_ctx();
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
@@ -497,6 +539,27 @@ pmc_status pmc_compress(pmc_ctx* ctx, const pmc_field* f, const void* d_x, int n
   *out = s;
   if (misses) return fail(ctx, PMC_E_BOUND, "%llu blocks missed their tolerance", misses);
   return PMC_OK;
+}
+
+pmc_status pmc_compress_static(pmc_ctx* ctx, const pmc_field* f, const void* d_x, int n, const double* tau,
+                               void* d_streams, size_t streams_cap, pmc_store** out) {
+  if (!ctx) return PMC_E_ARG;
+  if (out) *out = nullptr;
+  Geo g;
+  if (!make_geo(f, &g)) return fail(ctx, PMC_E_ARG, "bad field");
+  if (n < 1 || n > kMaxComps) return fail(ctx, PMC_E_ARG, "n must be in [1, %d]", kMaxComps);
+  const uint64_t need = ws_layout(f, g, n).total;
+  if (need > PMC_STATIC_WS_BYTES)
+    return fail(ctx, PMC_E_NOMEM,
+                "field needs %llu bytes of workspace; the static workspace holds %llu (use pmc_compress "
+                "with a caller workspace)",
+                (unsigned long long)need, (unsigned long long)PMC_STATIC_WS_BYTES);
+  void* ws = scratch_ptr(ctx->device);
+  if (!ws) return fail(ctx, PMC_E_DEVICE, "static workspace not set up on device %d", ctx->device);
+  // the same kernels as pmc_compress; every workspace word they read is
+  // written first in the same call (the per-component counters are cleared
+  // by a fill kernel), so nothing of an earlier call carries over
+  return pmc_compress(ctx, f, d_x, n, tau, ws, PMC_STATIC_WS_BYTES, d_streams, streams_cap, out);
 }
 
 pmc_status pmc_store_info(const pmc_store* s, int* n, double* tau, double* linf, uint64_t* bytes, uint64_t* nraw,

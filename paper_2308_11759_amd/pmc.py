@@ -64,6 +64,7 @@ SIGNATURES = {
     "pmc_accuracy_gain": (_int, [_vp, _P(Field), _vp, _vp, _dbl, _vp, _sz, _P(_dbl)]),
     "pmc_compress_sizes": (_int, [_P(Field), _int, _P(_sz), _P(_sz)]),
     "pmc_compress": (_int, [_vp, _P(Field), _vp, _int, _P(_dbl), _vp, _sz, _vp, _sz, _P(_vp)]),
+    "pmc_compress_static": (_int, [_vp, _P(Field), _vp, _int, _P(_dbl), _vp, _sz, _P(_vp)]),
     "pmc_store_info": (_int, [_vp, _P(_int), _P(_dbl), _P(_dbl), _P(_u64), _P(_u64), _P(_u64)]),
     "pmc_store_counts": (_int, [_vp, _int, _P(_u64)]),
     "pmc_store_codec": (_int, [_vp, _P(_int)]),
@@ -265,6 +266,27 @@ class Context:
             store = Store(self, h, streams)
             store.bound_missed = True
             return store
+        if st != OK:
+            if h.value:
+                self.lib.pmc_store_free(h)
+            self._check(st)
+        return Store(self, h, streams)
+
+    STATIC_WS_BYTES = 64 << 20  # PMC_STATIC_WS_BYTES
+
+    def compress_static(self, x, taus, streams=None):
+        """Alg. 1 without any workspace allocation: the library's static
+        per-GPU workspace (fields whose workspace fits STATIC_WS_BYTES).  With
+        `streams` given, no device memory is allocated at all."""
+        taus = [float(t) for t in taus]
+        n = len(taus)
+        f = field_of(x)
+        if streams is None:
+            streams = torch.empty(self.compress_sizes(x, n)[1] * n, dtype=torch.uint8, device=self.device)
+        tau_arr = (ctypes.c_double * n)(*taus)
+        h = ctypes.c_void_p()
+        st = self.lib.pmc_compress_static(self.handle, ctypes.byref(f), ctypes.c_void_p(x.data_ptr()), n, tau_arr,
+                                          ctypes.c_void_p(streams.data_ptr()), streams.numel(), ctypes.byref(h))
         if st != OK:
             if h.value:
                 self.lib.pmc_store_free(h)
