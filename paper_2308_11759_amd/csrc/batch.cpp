@@ -189,12 +189,13 @@ pmc_status pmc_batch_plan(pmc_ctx* ctx, int nf, const pmc_field* fields, const i
     b->tau.push_back(t);
     b->minexp.push_back(me);
     b->maxn = std::max(b->maxn, n[i]);
-    const uint64_t N = g.nx * g.ny * g.nz;
-    // x~ ping-pong buffers (component i reads buffer (i-1)&1, writes i&1)
+    // x~ ping-pong buffers (component i reads buffer (i-1)&1, writes i&1),
+    // in the encoder's tiled layout: 64 * 64 values per wave of 64 blocks
+    const uint64_t tile = align256((g.nblocks + 63) / 64 * 4096 * elem_size(&fields[i]));
     b->off_xt0.push_back(ws);
-    if (n[i] > 1) ws += align256(N * elem_size(&fields[i]));
+    if (n[i] > 1) ws += tile;
     b->off_xt1.push_back(ws);
-    if (n[i] > 2) ws += align256(N * elem_size(&fields[i]));
+    if (n[i] > 2) ws += tile;
     b->off_staging.push_back(ws);
     ws += align256(g.nchunks * chunk_cap_words_host(fields[i].dtype) * 4);
     b->off_cw.push_back(ws);

@@ -81,11 +81,12 @@ struct WsLayout {
 };
 
 // x~ is double-buffered: component i reads x~_{i-1} from xt[(i-1) & 1] and
-// writes x~_i to xt[i & 1] (the first reads nothing, the last writes nothing)
+// writes x~_i to xt[i & 1] (the first reads nothing, the last writes nothing),
+// each in the encoder's tiled layout: 64 * 64 values per wave of 64 blocks
 WsLayout ws_layout(const pmc_field* f, const Geo& g, int n) {
   WsLayout w{};
   uint64_t o = 0;
-  const uint64_t field = align256(g.nx * g.ny * g.nz * elem_size(f));
+  const uint64_t field = align256((g.nblocks + 63) / 64 * 4096 * elem_size(f));
   w.xt[0] = o;
   if (n > 1) o += field;
   w.xt[1] = o;

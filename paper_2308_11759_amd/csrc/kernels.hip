@@ -252,15 +252,6 @@ __device__ __forceinline__ BlockPos opaque_pos(BlockPos b) {
   b.z0 = opaque(b.z0);
   return b;
 }
-// also the valid extents, so that the edge paths' per-lane conditions are
-// re-derived where used instead of living across a loop as lane masks
-__device__ __forceinline__ BlockPos opaque_ext(BlockPos b) {
-  b = opaque_pos(b);
-  b.vx = opaque(b.vx);
-  b.vy = opaque(b.vy);
-  b.vz = opaque(b.vz);
-  return b;
-}
 
 // a + v * scale where v * scale is exact: one fused multiply-add equals the
 // plain sum of the (exact) product
@@ -297,6 +288,76 @@ template <class T> struct XLds {
   __device__ __forceinline__ T at(int l) const { return *slot(l >> 2, l & 3); }
 };
 
+// The encoder's own partial sums x~_i (its workspace, never seen outside
+// compression) are not kept in the field's layout but in one tile per wave:
+// the wave's 64 blocks as [row r][lane][16-byte piece] (float32: 4 values;
+// float64: [row r][half][lane][2 values]), the layout XLds uses in LDS.
+// Every row access of a wave is then one coalesced 1 KiB transfer at a
+// uniform offset, with no per-lane paths for partial blocks; their padded
+// samples hold values nothing reads (the residual is edge-replicated from
+// the block's valid samples in registers instead).
+constexpr uint64_t kTileValues = 64 * 64;  // values of one wave's tile
+template <class T> __device__ __forceinline__ uint32_t tile_index(uint32_t lane, int r, int t) {
+  if constexpr (sizeof(T) == 4) return ((uint32_t)r * 64 + lane) * 4 + (uint32_t)t;
+  else return (((uint32_t)r * 2 + (uint32_t)(t >> 1)) * 64 + lane) * 2 + (uint32_t)(t & 1);
+}
+// rows [r0, r0 + R) of this lane's block from a wave's tile; a null tile reads as +0
+template <class T, int R>
+__device__ __forceinline__ void tile_load_rows(const T* tile, uint32_t lane, int r0, T v[4 * R]) {
+  if (!tile) {
+#pragma unroll
+    for (int k = 0; k < 4 * R; ++k) v[k] = (T)0;
+    return;
+  }
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    if constexpr (sizeof(T) == 4) {
+      const float4 q = *reinterpret_cast<const float4*>(tile + tile_index<T>(lane, r0 + k, 0));
+      v[4 * k] = q.x; v[4 * k + 1] = q.y; v[4 * k + 2] = q.z; v[4 * k + 3] = q.w;
+    } else {
+      const double2 q0 = *reinterpret_cast<const double2*>(tile + tile_index<T>(lane, r0 + k, 0));
+      const double2 q1 = *reinterpret_cast<const double2*>(tile + tile_index<T>(lane, r0 + k, 2));
+      v[4 * k] = q0.x; v[4 * k + 1] = q0.y; v[4 * k + 2] = q1.x; v[4 * k + 3] = q1.y;
+    }
+  }
+}
+// row r of this lane's block into a wave's tile (streaming cache policy: the
+// next reader is the next component's launch)
+template <class T> __device__ __forceinline__ void tile_store_row(T* tile, uint32_t lane, int r, const T v[4]) {
+  if constexpr (sizeof(T) == 4) {
+    __builtin_nontemporal_store(nt_f4{v[0], v[1], v[2], v[3]}, reinterpret_cast<nt_f4*>(tile + tile_index<T>(lane, r, 0)));
+  } else {
+    __builtin_nontemporal_store(nt_d2{v[0], v[1]}, reinterpret_cast<nt_d2*>(tile + tile_index<T>(lane, r, 0)));
+    __builtin_nontemporal_store(nt_d2{v[2], v[3]}, reinterpret_cast<nt_d2*>(tile + tile_index<T>(lane, r, 2)));
+  }
+}
+// edge replication of a partial block's residual, in registers: each padded
+// sample takes the value of the last valid sample on each axis (x, then y,
+// then z), as the block gather of a partial block does
+template <class T>
+__device__ __forceinline__ void replicate_edges(T e[64], uint32_t vx, uint32_t vy, uint32_t vz) {
+#pragma unroll
+  for (int r = 0; r < 16; ++r)
+#pragma unroll
+    for (int t = 1; t < 4; ++t) e[4 * r + t] = (uint32_t)t < vx ? e[4 * r + t] : e[4 * r + t - 1];
+#pragma unroll
+  for (int lz = 0; lz < 4; ++lz)
+#pragma unroll
+    for (int ly = 1; ly < 4; ++ly)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int l = 4 * ly + 16 * lz + t;
+        e[l] = (uint32_t)ly < vy ? e[l] : e[l - 4];
+      }
+#pragma unroll
+  for (int lz = 1; lz < 4; ++lz)
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int l = 16 * lz + m;
+      e[l] = (uint32_t)lz < vz ? e[l] : e[l - 16];
+    }
+}
+
 // (the direct loads are only issued here: the caller waits, s_waitcnt 0,
 // before reading s_x, and may issue other loads first.  x is read from memory
 // once per launch, so its loads take the streaming (nt) policy, cache-policy
@@ -326,27 +387,21 @@ __device__ __forceinline__ void load_block_lds(const T* __restrict__ f, const Ge
   }
 }
 
-// one wave = 64 consecutive blocks = 4 chunks; `wave` numbers these groups
-// within the field.  s_x: 64 * 64 values of LDS owned by this wave.  kFull:
-// the caller guarantees that every block is full and rows are aligned (all
-// three dimensions multiples of 4), so the per-lane edge paths compile away
-// and their conditions hold no registers.
 // the candidate check of a codec-1 block: x~_i = x~_{i-1} + x_i row by row
 // in the field precision, each integer q = rint(e * inv_d) formed again and
 // turned into q * h_d as its row comes (so no array of integers or decoded
 // values is held across the check), the rows stored as they come (a
 // rejected candidate is overwritten later), and the largest |x - x~_i| in
 // double over the block's valid samples
-template <class T, bool kFull>
-__device__ __forceinline__ double check_rows_pq(const EncArgs<T>& a, const XLds<T>& XL, const T* tin,
-                                                const BlockPos& bq, bool wfull, uint64_t vmask,
-                                                const T e[64], double inv, double h) {
+template <class T>
+__device__ __forceinline__ double check_rows_pq(const XLds<T>& XL, const T* tin, T* tout, uint32_t lane,
+                                                uint64_t vmask, const T e[64], double inv, double h) {
   double ea = 0.0;
-  constexpr int RB = kFull ? 8 : 4;
+  constexpr int RB = 8;
 #pragma unroll
   for (int r0 = 0; r0 < 16; r0 += RB) {
     T tr[4 * RB];
-    load_rows<T, RB>(tin, a.g, bq, r0, wfull, tr);
+    tile_load_rows<T, RB>(tin, lane, r0, tr);
 #pragma unroll
     for (int k = 0; k < RB; ++k) {
       const int r = r0 + k;
@@ -358,12 +413,18 @@ __device__ __forceinline__ double check_rows_pq(const EncArgs<T>& a, const XLds<
         row[t] = tr[4 * k + t] + (T)((double)q * h);  // x~_{i-1} + x_i in the field precision
         ea = nmax(ea, masked_abs(vmask, l, (double)XL.at(l) - (double)row[t]));
       }
-      if (!a.last) store_row(a.xt_out, a.g, bq, r, row, wfull);
+      if (tout) tile_store_row(tout, lane, r, row);
     }
   }
   return ea;
 }
 
+// one wave = 64 consecutive blocks = 4 chunks; `wave` numbers these groups
+// within the field.  s_x: 64 * 64 values of LDS owned by this wave.  kFull:
+// the caller guarantees that every block is full and rows are aligned (all
+// three dimensions multiples of 4), so the per-lane edge paths of the x
+// loads and of the residual compile away and their conditions hold no
+// registers.  x~_{i-1} / x~_i are the wave's tiles (see tile_index).
 // kCodec: 0 the block-transform codec, 1 prediction and quantisation (its
 // residual block stays in registers for the candidates and the emission)
 template <class T, bool kFull = false, int kCodec = 0>
@@ -391,18 +452,22 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
   }
   // every lane has a full block of aligned rows: row accesses without per-lane paths
   const bool wfull = kFull || __all(bp.vx == 4 && bp.vy == 4 && bp.vz == 4 && a.g.rows_aligned);
+  // this wave's tiles of x~_{i-1} (none for the first component) and x~_i
+  // (none for the last)
+  const T* const tile_in = a.first ? nullptr : a.xt_in + (uint64_t)wave * kTileValues;
+  T* const tile_out = a.last ? nullptr : a.xt_out + (uint64_t)wave * kTileValues;
   // x into LDS and x~_{i-1} into registers, all loads in flight together
   load_block_lds(a.x, a.g, bp, s_x, lane, wfull);
   T e[64];
-  load_rows<T, 16>(a.first ? nullptr : a.xt_in, a.g, bp, 0, wfull, e);
+  tile_load_rows<T, 16>(tile_in, lane, 0, e);
   __builtin_amdgcn_s_waitcnt(0);  // direct loads, LDS writes and the rows complete
   const XLds<T> X{s_x, lane};
   // row addresses are recomputed where used instead of kept in registers
   bp = opaque_pos(bp);
   const uint64_t vmask = kFull ? ~0ull : valid_mask(bp);
 
-  // one pass over the rows: the residual e = x - x~_{i-1} (kept in registers
-  // for the transform) and its largest magnitude (the block exponent, the
+  // the residual e = x - x~_{i-1} (kept in registers), edge-replicated in a
+  // partial block, and its largest magnitude (the block exponent, the
   // all-zero test).  The first component, where x~_0 = 0 and the residual is
   // x itself, also gives the largest |x| (non-finite input; x is the same for
   // every component, and the host combines the components' flags).
@@ -411,14 +476,14 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
   int emax;
   {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
+    for (int l = 0; l < 64; ++l) e[l] = X.at(l) - e[l];
+    if constexpr (!kFull) {
+      if (!wfull) replicate_edges(e, bp.vx, bp.vy, bp.vz);
+    }
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int l = 4 * r + t;
-        e[l] = X.at(l) - e[l];
-        const U ab = abs_bits(e[l]);
-        maxabs = ab > maxabs ? ab : maxabs;
-      }
+    for (int l = 0; l < 64; ++l) {
+      const U ab = abs_bits(e[l]);
+      maxabs = ab > maxabs ? ab : maxabs;
     }
     if (a.first) xmax = maxabs;  // x - (+0) has the magnitude of x
     emax = block_emax<T>(maxabs);
@@ -453,8 +518,8 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
       // re-derived each iteration so the loads below are not hoisted out of
       // the loop into 64 registers
       const XLds<T> XL{opaque(s_x), lane};
-      const T* const tin = a.first ? nullptr : a.xt_in;
-      const BlockPos bq = kFull ? opaque_pos(bp) : opaque_ext(bp);  // row addresses are recomputed, not held
+      const T* const tin = tile_in;
+      const uint32_t ln = opaque(lane);  // tile addresses likewise
       bool feasible = false;
       uint32_t cb = 0;
       if constexpr (kCodec == 0) {
@@ -474,13 +539,12 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
           T dv[64];
           const T scale = dequantize_block(q, emax, dv);
           double ea = 0.0;
-          // rows of x~_{i-1} in flight together: eight in the full-field
-          // kernel (registers to spare), four where the edge paths need them
-          constexpr int RB = kFull ? 8 : 4;
+          // eight rows of x~_{i-1} in flight together
+          constexpr int RB = 8;
 #pragma unroll
           for (int r0 = 0; r0 < 16; r0 += RB) {
             T tr[4 * RB];
-            load_rows<T, RB>(tin, a.g, bq, r0, wfull, tr);
+            tile_load_rows<T, RB>(tin, ln, r0, tr);
 #pragma unroll
             for (int k = 0; k < RB; ++k) {
               const int r = r0 + k;
@@ -491,7 +555,7 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
                 row[t] = fma_exact(dv[l], scale, tr[4 * k + t]);  // x~_{i-1} + x_i in the field precision
                 ea = nmax(ea, masked_abs(vmask, l, (double)XL.at(l) - (double)row[t]));
               }
-              if (!a.last) store_row(a.xt_out, a.g, bq, r, row, wfull);
+              if (tile_out) tile_store_row(tile_out, ln, r, row);
             }
           }
           if (ea <= a.tau && ea <= eb) {
@@ -510,8 +574,8 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
           feasible = cb <= (uint32_t)FT<T>::RAW_BITS;
         }
         if (feasible) {
-          const double ea = check_rows_pq<T, kFull>(a, XL, tin, bq, wfull, vmask, e, __builtin_ldexp(a.inv0, delta),
-                                                    __builtin_ldexp(a.h0, -delta));
+          const double ea = check_rows_pq<T>(XL, tin, tile_out, ln, vmask, e, __builtin_ldexp(a.inv0, delta),
+                                             __builtin_ldexp(a.h0, -delta));
           if (ea <= a.tau && ea <= eb) {
             mode = MODE_CODED;
             nbits = cb;
@@ -541,7 +605,7 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
 #pragma unroll 1
     for (int r = 0; r < 16; ++r) {
       T tr[4], d[4];
-      load_rows<T, 1>(a.first ? nullptr : a.xt_in, a.g, bp, r, wfull, tr);
+      tile_load_rows<T, 1>(tile_in, lane, r, tr);
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int l = 4 * r + t;
@@ -549,21 +613,21 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
         d[t] = tr[t] + (xl - tr[t]);
         ea = nmax(ea, masked_abs(vmask, l, (double)xl - (double)d[t]));
       }
-      if (!a.last) store_row(a.xt_out, a.g, bp, r, d, wfull);
+      if (tile_out) tile_store_row(tile_out, lane, r, d);
     }
     err = ea;
     miss = !(ea <= a.tau && ea <= eb);
   } else if (active && mode == MODE_EMPTY) {
     miss = !(eb <= a.tau);
     // x~_i = x~_{i-1} + 0 (also over the rows of a rejected candidate)
-    if (!a.last) {
+    if (tile_out) {
 #pragma unroll 1
       for (int r = 0; r < 16; ++r) {
         T tr[4], d[4];
-        load_rows<T, 1>(a.first ? nullptr : a.xt_in, a.g, bp, r, wfull, tr);
+        tile_load_rows<T, 1>(tile_in, lane, r, tr);
 #pragma unroll
         for (int t = 0; t < 4; ++t) d[t] = tr[t] + (T)0;
-        store_row(a.xt_out, a.g, bp, r, d, wfull);
+        tile_store_row(tile_out, lane, r, d);
       }
     }
   }
@@ -630,11 +694,16 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
         w.put(3, 2);
 #pragma unroll 1
         for (int r = 0; r < 16; ++r) {
-          T xr[4], tr[4];
-          load_row(a.x, a.g, bp, r, xr);
-          load_row(a.first ? nullptr : a.xt_in, a.g, bp, r, tr);
+          T xr[4];
+          load_row(a.x, a.g, bp, r, xr);  // x of the sample the edge replication picks
+          const uint32_t ly = min<uint32_t>(r & 3, bp.vy - 1), lz = min<uint32_t>(r >> 2, bp.vz - 1);
 #pragma unroll
-          for (int t = 0; t < 4; ++t) w.put64((uint64_t)raw_bits_lo((T)(xr[t] - tr[t])), (uint32_t)P);
+          for (int t = 0; t < 4; ++t) {
+            // x~_{i-1} of the same sample, from the tile
+            const T tr = tile_in ? tile_in[tile_index<T>(lane, (int)(ly + 4 * lz), (int)min<uint32_t>(t, bp.vx - 1))]
+                                 : (T)0;
+            w.put64((uint64_t)raw_bits_lo((T)(xr[t] - tr)), (uint32_t)P);
+          }
         }
       } else if constexpr (kCodec == 0) {
         w.put(1, 2);  // nonempty, coded
