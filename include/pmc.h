@@ -43,7 +43,8 @@ typedef enum {
   PMC_E_CORRUPT = -4,     /* malformed stream */
   PMC_E_UNREACHABLE = -5, /* requested tolerance is below the last component's */
   PMC_E_BOUND = -6,       /* an Eq. (1) bound was missed (not expected; see the acceptance rule) */
-  PMC_E_DEVICE = -7       /* HIP runtime error */
+  PMC_E_DEVICE = -7,      /* HIP runtime error */
+  PMC_E_CANCELLED = -8    /* a served query was cancelled (pmc_server_cancel) */
 } pmc_status;
 
 typedef enum { PMC_F32 = 1, PMC_F64 = 2 } pmc_dtype;
@@ -291,6 +292,7 @@ typedef struct pmc_server pmc_server;
 typedef struct {
   uint64_t submitted, completed, hits, partial, misses, steps, batched_queries, max_queue;
   uint64_t cache_entries, cache_bytes, arena_peak, pending, running;
+  uint64_t cancelled;
 } pmc_server_stats;
 pmc_status pmc_server_create(pmc_ctx* ctx, size_t hbm_budget, void* d_arena, size_t arena_bytes, int max_batch,
                              pmc_server** out);
@@ -312,6 +314,15 @@ pmc_status pmc_server_poll(pmc_server* s, uint64_t ticket, int* done, pmc_status
  * 1 refined from a cached partial sum, 2 copied from the cache */
 pmc_status pmc_server_result(pmc_server* s, uint64_t ticket, const void** d_result, int* k, int* source);
 pmc_status pmc_server_release(pmc_server* s, uint64_t ticket);
+/* Cancels a query.  One still waiting is removed from the queue and never
+ * runs.  One already admitted to a running step finishes on the device, and
+ * its result slot is returned when that step ends (a caller's d_out may be
+ * written until then).  Either way pmc_server_poll then reports it done with
+ * status PMC_E_CANCELLED (for a running one: once its step has ended),
+ * pmc_server_result refuses it and pmc_server_release is a no-op.  PMC_OK,
+ * also for a query cancelled before; PMC_E_ARG for an unknown ticket or a
+ * query that has already finished (release it instead). */
+pmc_status pmc_server_cancel(pmc_server* s, uint64_t ticket);
 pmc_status pmc_server_get_stats(pmc_server* s, pmc_server_stats* out);
 /* finishes every submitted query, then stops the request loop */
 void pmc_server_destroy(pmc_server* s);

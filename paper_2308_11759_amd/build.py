@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpmc.so")
-SOURCES = ["kernels.hip", "capi.cpp", "batch.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "capi.cpp", "batch.cpp", "server.cpp", "format.cpp"]
 ARCH = os.environ.get("PMC_OFFLOAD_ARCH", "gfx950")
 
 

@@ -49,12 +49,8 @@ namespace pmc_host {
 
 pmc_status fail(pmc_ctx* ctx, pmc_status st, const char* fmt, ...);
 pmc_status hipfail(pmc_ctx* ctx, hipError_t e, const char* what);
-bool make_geo(const pmc_field* f, pmc::Geo* g);
 uint64_t elem_size(const pmc_field* f);
-uint64_t align256(uint64_t v);
-int floor_log2(double tau);
 uint64_t stream_cap_one(const pmc::Geo& g, int dtype);
-uint64_t aux_bytes(const pmc::Geo& g);
 // a store from per-component device results (offsets relative to d_base)
 pmc_store* store_from_meta(const pmc_field* f, const pmc::Geo& g, int n, const double* tau, const int* minexp,
                            const pmc::CompMeta* hm, const uint8_t* d_base, int codec);

@@ -4,27 +4,16 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "format.hpp"  // the block grid and the stream constants
+
 namespace pmc {
 
 constexpr int kMaxDecode = 16;  // components decoded by one k_decode launch
-constexpr int kMaxComps = 32;   // components per store
-constexpr uint64_t kStreamHeader = 64;
-constexpr uint32_t kStreamMagic = 0x31434D50u;  // "PMC1"
-constexpr uint32_t kStreamVersion = 1;
 
 enum : unsigned int {
   FLAG_NONFINITE = 1u,  // NaN / Inf in the input field
   FLAG_OVERFLOW = 2u,   // stream capacity exceeded
   FLAG_INDEX = 4u       // payload too large for 32-bit word offsets
-};
-
-// block grid of a field: 4x4x4 blocks, x fastest; chunks of 16 blocks
-struct Geo {
-  uint64_t nx, ny, nz;
-  uint64_t nbx, nby, nbz;
-  uint64_t nblocks, nchunks;
-  int rows_aligned;  // nx % 4 == 0: block rows can use 16-byte vector access
-  int pad;
 };
 
 // per-component results kept on the device during compression

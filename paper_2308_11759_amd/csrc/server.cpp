@@ -103,6 +103,7 @@ struct Query {
   clk::time_point arrival, done;
   uint64_t step = 0;
   int source = 0;       // 0 miss, 1 partial, 2 hit
+  bool cancel = false;  // cancelled while running: the result is dropped when its step ends
 };
 
 struct Step {
@@ -206,6 +207,12 @@ void retire(pmc_server* sv) {
       q.done = now;
       q.status = bad ? PMC_E_CORRUPT : PMC_OK;
       sv->stats.completed++;
+      if (q.cancel) {  // its step has ended: nothing reads or writes the slot any more
+        if (q.own_slot) sv->arena.release(q.slot_off, q.slot_bytes);
+        q.own_slot = false;
+        q.status = PMC_E_CANCELLED;
+        q.state = Q_RELEASED;
+      }
     }
     sv->outputs_inflight -= st.budget_bytes;
     sv->slot_busy[st.table_slot] = false;
@@ -497,11 +504,36 @@ pmc_status pmc_server_result(pmc_server* sv, uint64_t ticket, const void** d_res
   return PMC_OK;
 }
 
+pmc_status pmc_server_cancel(pmc_server* sv, uint64_t ticket) {
+  if (!sv) return PMC_E_ARG;
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (ticket >= sv->queries.size()) return PMC_E_ARG;
+  Query& q = sv->queries[ticket];
+  if (q.state == Q_PENDING) {
+    // not admitted yet: it holds no memory and no step refers to it
+    const auto it = std::find(sv->pending.begin(), sv->pending.end(), ticket);
+    if (it != sv->pending.end()) sv->pending.erase(it);
+    q.state = Q_RELEASED;
+    q.status = PMC_E_CANCELLED;
+    q.done = clk::now();
+    sv->stats.cancelled++;
+    return PMC_OK;
+  }
+  if (q.state == Q_RUNNING) {
+    if (!q.cancel) sv->stats.cancelled++;
+    q.cancel = true;
+    return PMC_OK;
+  }
+  if (q.status == PMC_E_CANCELLED) return PMC_OK;  // cancelled before
+  return fail(sv->ctx, PMC_E_ARG, "the query has finished: release it instead");
+}
+
 pmc_status pmc_server_release(pmc_server* sv, uint64_t ticket) {
   if (!sv) return PMC_E_ARG;
   std::lock_guard<std::mutex> lk(sv->mu);
   if (ticket >= sv->queries.size()) return PMC_E_ARG;
   Query& q = sv->queries[ticket];
+  if (q.state == Q_RELEASED && q.status == PMC_E_CANCELLED) return PMC_OK;  // nothing left to release
   if (q.state != Q_DONE) return PMC_E_ARG;
   if (q.own_slot) sv->arena.release(q.slot_off, q.slot_bytes);
   q.own_slot = false;

@@ -18,11 +18,12 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpmc.so")
 
 OK, E_ARG, E_NONFINITE, E_NOMEM, E_CORRUPT, E_UNREACHABLE, E_BOUND, E_DEVICE = 0, -1, -2, -3, -4, -5, -6, -7
+E_CANCELLED = -8
 F32, F64 = 1, 2
 OPT_FUSED_DECODE, OPT_SYNC_CHECK, OPT_PROFILE, OPT_CODEC = 1, 2, 3, 4
 CODEC_TRANSFORM, CODEC_PREDICTION = 0, 1
 _NAMES = {0: "OK", -1: "E_ARG", -2: "E_NONFINITE", -3: "E_NOMEM", -4: "E_CORRUPT", -5: "E_UNREACHABLE",
-          -6: "E_BOUND", -7: "E_DEVICE"}
+          -6: "E_BOUND", -7: "E_DEVICE", -8: "E_CANCELLED"}
 
 
 class PmcError(RuntimeError):
@@ -43,7 +44,7 @@ class ProfEntry(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in ("submitted", "completed", "hits", "partial", "misses", "steps",
                                                 "batched_queries", "max_queue", "cache_entries", "cache_bytes",
-                                                "arena_peak", "pending", "running")]
+                                                "arena_peak", "pending", "running", "cancelled")]
 
 
 _lib = None
@@ -96,6 +97,7 @@ SIGNATURES = {
     "pmc_server_poll": (_int, [_vp, _u64, _P(_int), _P(_int), _P(_dbl)]),
     "pmc_server_result": (_int, [_vp, _u64, _P(_vp), _P(_int), _P(_int)]),
     "pmc_server_release": (_int, [_vp, _u64]),
+    "pmc_server_cancel": (_int, [_vp, _u64]),
     "pmc_server_get_stats": (_int, [_vp, _P(ServerStats)]),
     "pmc_server_destroy": (None, [_vp]),
 }
@@ -484,6 +486,13 @@ class Server:
     def release(self, ticket):
         self.ctx._check(self.lib.pmc_server_release(self.handle, int(ticket)))
         self._outs.pop(int(ticket), None)
+
+    def cancel(self, ticket):
+        """Cancel a query: a waiting one never runs; a running one finishes on
+        the device and its result is dropped when its step ends.  poll() then
+        reports it done with status E_CANCELLED (the caller's `out` stays
+        referenced until then)."""
+        self.ctx._check(self.lib.pmc_server_cancel(self.handle, int(ticket)))
 
     def stats(self):
         s = ServerStats()

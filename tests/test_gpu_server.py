@@ -133,6 +133,55 @@ def test_caller_outputs_and_unreachable(served):
     srv.close()
 
 
+def test_cancellation(served):
+    """Cancelled queries: one still waiting never runs, one already running
+    is dropped when its step ends; both report E_CANCELLED, refuse result()
+    and take release() as a no-op, and every query around them still equals
+    the oracle's x~_k."""
+    from paper_2308_11759_amd import pmc
+    ctx, xs, stores, taus, refs = served
+    srv = pmc.Server(ctx, arena_bytes=256 << 20, max_batch=1)  # one query per step: most are waiting
+    fids = [srv.add(s) for s in stores]
+    tickets = []
+    for q in range(60):
+        f = q % len(fids)
+        k = 1 + (q * 5) % 6
+        tickets.append((srv.submit(fids[f], taus[f][k - 1]), f, k))
+    cancelled = set()
+    for i, (t, f, k) in enumerate(tickets):
+        if i % 2 == 1:
+            try:
+                srv.cancel(t)
+                cancelled.add(t)
+            except pmc.PmcError as e:
+                assert e.status == pmc.E_ARG  # it had finished already
+    wait_all(srv, [t for t, _, _ in tickets])
+    for t, f, k in tickets:
+        done, st, lat = srv.poll(t)
+        assert done
+        if t in cancelled:
+            assert st == pmc.E_CANCELLED
+            with pytest.raises(pmc.PmcError) as ei:
+                srv.result(t, f)
+            assert ei.value.status == pmc.E_ARG
+            srv.release(t)  # nothing left to release
+            srv.cancel(t)   # cancelling again is accepted
+        else:
+            assert st == pmc.OK
+            view, kk, src = srv.result(t, f)
+            assert kk == k
+            assert np.array_equal(view.cpu().numpy(), refs[f][k - 1]), (t, f, k, src)
+            srv.release(t)
+            with pytest.raises(pmc.PmcError) as ei:
+                srv.cancel(t)  # finished: release, not cancel
+            assert ei.value.status == pmc.E_ARG
+    s = srv.stats()
+    say("server stats with cancellations: %s" % s)
+    assert s["cancelled"] == len(cancelled) > 0
+    assert s["pending"] == 0 and s["running"] == 0
+    srv.close()
+
+
 def test_queries_with_wide_spans(served):
     """Queries whose streams exceed the decoder's LDS staging span (white
     noise to 2^-28) run the global-reader kernel, alone and mixed with
