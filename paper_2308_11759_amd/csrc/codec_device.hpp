@@ -443,14 +443,21 @@ struct LBits {
   __device__ __forceinline__ bool bad() const { return (uint64_t)p * 32 + o > (uint64_t)end * 32; }
 };
 
-// prefix parity: bit j of the result is the XOR of bits 0..j of s
-__device__ __forceinline__ uint32_t prefix_xor(uint32_t s) {
-  s ^= s << 1;
-  s ^= s << 2;
-  s ^= s << 4;
-  s ^= s << 8;
-  s ^= s << 16;
-  return s;
+// The run terminators of a group-test section that starts with a positive
+// test at bit 0: the ones with an even number of ones at or below them.
+// Inside a section a test is always followed by its
+// run and terminator, and a terminator by the next test, so apart from bit 0
+// every maximal run of ones starts with a terminator and alternates
+// terminator, test, ...: the terminators are the bits at even offsets from
+// their run's first bit.  Runs that start at an even position are found by
+// adding their first bits (the carry clears the run); the rest start at odd
+// positions.  Past the section's end (garbage bits of what follows) the two
+// forms may differ; the plane reader never takes a terminator from there.
+__device__ __forceinline__ uint32_t terminators(uint32_t s) {
+  const uint32_t x = s & ~1u;
+  const uint32_t first = x & ~(x << 1);                        // first bit of each run
+  const uint32_t even = ((x + (first & 0x55555555u)) ^ x) & x;  // runs starting at even positions
+  return x & (even ^ 0xAAAAAAAAu);                             // even offsets within each run
 }
 
 // squeeze: every set bit of m, at position t and i-th from the bottom
@@ -499,7 +506,7 @@ __device__ __forceinline__ uint64_t plane_read(R& r, uint32_t& n, const uint8_t*
   while (n < 64) {
     const uint32_t s = (r.peek32() << vg) | vg;
     const bool neg = (s & 1u) == 0u;  // negative first test: the plane ends here
-    const uint32_t term = s & ~prefix_xor(s);
+    const uint32_t term = terminators(s);
     const uint32_t ends = term & ~(s >> 1) & 0x7FFFFFFFu;
     const uint32_t last = (uint32_t)__builtin_ctz(ends | 0x80000000u);
     const uint32_t tm = neg ? 0u : term & ((2u << last) - 1u);
@@ -730,79 +737,128 @@ __device__ __forceinline__ void planes_emit(LdsBits& w, const typename FT<T>::U 
   }
 }
 
-// read p planes from the top and return the coefficients in coded order as
-// two's complement integers (negabinary decoded; planes below p are zero).
-// rel selects which 16 planes go through the register transpose: the block's
-// top 16 (rel = false), or the 16 from its first non-empty plane (rel =
-// true).  The loop over the 16 plane slots is unrolled, so a wave runs each
-// slot's group-test windows for as long as its slowest lane; in residual
-// components, whose blocks are noise-like, the planes where most coefficients
-// become significant follow the first non-empty one, and counting slots from
-// there lines them up across the wave's blocks.
-template <class T, class R>
-__device__ __forceinline__ void planes_read(R& r, typename FT<T>::S c[64], int p, const uint8_t* sq, bool rel) {
+// Transpose of the plane words of W slots (W = 4, 8 or 16) into W-bit
+// slices, one per coefficient.  In: A[W-1-t'] holds slot t' of coefficients
+// 0..31 (bit j: coefficient j), A[2W-1-t'] of coefficients 32..63.  Out: in
+// word i of each half, the W-bit group g is the slice of coefficient W g + i
+// of that half, slot t' at bit W-1-t'.  Each half is a row of independent
+// W x W bit-matrix transposes, one per group, done by the recursive swap of
+// off-diagonal blocks (strides W/2, ..., 1): stage J swaps, in each word pair
+// (k, k+J) with bit J of k clear, the bits of a selected by M << J with the
+// bits of b selected by M (M: the low J bits of every 2J-bit field).  The
+// byte stage is one v_perm per word; the others exchange the masked bits
+// through one xor-difference.
+template <int J, uint32_t M, int N> __device__ __forceinline__ void gstage(uint32_t A[N]) {
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    if (k & J) continue;
+    const uint32_t a = A[k], b = A[k + J];
+    if constexpr (J == 8) {
+      A[k] = __builtin_amdgcn_perm(b, a, 0x06020400u);      // a0 b0 a2 b2
+      A[k + J] = __builtin_amdgcn_perm(b, a, 0x07030501u);  // a1 b1 a3 b3
+    } else {
+      const uint32_t t = ((a >> J) ^ b) & M;
+      A[k + J] = b ^ t;
+      A[k] = a ^ (t << J);
+    }
+  }
+}
+template <int W> __device__ __forceinline__ void transpose_groups(uint32_t A[2 * W]) {
+  if constexpr (W >= 16) gstage<8, 0x00FF00FFu, 2 * W>(A);
+  if constexpr (W >= 8) gstage<4, 0x0F0F0F0Fu, 2 * W>(A);
+  gstage<2, 0x33333333u, 2 * W>(A);
+  gstage<1, 0x55555555u, 2 * W>(A);
+}
+
+// planes [zlead, p) of one block through W slots (slot t' = plane base + t'),
+// into coded-order two's complement integers; planes at or beyond base + W
+// only exist for W = 16 and are added one at a time.
+template <class T, int W, class R>
+__device__ __forceinline__ void planes_slots(R& r, typename FT<T>::S c[64], int p, int zlead, const uint8_t* sq,
+                                             bool rel) {
   typedef typename FT<T>::U U;
   typedef typename FT<T>::S S;
   constexpr int P = FT<T>::P;
   uint32_t n = 0;
+  // Which planes share a slot across the wave matters: a slot costs the wave
+  // as many group-test windows as its slowest lane needs.  Residual
+  // components are noise-like, and the planes where most coefficients become
+  // significant follow each block's first non-empty plane, so slots count
+  // from that plane.  In a store's first component those planes lie at a
+  // similar absolute bit level in every block (the data's fine-scale
+  // content), i.e. at a fixed distance above the last coded plane, so slots
+  // count back from the last plane (base may be negative: leading slots then
+  // hold no plane).  Planes above base are empty in either case (base <=
+  // zlead).
+  const int base = rel ? (zlead < P - W ? zlead : P - W) : (p - W < zlead ? p - W : zlead);
+  uint32_t A[2 * W];
+#pragma unroll
+  for (int tp = 0; tp < W; ++tp) {
+    const int t = base + tp;
+    uint64_t wd = 0;
+    if (t >= zlead && t < p) wd = plane_read(r, n, sq);
+    A[W - 1 - tp] = (uint32_t)wd;
+    A[2 * W - 1 - tp] = (uint32_t)(wd >> 32);
+  }
+  transpose_groups<W>(A);
+  // A slice X stands for the coefficient X << sh (sh = P - W - base; the
+  // planes above are empty), whose value is ((X ^ M) - M) << sh with M the
+  // negabinary mask's bits at the slice's positions (1010... for even sh,
+  // 0101... for odd): the mask's lower bits cancel.  One xor serves a whole
+  // word of slices.  With base < 0 the slice's top -base bits are zero digits
+  // and sh + W - 1 >= P: what the shift drops is the mask alone, dropped from
+  // the offset alike (all modulo 2^P).
+  const int sh = P - W - base;
+  const uint32_t MM = (sh & 1) ? 0x55555555u : 0xAAAAAAAAu;
+  constexpr uint32_t kSlice = (1u << W) - 1u;
+  // -(M << sh), modulo 2^P, kept opaque so that each coefficient is one
+  // shift-and-add of its slice rather than a shift and a subtraction
+  const U off = opaque((U)0 - ((U)(MM & kSlice) << sh));
+#pragma unroll
+  for (int i = 0; i < W; ++i) {
+    const uint32_t xl = A[i] ^ MM, xh = A[W + i] ^ MM;
+#pragma unroll
+    for (int g = 0; g < 32 / W; ++g) {
+      c[W * g + i] = (S)(((U)((xl >> (W * g)) & kSlice) << sh) + off);
+      c[32 + W * g + i] = (S)(((U)((xh >> (W * g)) & kSlice) << sh) + off);
+    }
+  }
+  if constexpr (W == 16) {
+    // deeper planes (rare): a plane bit at an even position b adds 2^b to the
+    // two's complement value, one at an odd position subtracts it (the
+    // negabinary weight of bit b is (-2)^b)
+    for (int t = base + 16 > zlead ? base + 16 : zlead; t < p; ++t) {
+      const uint64_t wd = plane_read(r, n, sq);
+      const uint32_t lo = (uint32_t)wd, hi = (uint32_t)(wd >> 32);
+      const int b = P - 1 - t;
+      const U m = (b & 1) ? ~(U)0 : (U)0;  // negate odd positions: (v ^ m) - m
+#pragma unroll
+      for (int j = 0; j < 32; ++j) {
+        c[j] = (S)((U)c[j] + ((((U)((lo >> j) & 1u) << b) ^ m) - m));
+        c[j + 32] = (S)((U)c[j + 32] + ((((U)((hi >> j) & 1u) << b) ^ m) - m));
+      }
+    }
+  }
+}
+
+// read p planes from the top and return the coefficients in coded order as
+// two's complement integers (negabinary decoded; planes below p are zero).
+// The planes go through W register slots and one W x W bit transpose per
+// group of W coefficients; W is the smallest of 4, 8 and 16 that holds every
+// active lane's coded planes (a wave-uniform choice: residual components
+// typically code 3 to 5 planes per block, a store's first one about 10).
+template <class T, class R>
+__device__ __forceinline__ void planes_read(R& r, typename FT<T>::S c[64], int p, const uint8_t* sq, bool rel) {
   // Leading empty planes: until a coefficient is significant, a plane
   // without a new one is a single 0 (its negative group test), so the first
   // zeros of the block's plane data are that many empty planes, skipped at once.
   const int z0 = (int)__builtin_ctz(r.peek32() | 0x80000000u);
   const int zlead = z0 < p ? z0 : p;
   r.skip((uint32_t)zlead);
-  // slot t' holds plane base + t'.  Which planes share a slot across the
-  // wave matters: a slot costs the wave as many group-test windows as its
-  // slowest lane needs.  Residual components are noise-like, and the planes
-  // where most coefficients become significant follow each block's first
-  // non-empty plane, so slots count from that plane.  In a store's first
-  // component those planes lie at a similar absolute bit level in every block
-  // (the data's fine-scale content), i.e. at a fixed distance above the last
-  // coded plane, so slots count back from the last plane (base may be
-  // negative: leading slots then hold no plane).  Planes above base are empty
-  // in either case (base <= zlead).
-  const int base = rel ? (zlead < P - 16 ? zlead : P - 16) : (p - 16 < zlead ? p - 16 : zlead);
-  uint32_t Tw[32];
-#pragma unroll
-  for (int tp = 0; tp < 16; ++tp) {
-    const int t = base + tp;
-    uint64_t wd = 0;
-    if (t >= zlead && t < p) wd = plane_read(r, n, sq);
-    Tw[15 - tp] = (uint32_t)wd;
-    Tw[31 - tp] = (uint32_t)(wd >> 32);
-  }
-  transpose32(Tw);  // back to 16-bit slices of coefficients j and j+32
-  // A slice X stands for the coefficient X << sh (sh = P - 16 - base; the
-  // planes above are empty), whose value is ((X ^ M) - M) << sh with M the
-  // negabinary mask's bits at the slice's positions (0xAAAA for even sh,
-  // 0x5555 for odd): the mask's lower bits cancel.  One xor serves both
-  // slices of a word.  With base < 0 the slice's top -base bits are zero
-  // digits and sh + 15 >= P: what the shift drops is the mask alone, dropped
-  // from the offset alike (all modulo 2^P).
-  const int sh = P - 16 - base;
-  const uint32_t M = (sh & 1) ? 0x5555u : 0xAAAAu;
-  const uint32_t MM = M | (M << 16);
-  const U off = (U)0 - ((U)M << sh);  // -(M << sh), modulo 2^P
-#pragma unroll
-  for (int j = 0; j < 32; ++j) {
-    const uint32_t x = Tw[j] ^ MM;
-    c[j] = (S)(((U)(x & 0xFFFFu) << sh) + off);
-    c[j + 32] = (S)(((U)(x >> 16) << sh) + off);
-  }
-  // deeper planes (rare): a plane bit at an even position b adds 2^b to the
-  // two's complement value, one at an odd position subtracts it (the
-  // negabinary weight of bit b is (-2)^b)
-  for (int t = base + 16 > zlead ? base + 16 : zlead; t < p; ++t) {
-    const uint64_t wd = plane_read(r, n, sq);
-    const uint32_t lo = (uint32_t)wd, hi = (uint32_t)(wd >> 32);
-    const int b = P - 1 - t;
-    const U m = (b & 1) ? ~(U)0 : (U)0;  // negate odd positions: (v ^ m) - m
-#pragma unroll
-    for (int j = 0; j < 32; ++j) {
-      c[j] = (S)((U)c[j] + ((((U)((lo >> j) & 1u) << b) ^ m) - m));
-      c[j + 32] = (S)((U)c[j + 32] + ((((U)((hi >> j) & 1u) << b) ^ m) - m));
-    }
-  }
+  const int np = p - zlead;
+  if (__all(np <= 4)) planes_slots<T, 4>(r, c, p, zlead, sq, rel);
+  else if (__all(np <= 8)) planes_slots<T, 8>(r, c, p, zlead, sq, rel);
+  else planes_slots<T, 16>(r, c, p, zlead, sq, rel);
 }
 
 // advance a reader over one block without reconstructing it; returns false
