@@ -513,10 +513,13 @@ __device__ __forceinline__ uint64_t plane_read(R& r, uint32_t& n, const uint8_t*
     // terminators whose coefficient stays below 63; one beyond marks a run
     // that reaches coefficient 63 instead
     const uint32_t rel = squeeze32(tm, sq);
-    const uint32_t room = 63u - n;  // coefficients n..62 may carry a terminator
-    const uint32_t vrel = room >= 32u ? rel : rel & ((1u << room) - 1u);
+    // coefficients n..62 may carry a terminator; rel < 2^31 (a squeezed bit
+    // moves down at least one place), so 31 low bits cover room >= 31
+    const uint32_t room = 63u - n;
+    const uint32_t vrel = __builtin_amdgcn_ubfe(rel, 0u, room < 31u ? room : 31u);
     const bool tokens = vrel == rel && tm != 0u;
-    const uint32_t nn = vrel != 0u ? 32u - (uint32_t)__builtin_clz(vrel) : 0u;
+    // bit length of vrel (0 for 0): vrel < 2^31, so (vrel << 1) | 1 is nonzero
+    const uint32_t nn = 31u - (uint32_t)__builtin_clz((vrel << 1) | 1u);
     const uint32_t g = nn + (uint32_t)__builtin_popcount(vrel);  // the bit after the last one taken
     wd |= (uint64_t)vrel << n;
     n += nn;
