@@ -774,15 +774,12 @@ template <int W> __device__ __forceinline__ void transpose_groups(uint32_t A[2 *
 }
 
 // planes [zlead, p) of one block through W slots (slot t' = plane base + t'),
-// into coded-order two's complement integers; planes at or beyond base + W
-// only exist for W = 16 and are added one at a time.
+// transposed into W-bit slices (transpose_groups); returns base.
 template <class T, int W, class R>
-__device__ __forceinline__ void planes_slots(R& r, typename FT<T>::S c[64], int p, int zlead, const uint8_t* sq,
-                                             bool rel) {
-  typedef typename FT<T>::U U;
-  typedef typename FT<T>::S S;
+__device__ __forceinline__ int read_slots(R& r, uint32_t A[2 * W], int p, int zlead, const uint8_t* sq, bool rel,
+                                          uint32_t& n) {
   constexpr int P = FT<T>::P;
-  uint32_t n = 0;
+  n = 0;
   // Which planes share a slot across the wave matters: a slot costs the wave
   // as many group-test windows as its slowest lane needs.  Residual
   // components are noise-like, and the planes where most coefficients become
@@ -794,7 +791,6 @@ __device__ __forceinline__ void planes_slots(R& r, typename FT<T>::S c[64], int 
   // hold no plane).  Planes above base are empty in either case (base <=
   // zlead).
   const int base = rel ? (zlead < P - W ? zlead : P - W) : (p - W < zlead ? p - W : zlead);
-  uint32_t A[2 * W];
 #pragma unroll
   for (int tp = 0; tp < W; ++tp) {
     const int t = base + tp;
@@ -804,6 +800,19 @@ __device__ __forceinline__ void planes_slots(R& r, typename FT<T>::S c[64], int 
     A[2 * W - 1 - tp] = (uint32_t)(wd >> 32);
   }
   transpose_groups<W>(A);
+  return base;
+}
+
+// the coded planes into coded-order two's complement integers; planes at or
+// beyond base + W only exist for W = 16 and are added one at a time.
+template <class T, int W, class R>
+__device__ __forceinline__ void planes_slots(R& r, typename FT<T>::S c[64], int p, int zlead, const uint8_t* sq,
+                                             bool rel) {
+  typedef typename FT<T>::U U;
+  typedef typename FT<T>::S S;
+  constexpr int P = FT<T>::P;
+  uint32_t A[2 * W], n;
+  const int base = read_slots<T, W>(r, A, p, zlead, sq, rel, n);
   // A slice X stands for the coefficient X << sh (sh = P - W - base; the
   // planes above are empty), whose value is ((X ^ M) - M) << sh with M the
   // negabinary mask's bits at the slice's positions (1010... for even sh,
@@ -844,24 +853,84 @@ __device__ __forceinline__ void planes_slots(R& r, typename FT<T>::S c[64], int 
   }
 }
 
-// read p planes from the top and return the coefficients in coded order as
-// two's complement integers (negabinary decoded; planes below p are zero).
-// The planes go through W register slots and one W x W bit transpose per
-// group of W coefficients; W is the smallest of 4, 8 and 16 that holds every
-// active lane's coded planes (a wave-uniform choice: residual components
-// typically code 3 to 5 planes per block, a store's first one about 10).
+// read planes [zlead, p) (the leading empty planes already skipped) and
+// return the coefficients in coded order as two's complement integers
+// (negabinary decoded; planes below p are zero).  The planes go through W
+// register slots and one W x W bit transpose per group of W coefficients; W
+// is the smallest of 4, 8 and 16 that holds every active lane's coded planes
+// (a wave-uniform choice: residual components typically code 3 to 5 planes
+// per block, a store's first one about 10).
 template <class T, class R>
-__device__ __forceinline__ void planes_read(R& r, typename FT<T>::S c[64], int p, const uint8_t* sq, bool rel) {
-  // Leading empty planes: until a coefficient is significant, a plane
-  // without a new one is a single 0 (its negative group test), so the first
-  // zeros of the block's plane data are that many empty planes, skipped at once.
-  const int z0 = (int)__builtin_ctz(r.peek32() | 0x80000000u);
-  const int zlead = z0 < p ? z0 : p;
-  r.skip((uint32_t)zlead);
+__device__ __forceinline__ void planes_read(R& r, typename FT<T>::S c[64], int p, int zlead, const uint8_t* sq,
+                                            bool rel) {
   const int np = p - zlead;
   if (__all(np <= 4)) planes_slots<T, 4>(r, c, p, zlead, sq, rel);
   else if (__all(np <= 8)) planes_slots<T, 8>(r, c, p, zlead, sq, rel);
   else planes_slots<T, 16>(r, c, p, zlead, sq, rel);
+}
+
+// The float64 high-word route: a block whose coded planes all lie in the top
+// 26 bit positions (p <= 26) has coefficients that are multiples of 2^38.
+// Every word the inverse lifting then forms is a multiple of 2^32: sums,
+// differences and doublings of such words act on their high 32-bit words
+// modulo 2^32 exactly as on the words modulo 2^64, and each halving meets an
+// even high word (the inputs are multiples of 2^32 * 2^6 and a value passes
+// at most six halvings, two per pass), so the word's arithmetic shift is its
+// high word's.  The lifting therefore runs on the high words alone, in 32-bit
+// integers (half the registers and operations), giving the same words
+// q = h * 2^32.
+// The high word of a coefficient is (X << (sh - 32)) - (M << (sh - 32))
+// modulo 2^32 (sh >= 38 here); deeper planes add their digits' weights to
+// it.  Then q * 2^(emax-62) = h * 2^(emax-30), computed exactly by a
+// conversion and a power-of-two scale while the result is normal (the caller
+// checks emax >= -992), which is the value dequantize() gives.
+template <int W, class R>
+__device__ __forceinline__ void decode_hi32(R& r, int p, int zlead, int emax, double acc[64], const uint8_t* sq,
+                                            bool rel) {
+  uint32_t A[2 * W], n;
+  const int base = read_slots<double, W>(r, A, p, zlead, sq, rel, n);
+  const int sh32 = 32 - W - base;  // sh - 32
+  const uint32_t MM = (sh32 & 1) ? 0x55555555u : 0xAAAAAAAAu;
+  constexpr uint32_t kSlice = (1u << W) - 1u;
+  const uint32_t off = opaque(0u - ((MM & kSlice) << sh32));
+  int32_t c[64];
+#pragma unroll
+  for (int i = 0; i < W; ++i) {
+    const uint32_t xl = A[i] ^ MM, xh = A[W + i] ^ MM;
+#pragma unroll
+    for (int g = 0; g < 32 / W; ++g) {
+      c[W * g + i] = (int32_t)((((xl >> (W * g)) & kSlice) << sh32) + off);
+      c[32 + W * g + i] = (int32_t)((((xh >> (W * g)) & kSlice) << sh32) + off);
+    }
+  }
+  if constexpr (W == 16) {
+    // deeper planes: digit weights (-2)^b at b = 63 - t >= 38, in the high word
+    for (int t = base + 16 > zlead ? base + 16 : zlead; t < p; ++t) {
+      const uint64_t wd = plane_read(r, n, sq);
+      const uint32_t lo = (uint32_t)wd, hi = (uint32_t)(wd >> 32);
+      const int b = 31 - t;  // (63 - t) - 32
+      const uint32_t m = (b & 1) ? ~0u : 0u;
+#pragma unroll
+      for (int j = 0; j < 32; ++j) {
+        c[j] = (int32_t)((uint32_t)c[j] + ((((lo >> j) & 1u) << b ^ m) - m));
+        c[j + 32] = (int32_t)((uint32_t)c[j + 32] + ((((hi >> j) & 1u) << b ^ m) - m));
+      }
+    }
+  }
+  int32_t q[64];
+#pragma unroll
+  for (int r2 = 0; r2 < 64; ++r2) q[kOrder.at[r2]] = c[r2];
+#pragma unroll
+  for (int l = 0; l < 16; ++l) lift_inv(q[l], q[l + 16], q[l + 32], q[l + 48]);
+#pragma unroll
+  for (int l = 0; l < 16; ++l) {
+    const int b = 16 * (l >> 2) + (l & 3);
+    lift_inv(q[b], q[b + 4], q[b + 8], q[b + 12]);
+  }
+#pragma unroll
+  for (int r2 = 0; r2 < 16; ++r2) lift_inv(q[4 * r2], q[4 * r2 + 1], q[4 * r2 + 2], q[4 * r2 + 3]);
+#pragma unroll
+  for (int l = 0; l < 64; ++l) acc[l] = acc[l] + __builtin_ldexp((double)q[l], emax - 30);
 }
 
 // advance a reader over one block without reconstructing it; returns false

@@ -944,8 +944,26 @@ __device__ __forceinline__ bool decode_block_add(R& r, int minexp, T acc[64], co
   int p = emax - minexp + kGuard;
   p = (p < 0 ? 0 : (p > P ? P : p)) + delta;
   if (emax < 2 - FT<T>::BIAS || p < 1 || p > P) return false;
+  // Leading empty planes: until a coefficient is significant, a plane
+  // without a new one is a single 0 (its negative group test), so the first
+  // zeros of the block's plane data are that many empty planes, skipped at once.
+  const int z0 = (int)__builtin_ctz(r.peek32() | 0x80000000u);
+  const int zlead = z0 < p ? z0 : p;
+  r.skip((uint32_t)zlead);
+  if constexpr (sizeof(T) == 8) {
+    // every coded plane in the top 26 bit positions and every result
+    // normal: the lifting on the coefficients' high words (a wave-uniform
+    // choice; both routes give the same sums)
+    if (__all(p <= 26 && emax >= -992)) {
+      const int np = p - zlead;
+      if (__all(np <= 4)) decode_hi32<4>(r, p, zlead, emax, acc, sq, rel);
+      else if (__all(np <= 8)) decode_hi32<8>(r, p, zlead, emax, acc, sq, rel);
+      else decode_hi32<16>(r, p, zlead, emax, acc, sq, rel);
+      return true;
+    }
+  }
   typename FT<T>::S c[64], q[64];
-  planes_read<T>(r, c, p, sq, rel);
+  planes_read<T>(r, c, p, zlead, sq, rel);
   inverse_zy_ints<T>(c, q);
   inverse_x<T>(q);
   dequant_add(q, emax, acc);
