@@ -196,6 +196,15 @@ pmc_status pmc_store_counts(const pmc_store* s, int i, uint64_t counts[5]);
  * spans, e.g. streams of mostly raw blocks, are read from device memory).
  * Either pointer may be NULL.  PMC_E_ARG on a bad index. */
 pmc_status pmc_store_span(const pmc_store* s, int i, uint64_t* max_span_words, int* staged);
+/* Decode route of component i (0-based): *high_half = 1 when the store is
+ * float32 with the block-transform codec and every coded block of the
+ * component codes its planes in the top ten bit positions of a coefficient
+ * with an exponent inside float32's fast dequantisation.  Retrievals whose
+ * residual components (index > 0) all qualify run those components' inverse
+ * transforms on the coefficients' high 16-bit halves, two per register (the
+ * same results).  Found by the encoder, and again from the payload when a
+ * store is deserialised.  PMC_E_ARG on a bad index or a NULL pointer. */
+pmc_status pmc_store_decode_route(const pmc_store* s, int i, int* high_half);
 /* Field of a store. */
 pmc_status pmc_store_field(const pmc_store* s, pmc_field* f);
 /* Device address and byte size of component i's stream (0-based). */
@@ -234,10 +243,11 @@ pmc_status pmc_store_serialize(pmc_ctx* ctx, const pmc_store* s, void* host_buf,
  * d_streams (capacity cap, caller-owned).  pmc_store_device_bytes validates
  * the blob on the host (sizes with checked arithmetic, every stream header
  * and chunk index; PMC_E_CORRUPT otherwise) and reports the device bytes a
- * store needs: the per-block indexes, the streams and a 256-byte status word.
- * pmc_store_deserialize validates the same way, uploads, rebuilds the
- * per-block indexes on the device and synchronises; a payload that does not
- * parse gives PMC_E_CORRUPT and no store. */
+ * store needs: the per-block indexes, the streams and a 512-byte trailer (a
+ * status word and per-component flags).  pmc_store_deserialize validates the
+ * same way, uploads, rebuilds the per-block indexes on the device (finding
+ * each component's decode route, pmc_store_decode_route) and synchronises; a
+ * payload that does not parse gives PMC_E_CORRUPT and no store. */
 pmc_status pmc_store_device_bytes(const void* host_buf, size_t size, size_t* need);
 pmc_status pmc_store_deserialize(pmc_ctx* ctx, const void* host_buf, size_t size, void* d_streams, size_t cap,
                                  pmc_store** out);

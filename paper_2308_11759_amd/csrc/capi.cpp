@@ -98,6 +98,7 @@ pmc_store* store_from_meta(const pmc_field* f, const Geo& g, int n, const double
     s->nesc.push_back(hm[i].nesc);
     s->nmiss.push_back(hm[i].nmiss);
     s->max_span.push_back(hm[i].max_span);
+    s->full.push_back(hm[i].full);
   }
   return s;
 }
@@ -557,6 +558,12 @@ pmc_status pmc_store_span(const pmc_store* s, int i, uint64_t* max_span_words, i
   return PMC_OK;
 }
 
+pmc_status pmc_store_decode_route(const pmc_store* s, int i, int* high_half) {
+  if (!s || !high_half || i < 0 || i >= s->n) return PMC_E_ARG;
+  *high_half = s->f.dtype == PMC_F32 && s->codec == 0 && s->full[i] == 0 ? 1 : 0;
+  return PMC_OK;
+}
+
 pmc_status pmc_store_field(const pmc_store* s, pmc_field* f) {
   if (!s || !f) return PMC_E_ARG;
   *f = s->f;
@@ -598,7 +605,11 @@ static pmc_status decode_range(pmc_ctx* ctx, const pmc_store* s, int k0, int k1,
   for (int i0 = k0; i0 < k1; i0 += group) {
     const int i1 = i0 + group < k1 ? i0 + group : k1;
     uint64_t span = 0;
-    for (int i = i0; i < i1; ++i) span = std::max(span, s->max_span[i]);
+    bool hires = true;  // every residual component's blocks on the high-half route
+    for (int i = i0; i < i1; ++i) {
+      span = std::max(span, s->max_span[i]);
+      if (i > 0 && s->full[i] != 0) hires = false;
+    }
     if (s->f.dtype == PMC_F32) {
       DecArgs<float> a{};
       fill_decode_args(s, i0, i1, a);
@@ -607,7 +618,7 @@ static pmc_status decode_range(pmc_ctx* ctx, const pmc_store* s, int k0, int k1,
       a.g = s->g;
       a.status = status;
       ProfScope ps(ctx, s->codec == 0 ? "k_decode_f32" : "k_decode_pq_f32");
-      e = launch_decode<float>(a, span, s->codec, ctx->stream);
+      e = launch_decode<float>(a, span, s->codec, hires, ctx->stream);
     } else {
       DecArgs<double> a{};
       fill_decode_args(s, i0, i1, a);
@@ -616,7 +627,7 @@ static pmc_status decode_range(pmc_ctx* ctx, const pmc_store* s, int k0, int k1,
       a.g = s->g;
       a.status = status;
       ProfScope ps(ctx, s->codec == 0 ? "k_decode_f64" : "k_decode_pq_f64");
-      e = launch_decode<double>(a, span, s->codec, ctx->stream);
+      e = launch_decode<double>(a, span, s->codec, false, ctx->stream);
     }
     if (e != hipSuccess) return hipfail(ctx, e, "decode");
     in = d_out;
@@ -794,10 +805,12 @@ pmc_status pmc_store_deserialize(pmc_ctx* ctx, const void* host_buf, size_t size
   }
   hipError_t e = hipSetDevice(ctx->device);
   uint8_t* base = (uint8_t*)d_streams;
-  // one status word after the streams: set by the index rebuild when a
-  // chunk's payload does not parse
-  unsigned int* status = (unsigned int*)(base + need - 256);
-  if (e == hipSuccess) e = launch_fill64((unsigned long long*)status, 1, 0ull, ctx->stream);
+  // after the streams: a status word, set by the index rebuild when a
+  // chunk's payload does not parse, then one flag per component, set when a
+  // coded block is outside the float32 high-half decode route
+  unsigned int* status = (unsigned int*)(base + need - kBlobTrailerBytes);
+  unsigned long long* full = (unsigned long long*)(base + need - kBlobTrailerBytes) + 1;
+  if (e == hipSuccess) e = launch_fill64((unsigned long long*)status, 1 + (uint64_t)v.n, 0ull, ctx->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(base + v.n * auxb, region, v.region_bytes, hipMemcpyHostToDevice, ctx->stream);
   // rebuild the per-block index of every stream
@@ -809,12 +822,16 @@ pmc_status pmc_store_deserialize(pmc_ctx* ctx, const void* host_buf, size_t size
     a.minexp = s->minexp[i];
     a.g = g;
     a.status = status;
+    a.full = full + i;
     e = s->f.dtype == PMC_F32 ? launch_aux<float>(a, s->codec, ctx->stream)
                               : launch_aux<double>(a, s->codec, ctx->stream);
   }
-  unsigned int h = 0;
-  if (e == hipSuccess) e = hipMemcpyAsync(&h, status, 4, hipMemcpyDeviceToHost, ctx->stream);
+  unsigned long long trailer[1 + kMaxComps] = {};
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(trailer, status, 8 * (1 + (size_t)v.n), hipMemcpyDeviceToHost, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  const unsigned int h = (unsigned int)(trailer[0] & 0xFFFFFFFFull);
+  for (int i = 0; i < v.n; ++i) s->full.push_back(trailer[1 + i]);
   if (e != hipSuccess) {
     delete s;
     return hipfail(ctx, e, "stream upload");

@@ -64,6 +64,13 @@ constexpr Order make_order() {
   return o;
 }
 constexpr Order kOrder = make_order();
+// its inverse: the coded position of block index l
+constexpr Order make_inv_order() {
+  Order o{};
+  for (int r = 0; r < 64; ++r) o.at[kOrder.at[r]] = (int8_t)r;
+  return o;
+}
+constexpr Order kInvOrder = make_inv_order();
 
 // a copy the compiler cannot prove equal to the original: recomputing the
 // residual from such copies stops common-subexpression elimination from
@@ -93,6 +100,14 @@ template <class S> __device__ __forceinline__ S wdbl(S a) {
   return (S)((W)a << 1);
 }
 template <class S> __device__ __forceinline__ S half(S a) { return a >> 1; }  // floor(a/2)
+// the same on two 16-bit values per 32-bit register (packed 16-bit
+// operations), for the float32 decoder's high-half route
+typedef short v2s __attribute__((ext_vector_type(2)));
+typedef unsigned short v2u __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ v2s wadd(v2s a, v2s b) { return (v2s)((v2u)a + (v2u)b); }
+__device__ __forceinline__ v2s wsub(v2s a, v2s b) { return (v2s)((v2u)a - (v2u)b); }
+__device__ __forceinline__ v2s wdbl(v2s a) { return (v2s)((v2u)a << (v2u)1); }
+__device__ __forceinline__ v2s half(v2s a) { return a >> (v2s)1; }
 
 // 4-point lifting realisation of the basis (1/16)[[4,4,4,4],[5,1,-1,-5],
 // [-4,4,4,-4],[-2,6,-6,2]]: the sums of the outer and inner pairs give the
@@ -681,6 +696,51 @@ __device__ __forceinline__ void dequant_add(const int64_t q[64], int emax, doubl
   for (int l = 0; l < 64; ++l) acc[l] = acc[l] + dequantize(q[l], emax);
 }
 
+// The float32 high-half route: a block whose coded planes all lie in the top
+// ten bit positions (p <= 10) has coefficients that are multiples of 2^22.
+// Every word the inverse lifting then forms is a multiple of 2^16: sums,
+// differences and doublings of such words act on their high halves modulo
+// 2^16 exactly as on the words modulo 2^32, and each halving meets an even
+// high half (the inputs are multiples of 2^16 * 2^6 and a value passes at most
+// six halvings, two per pass), so the word's arithmetic shift is its high
+// half's.  The lifting therefore runs on the high halves alone, two block
+// values per register with packed 16-bit operations, and yields the same
+// words q = h * 2^16: pairs of adjacent x for the z and y passes, pairs of
+// adjacent rows for the x pass (one byte permute per register between).
+// Then h * 2^(emax-14) equals q * 2^(emax-30) exactly while fast_dequant(emax)
+// holds, so the fused multiply-add is the one of dequant_add.
+__device__ __forceinline__ void inverse_dequant_add_hi16(const int32_t c[64], int emax, float acc[64]) {
+  v2s R[32];  // R[m] = (q[2m], q[2m+1]) in block order, high halves
+#pragma unroll
+  for (int m = 0; m < 32; ++m)
+    R[m] = __builtin_bit_cast(v2s, __builtin_amdgcn_perm((uint32_t)c[kInvOrder.at[2 * m + 1]],
+                                                         (uint32_t)c[kInvOrder.at[2 * m]], 0x07060302u));
+#pragma unroll
+  for (int m = 0; m < 8; ++m) lift_inv(R[m], R[m + 8], R[m + 16], R[m + 24]);  // z: l, l+16, l+32, l+48
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {  // y: l, l+4, l+8, l+12 for l = 16 lz + lx
+    const int m = 8 * (k >> 1) + (k & 1);
+    lift_inv(R[m], R[m + 2], R[m + 4], R[m + 6]);
+  }
+  const float scale = __uint_as_float((uint32_t)(emax - 14 + 127) << 23);
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {  // rows 2s and 2s+1: T[x] = (q[8s + x], q[8s + 4 + x])
+    const uint32_t a0 = __builtin_bit_cast(uint32_t, R[4 * s]), a1 = __builtin_bit_cast(uint32_t, R[4 * s + 1]);
+    const uint32_t b0 = __builtin_bit_cast(uint32_t, R[4 * s + 2]), b1 = __builtin_bit_cast(uint32_t, R[4 * s + 3]);
+    v2s T0 = __builtin_bit_cast(v2s, __builtin_amdgcn_perm(b0, a0, 0x05040100u));
+    v2s T1 = __builtin_bit_cast(v2s, __builtin_amdgcn_perm(b0, a0, 0x07060302u));
+    v2s T2 = __builtin_bit_cast(v2s, __builtin_amdgcn_perm(b1, a1, 0x05040100u));
+    v2s T3 = __builtin_bit_cast(v2s, __builtin_amdgcn_perm(b1, a1, 0x07060302u));
+    lift_inv(T0, T1, T2, T3);
+    const v2s T[4] = {T0, T1, T2, T3};
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      acc[8 * s + x] = __builtin_fmaf((float)T[x].x, scale, acc[8 * s + x]);
+      acc[8 * s + 4 + x] = __builtin_fmaf((float)T[x].y, scale, acc[8 * s + 4 + x]);
+    }
+  }
+}
+
 template <class U> __device__ __forceinline__ U plane_mask(int P, int p) {
   return p >= P ? ~(U)0 : ~(((U)1 << (P - p)) - (U)1);
 }
@@ -933,9 +993,19 @@ __device__ __forceinline__ void decode_hi32(R& r, int p, int zlead, int emax, do
   for (int l = 0; l < 64; ++l) acc[l] = acc[l] + __builtin_ldexp((double)q[l], emax - 30);
 }
 
+// a coded float32 block decodes on the high-half route (inverse_dequant_add_hi16)
+// when its coded planes all lie in the top ten bit positions and its
+// exponent keeps the scaled values normal
+template <class T> __device__ __forceinline__ bool hi16_block(int p, int emax) {
+  return sizeof(T) == 4 && p <= 10 && fast_dequant(emax);
+}
+
 // advance a reader over one block without reconstructing it; returns false
-// on a malformed header
-template <class T, class R> __device__ __forceinline__ bool block_skip(R& r, int minexp, const uint8_t* sq) {
+// on a malformed header.  full: set for a coded block outside the float32
+// high-half route (hi16_block)
+template <class T, class R>
+__device__ __forceinline__ bool block_skip(R& r, int minexp, const uint8_t* sq, bool& full) {
+  full = false;
   constexpr int P = FT<T>::P;
   if (!r.get(1)) return true;  // empty
   if (r.get(1)) {              // raw
@@ -951,6 +1021,7 @@ template <class T, class R> __device__ __forceinline__ bool block_skip(R& r, int
   int p = emax - minexp + kGuard;
   p = (p < 0 ? 0 : (p > P ? P : p)) + delta;
   if (emax < 2 - FT<T>::BIAS || p < 1 || p > P) return false;
+  full = sizeof(T) == 4 && !hi16_block<T>(p, emax);
   uint32_t n = 0;
   for (int t = 0; t < p; ++t) (void)plane_read(r, n, sq);
   return true;

@@ -156,7 +156,7 @@ bool check_blob_streams(const BlobView& v, const pmc::Geo& g, const uint8_t* reg
 }
 
 uint64_t blob_device_bytes(const BlobView& v, const pmc::Geo& g) {
-  return v.n * aux_bytes(g) + align256(v.region_bytes) + 256;
+  return v.n * aux_bytes(g) + align256(v.region_bytes) + kBlobTrailerBytes;
 }
 
 }  // namespace pmc_host

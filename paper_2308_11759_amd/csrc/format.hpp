@@ -69,7 +69,9 @@ bool check_stream(const uint8_t* p, uint64_t bytes, const pmc_field* f, const pm
 bool check_blob_streams(const BlobView& v, const pmc::Geo& g, const uint8_t* region, std::vector<uint64_t>* words,
                         std::vector<uint64_t>* spans);
 // device bytes of a store rebuilt from a blob: the block indexes, the
-// streams, and one 256-byte status word at the end
+// streams, and a trailer (a status word and one 64-bit flag per component)
+// at the end
+constexpr uint64_t kBlobTrailerBytes = 512;
 uint64_t blob_device_bytes(const BlobView& v, const pmc::Geo& g);
 
 }  // namespace pmc_host

@@ -42,6 +42,7 @@ struct pmc_store {
   std::vector<int> minexp;
   std::vector<uint64_t> bytes, offset, aux_offset, words, nempty, ncoded, nraw, nesc, nmiss;
   std::vector<uint64_t> max_span;  // largest payload words of a decode wave's four chunks
+  std::vector<uint64_t> full;      // nonzero: a coded block is outside the float32 high-half decode route
   const uint8_t* d_base = nullptr;  // caller-owned device memory holding the streams
 };
 

@@ -646,6 +646,8 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
     const unsigned long long be = __ballot(active && mode == MODE_EMPTY);
     const unsigned long long br = __ballot(active && mode == MODE_RAW);
     const unsigned long long bs = __ballot(active && mode == MODE_CODED && delta > 0);
+    const unsigned long long bf =
+        kCodec == 0 && sizeof(T) == 4 ? __ballot(active && mode == MODE_CODED && !hi16_block<T>(p, emax)) : 0ull;
     const unsigned long long bm = __ballot(miss);
     const bool nonfinite = xmax >= abs_bits((T)__builtin_inf());  // an infinite or NaN sample
     const unsigned long long bn = __ballot(active && nonfinite);
@@ -654,6 +656,8 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
       if (be) atomicAdd(&a.meta->nempty, (unsigned long long)__popcll(be));
       if (br) atomicAdd(&a.meta->nraw, (unsigned long long)__popcll(br));
       if (bs) atomicAdd(&a.meta->nesc, (unsigned long long)__popcll(bs));
+      // a flag, read first: most waves of such a component would set it
+      if (bf && *(volatile unsigned long long*)&a.meta->full == 0) atomicOr(&a.meta->full, 1ull);
       if (bm) atomicAdd(&a.meta->nmiss, (unsigned long long)__popcll(bm));
       if (bn) atomicOr(&a.meta->flags, (unsigned int)FLAG_NONFINITE);
       const unsigned long long wb = (unsigned long long)__double_as_longlong(wm);
@@ -907,7 +911,12 @@ __global__ __launch_bounds__(64) void k_pack(PackArgs a) {
 // Alg. 2 over one block per lane: x~ = (((x~_in or +0) + x_1) + x_2) ... in
 // the field precision; the block's bits start at its chunk's word offset plus
 // the block's bit offset from the per-block index
-template <class T, class R>
+// routes of the inverse transform: kRouteAuto picks per wave (float64: the
+// high-word route where it applies); kRouteFull the plain route; kRouteHi16
+// the float32 high-half route, for components whose every block has p <= 10
+// and fast_dequant(emax) (the caller guarantees it)
+constexpr int kRouteAuto = 0, kRouteFull = 1, kRouteHi16 = 2;
+template <class T, int kRoute = kRouteAuto, class R>
 __device__ __forceinline__ bool decode_block_add(R& r, int minexp, T acc[64], const uint8_t* sq, bool rel) {
   typedef typename FT<T>::U U;
   constexpr int P = FT<T>::P;
@@ -950,7 +959,7 @@ __device__ __forceinline__ bool decode_block_add(R& r, int minexp, T acc[64], co
   const int z0 = (int)__builtin_ctz(r.peek32() | 0x80000000u);
   const int zlead = z0 < p ? z0 : p;
   r.skip((uint32_t)zlead);
-  if constexpr (sizeof(T) == 8) {
+  if constexpr (sizeof(T) == 8 && kRoute == kRouteAuto) {
     // every coded plane in the top 26 bit positions and every result
     // normal: the lifting on the coefficients' high words (a wave-uniform
     // choice; both routes give the same sums)
@@ -964,6 +973,10 @@ __device__ __forceinline__ bool decode_block_add(R& r, int minexp, T acc[64], co
   }
   typename FT<T>::S c[64], q[64];
   planes_read<T>(r, c, p, zlead, sq, rel);
+  if constexpr (sizeof(T) == 4 && kRoute == kRouteHi16) {
+    inverse_dequant_add_hi16(c, emax, acc);
+    return true;
+  }
   inverse_zy_ints<T>(c, q);
   inverse_x<T>(q);
   dequant_add(q, emax, acc);
@@ -1015,14 +1028,14 @@ __device__ __forceinline__ void stage_span(const uint32_t* payload, const Span& 
 // malformed stream.  kFull: every block of the field is full and rows are
 // aligned (all dimensions multiples of 4): no per-lane edge paths.
 // one block of one component, codec 0 (minexp) or codec 1 (step = 2 tau)
-template <class T, int kCodec, class R>
+template <class T, int kCodec, int kRoute = kRouteAuto, class R>
 __device__ __forceinline__ bool decode_block_codec(R& r, int minexp, double step, T acc[64], const uint8_t* sq,
                                                    bool rel) {
-  if constexpr (kCodec == 0) return decode_block_add<T>(r, minexp, acc, sq, rel);
+  if constexpr (kCodec == 0) return decode_block_add<T, kRoute>(r, minexp, acc, sq, rel);
   else return pq_decode_add<T>(r, step, acc);
 }
 
-template <class T, bool kStaged, bool kBox = false, bool kFull = false, int kCodec = 0>
+template <class T, bool kStaged, bool kBox = false, bool kFull = false, int kCodec = 0, bool kHiRes = false>
 __device__ __forceinline__ bool decode_wave(const Geo& g, const uint8_t* const* s, const uint32_t* const* aux,
                                             const uint64_t* words, const int* minexp, const double* step, int ncomp,
                                             uint32_t relmask, const T* in, T* out, uint64_t w, const uint8_t* sq,
@@ -1069,60 +1082,73 @@ __device__ __forceinline__ bool decode_wave(const Geo& g, const uint8_t* const* 
         off = aux[0][blk];
       }
     }
-    for (int i = 0; i < ncomp; ++i) {
-      __builtin_amdgcn_s_waitcnt(0);  // component i's words and lane values
-      __syncthreads();
-      // the next component: into the other half while this one decodes, when
-      // both fit a half
-      Span nxt{0, 0, false};
-      uint32_t nxt_base = 0, nxt_cap = kStageWords;
-      uint32_t nstart = 0, nstop = 0, noff = 0;
-      bool pre = false;
-      const uint32_t* nindex = nullptr;
-      if (i + 1 < ncomp) {
-        nindex = reinterpret_cast<const uint32_t*>(s[i + 1] + kHeaderBytes);
-        nxt = wave_span(nindex, g.nchunks, words[i + 1], w);
-        pre = nxt.ok && cur.ok && cur.s1 - cur.s0 <= kHalfWords && nxt.s1 - nxt.s0 <= kHalfWords;
-        if (pre) {
-          nxt_base = cur_base == 0 ? kHalf1 : 0;
-          nxt_cap = kHalfWords;
-          stage_span(nindex + g.nchunks, nxt, stage, nxt_base);
+    auto component = [&](int i, auto route) {
+        __builtin_amdgcn_s_waitcnt(0);  // component i's words and lane values
+        __syncthreads();
+        // the next component: into the other half while this one decodes, when
+        // both fit a half
+        Span nxt{0, 0, false};
+        uint32_t nxt_base = 0, nxt_cap = kStageWords;
+        uint32_t nstart = 0, nstop = 0, noff = 0;
+        bool pre = false;
+        const uint32_t* nindex = nullptr;
+        if (i + 1 < ncomp) {
+          nindex = reinterpret_cast<const uint32_t*>(s[i + 1] + kHeaderBytes);
+          nxt = wave_span(nindex, g.nchunks, words[i + 1], w);
+          pre = nxt.ok && cur.ok && cur.s1 - cur.s0 <= kHalfWords && nxt.s1 - nxt.s0 <= kHalfWords;
+          if (pre) {
+            nxt_base = cur_base == 0 ? kHalf1 : 0;
+            nxt_cap = kHalfWords;
+            stage_span(nindex + g.nchunks, nxt, stage, nxt_base);
+            if (active) {
+              nstart = nindex[chunk];
+              nstop = chunk + 1 < g.nchunks ? nindex[chunk + 1] : (uint32_t)min<uint64_t>(words[i + 1], 0xFFFFFFFFull);
+              noff = aux[i + 1][blk];
+            }
+          }
+        }
+        if (active && ok) {
+          if (!cur.ok || words[i] > 0xFFFFFFFFull || start > stop || stop > words[i] ||
+              off >= (uint64_t)(stop - start) * 32 || start < cur.s0 || stop > cur.s1) {
+            ok = false;
+          } else {
+            const uint32_t s0 = (uint32_t)cur.s0;
+            LBits r;
+            r.init(stage + cur_base, start - s0 + (off >> 5), stop - s0, cur_cap);
+            r.skip((uint32_t)(off & 31));
+            ok = decode_block_codec<T, kCodec, decltype(route)::value>(r, minexp[i], step[i], acc, sq,
+                                                                        (relmask >> i) & 1u) && !r.bad();
+          }
+        }
+        if (i + 1 < ncomp && !pre) {  // staged after this component, into the whole buffer's first half or all of it
+          __syncthreads();  // every lane is done with this component's words
+          nxt_base = 0;
+          nxt_cap = nxt.s1 - nxt.s0 <= kHalfWords ? kHalfWords : kStageWords;
+          if (nxt.ok) stage_span(nindex + g.nchunks, nxt, stage, 0);
           if (active) {
             nstart = nindex[chunk];
             nstop = chunk + 1 < g.nchunks ? nindex[chunk + 1] : (uint32_t)min<uint64_t>(words[i + 1], 0xFFFFFFFFull);
             noff = aux[i + 1][blk];
           }
         }
+        cur = nxt;
+        cur_base = nxt_base;
+        cur_cap = nxt_cap;
+        start = nstart;
+        stop = nstop;
+        off = noff;
+    };
+    if constexpr (kHiRes) {
+      // the store's first component (if decoded here) on the full route,
+      // the residual ones on the high-half route only
+      int i = 0;
+      if (ncomp > 0 && !(relmask & 1u)) {
+        component(0, std::integral_constant<int, kRouteFull>{});
+        i = 1;
       }
-      if (active && ok) {
-        if (!cur.ok || words[i] > 0xFFFFFFFFull || start > stop || stop > words[i] ||
-            off >= (uint64_t)(stop - start) * 32 || start < cur.s0 || stop > cur.s1) {
-          ok = false;
-        } else {
-          const uint32_t s0 = (uint32_t)cur.s0;
-          LBits r;
-          r.init(stage + cur_base, start - s0 + (off >> 5), stop - s0, cur_cap);
-          r.skip((uint32_t)(off & 31));
-          ok = decode_block_codec<T, kCodec>(r, minexp[i], step[i], acc, sq, (relmask >> i) & 1u) && !r.bad();
-        }
-      }
-      if (i + 1 < ncomp && !pre) {  // staged after this component, into the whole buffer's first half or all of it
-        __syncthreads();  // every lane is done with this component's words
-        nxt_base = 0;
-        nxt_cap = nxt.s1 - nxt.s0 <= kHalfWords ? kHalfWords : kStageWords;
-        if (nxt.ok) stage_span(nindex + g.nchunks, nxt, stage, 0);
-        if (active) {
-          nstart = nindex[chunk];
-          nstop = chunk + 1 < g.nchunks ? nindex[chunk + 1] : (uint32_t)min<uint64_t>(words[i + 1], 0xFFFFFFFFull);
-          noff = aux[i + 1][blk];
-        }
-      }
-      cur = nxt;
-      cur_base = nxt_base;
-      cur_cap = nxt_cap;
-      start = nstart;
-      stop = nstop;
-      off = noff;
+      for (; i < ncomp; ++i) component(i, std::integral_constant<int, kRouteHi16>{});
+    } else {
+      for (int i = 0; i < ncomp; ++i) component(i, std::integral_constant<int, kRouteAuto>{});
     }
   } else {
     for (int i = 0; i < ncomp; ++i) {
@@ -1163,12 +1189,14 @@ __device__ __forceinline__ bool decode_wave(const Geo& g, const uint8_t* const* 
   return ok || !active;
 }
 
-template <class T, bool kStaged, bool kFull, int kCodec>
+// kHiRes: the launch's residual components decode on the float32 high-half
+// route alone (the host has checked that every block of them qualifies)
+template <class T, bool kStaged, bool kFull, int kCodec, bool kHiRes = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_decode(DecArgs<T> a) {
   __shared__ uint8_t s_squeeze[256];
   __shared__ uint32_t s_stage[kStaged ? kStageWords + 3 : 1];
   squeeze_table(s_squeeze);
-  if (!decode_wave<T, kStaged, false, kFull, kCodec>(a.g, a.s, a.aux, a.words, a.minexp, a.step, a.ncomp, a.relmask,
+  if (!decode_wave<T, kStaged, false, kFull, kCodec, kHiRes>(a.g, a.s, a.aux, a.words, a.minexp, a.step, a.ncomp, a.relmask,
                                                      a.in, a.out, blockIdx.x, s_squeeze, s_stage))
     atomicOr(a.status, 1u);
 }
@@ -1233,11 +1261,15 @@ __global__ __launch_bounds__(64) void k_aux(AuxArgs a) {
   GBits r;
   r.init(payload, (uint32_t)start, (uint32_t)(ok ? stop : start));
   const uint64_t b0 = chunk * kChunkBlocks, b1 = min<uint64_t>(a.g.nblocks, b0 + kChunkBlocks);
+  bool any_full = false;
   for (uint64_t blk = b0; blk < b1; ++blk) {
     a.aux[blk] = ok ? (uint32_t)r.consumed((uint32_t)start) : 0u;
-    if (ok) ok = (kCodec == 0 ? block_skip<T>(r, a.minexp, s_squeeze) : pq_block_skip<T>(r)) && !r.bad();
+    bool full = false;
+    if (ok) ok = (kCodec == 0 ? block_skip<T>(r, a.minexp, s_squeeze, full) : pq_block_skip<T>(r)) && !r.bad();
+    any_full = any_full || full;
   }
   if (!ok && a.status) atomicOr(a.status, 1u);
+  if (any_full && a.full && *(volatile unsigned long long*)a.full == 0) atomicOr(a.full, 1ull);
 }
 
 // ---------------------------------------------------------------------------
@@ -1523,11 +1555,19 @@ template <class T> hipError_t launch_pack(const PackArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 uint64_t stage_words() { return kStageWords; }
-template <class T, int kCodec> void launch_decode_codec(const DecArgs<T>& a, uint64_t max_span, hipStream_t s) {
+template <class T, int kCodec>
+void launch_decode_codec(const DecArgs<T>& a, uint64_t max_span, bool hires, hipStream_t s) {
   const uint64_t wgs = (a.g.nblocks + 63) / 64;
   const dim3 grid((uint32_t)wgs), wg(64);
   // every block full and every row aligned: the kernel without edge paths
   const bool full = a.g.nx % 4 == 0 && a.g.ny % 4 == 0 && a.g.nz % 4 == 0 && a.g.rows_aligned;
+  if constexpr (sizeof(T) == 4 && kCodec == 0) {
+    if (hires && max_span <= kStageWords) {
+      if (full) hipLaunchKernelGGL((k_decode<T, true, true, kCodec, true>), grid, wg, 0, s, a);
+      else hipLaunchKernelGGL((k_decode<T, true, false, kCodec, true>), grid, wg, 0, s, a);
+      return;
+    }
+  }
   if (max_span <= kStageWords) {
     if (full) hipLaunchKernelGGL((k_decode<T, true, true, kCodec>), grid, wg, 0, s, a);
     else hipLaunchKernelGGL((k_decode<T, true, false, kCodec>), grid, wg, 0, s, a);
@@ -1536,9 +1576,10 @@ template <class T, int kCodec> void launch_decode_codec(const DecArgs<T>& a, uin
     else hipLaunchKernelGGL((k_decode<T, false, false, kCodec>), grid, wg, 0, s, a);
   }
 }
-template <class T> hipError_t launch_decode(const DecArgs<T>& a, uint64_t max_span, int codec, hipStream_t s) {
-  if (codec == 0) launch_decode_codec<T, 0>(a, max_span, s);
-  else launch_decode_codec<T, 1>(a, max_span, s);
+template <class T>
+hipError_t launch_decode(const DecArgs<T>& a, uint64_t max_span, int codec, bool hires, hipStream_t s) {
+  if (codec == 0) launch_decode_codec<T, 0>(a, max_span, hires, s);
+  else launch_decode_codec<T, 1>(a, max_span, false, s);
   return hipGetLastError();
 }
 template <class T>
@@ -1753,8 +1794,8 @@ template hipError_t launch_encode<float>(const EncArgs<float>&, int, hipStream_t
 template hipError_t launch_encode<double>(const EncArgs<double>&, int, hipStream_t);
 template hipError_t launch_pack<float>(const PackArgs&, hipStream_t);
 template hipError_t launch_pack<double>(const PackArgs&, hipStream_t);
-template hipError_t launch_decode<float>(const DecArgs<float>&, uint64_t, int, hipStream_t);
-template hipError_t launch_decode<double>(const DecArgs<double>&, uint64_t, int, hipStream_t);
+template hipError_t launch_decode<float>(const DecArgs<float>&, uint64_t, int, bool, hipStream_t);
+template hipError_t launch_decode<double>(const DecArgs<double>&, uint64_t, int, bool, hipStream_t);
 template hipError_t launch_decode_queries<float>(const ServeArgs&, uint64_t, int, hipStream_t);
 template hipError_t launch_decode_queries<double>(const ServeArgs&, uint64_t, int, hipStream_t);
 template hipError_t launch_aux<float>(const AuxArgs&, int, hipStream_t);

@@ -26,7 +26,8 @@ struct CompMeta {
   unsigned int flags;
   unsigned int pad;
   unsigned long long max_span;  // largest payload words of four consecutive chunks (one decode wave)
-  unsigned long long reserved[5];
+  unsigned long long full;      // nonzero: some coded block is outside the float32 high-half decode route
+  unsigned long long reserved[4];
 };
 static_assert(sizeof(CompMeta) == 128, "CompMeta layout");
 
@@ -133,6 +134,7 @@ struct AuxArgs {
   int minexp;
   Geo g;
   unsigned int* status;  // optional (NULL): set when a chunk fails to parse
+  unsigned long long* full;  // optional (NULL): set when a coded block is outside the float32 high-half route
 };
 
 // ---- batches of fields (one table entry per field) -----------------------
@@ -183,7 +185,11 @@ template <class T> hipError_t launch_aux(const AuxArgs& a, int codec, hipStream_
 // streams; spans up to the LDS staging capacity use the staged kernel
 template <class T> hipError_t launch_decode_queries(const ServeArgs& a, uint64_t max_span, int codec, hipStream_t s);
 template <class T> hipError_t launch_pack(const PackArgs& a, hipStream_t s);
-template <class T> hipError_t launch_decode(const DecArgs<T>& a, uint64_t max_span, int codec, hipStream_t s);
+// hires: every residual component of the launch (store index > 0) has no
+// block outside the float32 high-half route (CompMeta.full == 0), so the
+// decoder may run them on that route alone
+template <class T>
+hipError_t launch_decode(const DecArgs<T>& a, uint64_t max_span, int codec, bool hires, hipStream_t s);
 // components [0, a.ncomp) of the blocks meeting the box, written to a.out as the box alone
 template <class T>
 hipError_t launch_decode_box(const DecArgs<T>& a, const BoxArgs& b, uint64_t max_span, int codec, hipStream_t s);

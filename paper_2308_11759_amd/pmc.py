@@ -68,6 +68,7 @@ SIGNATURES = {
     "pmc_compress_static": (_int, [_vp, _P(Field), _vp, _int, _P(_dbl), _vp, _sz, _P(_vp)]),
     "pmc_store_info": (_int, [_vp, _P(_int), _P(_dbl), _P(_dbl), _P(_u64), _P(_u64), _P(_u64)]),
     "pmc_store_counts": (_int, [_vp, _int, _P(_u64)]),
+    "pmc_store_decode_route": (_int, [_vp, _int, _P(_int)]),
     "pmc_store_codec": (_int, [_vp, _P(_int)]),
     "pmc_store_span": (_int, [_vp, _int, _P(_u64), _P(_int)]),
     "pmc_store_field": (_int, [_vp, _P(Field)]),
@@ -567,8 +568,11 @@ class Store:
             self.lib.pmc_store_counts(self.handle, i, c)
             span, staged = ctypes.c_uint64(), ctypes.c_int()
             self.lib.pmc_store_span(self.handle, i, ctypes.byref(span), ctypes.byref(staged))
+            hh = ctypes.c_int()
+            self.lib.pmc_store_decode_route(self.handle, i, ctypes.byref(hh))
             out.append(dict(tau=tau[i], linf=linf[i], bytes=by[i], nempty=c[0], ncoded=c[1], nraw=c[2],
-                            nesc=c[3], nmiss=c[4], max_span=span.value, staged=bool(staged.value)))
+                            nesc=c[3], nmiss=c[4], max_span=span.value, staged=bool(staged.value),
+                            high_half=bool(hh.value)))
         return out
 
     @property

@@ -81,7 +81,7 @@ def test_blob_validation_uses_checked_arithmetic():
     assert check(blob) == pmc.OK
     nblocks = 2 * 3 * 5
     region = align256(len(comps[0])) + len(comps[1])
-    assert need.value == 2 * align256(4 * nblocks) + align256(region) + 256
+    assert need.value == 2 * align256(4 * nblocks) + align256(region) + 512
     # a component size that makes the running region sum wrap
     bad = bytearray(blob)
     struct.pack_into("<Q", bad, 48 + 16, (1 << 64) - 64)

@@ -195,6 +195,44 @@ def test_decode_oracle_streams(ctx):
     assert np.array_equal(ctx.retrieve(again, 5).cpu().numpy(), recon[-1])
 
 
+def test_float32_decode_routes(ctx):
+    """Float32 retrievals run the inverse transform of residual components on
+    the coefficients' high 16-bit halves when every block of them codes its
+    planes in the top ten bit positions.  The route the encoder finds for
+    each component equals the one the deserialiser finds from the payload
+    (of the GPU's streams and of the oracle's), and every x~_k equals the
+    oracle's on both routes: refinements of single components that qualify
+    (the high-half route), and a schedule of 6 bits per component whose
+    residual blocks code 12 or more planes."""
+    for label, taus in (("3 bits per component", [2.0 ** (-3 * (i + 1)) for i in range(6)]),
+                        ("6 bits per component", [2.0 ** (-6 * (i + 1)) for i in range(4)])):
+        x = inputs.spectral_field((20, 24, 36), seed=31, dtype=np.float32)
+        comps, meta, recon = oracle_run(x, taus)
+        store = ctx.compress(to_dev(x), taus)
+        route = [c["high_half"] for c in store.info]
+        say("%s: high-half route per component %s" % (label, route))
+        again = ctx.deserialize(store.serialize())
+        theirs = ctx.deserialize(store_blob(x.shape, x.dtype, comps, meta))
+        assert [c["high_half"] for c in again.info] == route
+        assert [c["high_half"] for c in theirs.info] == route
+        n = len(taus)
+        for st in (store, again, theirs):
+            for k in range(1, n + 1):
+                assert np.array_equal(ctx.retrieve(st, k).cpu().numpy(), recon[k - 1]), (label, k)
+            for j in range(1, n):  # x~_j -> x~_{j+1}: component j alone
+                xt = ctx.retrieve(st, j)
+                ctx.refine(st, j, j + 1, xt)
+                assert np.array_equal(xt.cpu().numpy(), recon[j]), (label, j)
+        if label == "6 bits per component":
+            assert not any(route[1:])
+        else:
+            assert sum(route[1:]) >= 3
+    # float64 stores never take it
+    xd = inputs.spectral_field((12, 16, 20), seed=32, dtype=np.float64)
+    st = ctx.compress(to_dev(xd), [0.1, 0.01])
+    assert [c["high_half"] for c in st.info] == [False, False]
+
+
 def test_fused_literal_refine_agree(ctx):
     from paper_2308_11759_amd import pmc
     x = inputs.spectral_field((24, 28, 40), seed=9, dtype=np.float32)
