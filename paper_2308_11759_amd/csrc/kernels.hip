@@ -427,7 +427,9 @@ __device__ __forceinline__ double check_rows_pq(const XLds<T>& XL, const T* tin,
 // registers.  x~_{i-1} / x~_i are the wave's tiles (see tile_index).
 // kCodec: 0 the block-transform codec, 1 prediction and quantisation (its
 // residual block stays in registers for the candidates and the emission)
-template <class T, bool kFull = false, int kCodec = 0>
+// kHiCheck: float64 candidates may be checked on the high-word route (the
+// batched kernel leaves it out: it holds too many registers there)
+template <class T, bool kFull = false, int kCodec = 0, bool kHiCheck = true>
 __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T* s_x, const uint16_t* unsq) {
   typedef typename FT<T>::U U;
   typedef typename FT<T>::S S;
@@ -531,13 +533,35 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
           const U m = plane_mask<U>(P, p);
           // decode, add and check one row at a time; x~_i rows are stored as
           // they come (a rejected candidate is overwritten below)
-          S c[64], q[64];
-#pragma unroll
-          for (int r = 0; r < 64; ++r) c[r] = from_nb<T>(u[r] & m);  // the top p planes
-          inverse_zy_ints<T>(c, q);
-          inverse_x<T>(q);
           T dv[64];
-          const T scale = dequantize_block(q, emax, dv);
+          T scale;
+          if (sizeof(T) == 8 && kHiCheck && __all(p <= 26 && emax >= -992)) {
+            // float64 with the top p <= 26 planes: the inverse transform on
+            // the coefficients' high 32-bit words (see decode_hi32), the
+            // same values
+            int32_t h[64];
+#pragma unroll
+            for (int r = 0; r < 64; ++r) h[kOrder.at[r]] = (int32_t)((uint64_t)from_nb<T>(u[r] & m) >> 32);
+#pragma unroll
+            for (int l = 0; l < 16; ++l) lift_inv(h[l], h[l + 16], h[l + 32], h[l + 48]);
+#pragma unroll
+            for (int l = 0; l < 16; ++l) {
+              const int b = 16 * (l >> 2) + (l & 3);
+              lift_inv(h[b], h[b + 4], h[b + 8], h[b + 12]);
+            }
+#pragma unroll
+            for (int r = 0; r < 16; ++r) lift_inv(h[4 * r], h[4 * r + 1], h[4 * r + 2], h[4 * r + 3]);
+#pragma unroll
+            for (int l = 0; l < 64; ++l) dv[l] = (T)__builtin_ldexp((double)h[l], emax - 30);
+            scale = (T)1;
+          } else {
+            S c[64], q[64];
+#pragma unroll
+            for (int r = 0; r < 64; ++r) c[r] = from_nb<T>(u[r] & m);  // the top p planes
+            inverse_zy_ints<T>(c, q);
+            inverse_x<T>(q);
+            scale = dequantize_block(q, emax, dv);
+          }
           double ea = 0.0;
           // eight rows of x~_{i-1} in flight together
           constexpr int RB = 8;
@@ -1417,7 +1441,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
   for (uint32_t it = blockIdx.x; it < b.nitems; it += gridDim.x) {
     const Item w = b.items[it];
     const FieldDev* f = b.fields + w.field;
-    if (b.comp < f->ncomp) encode_wave<T>(field_enc_args<T>(*f, b.comp), w.index, s_x, s_unsq);
+    if (b.comp < f->ncomp) encode_wave<T, false, 0, false>(field_enc_args<T>(*f, b.comp), w.index, s_x, s_unsq);
     __syncthreads();  // the next item reuses s_x
   }
 }
