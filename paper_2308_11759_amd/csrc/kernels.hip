@@ -1250,7 +1250,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
 
 // many retrieval queries in one launch: wave w belongs to the query q with
 // wave_prefix[q] <= w < wave_prefix[q + 1]
-template <class T, bool kStaged, int kCodec>
+template <class T, bool kStaged, int kCodec, bool kHiRes = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_decode_queries(ServeArgs a) {
   __shared__ uint8_t s_squeeze[256];
   __shared__ uint32_t s_stage[kStaged ? kStageWords + 3 : 1];
@@ -1263,9 +1263,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     else hi = mid;
   }
   const QueryDev& q = a.q[lo];
-  if (!decode_wave<T, kStaged, false, false, kCodec>(q.g, q.s, q.aux, q.words, q.minexp, q.step, q.ncomp, q.relmask,
-                                                     reinterpret_cast<const T*>(q.in), reinterpret_cast<T*>(q.out),
-                                                     w - a.wave_prefix[lo], s_squeeze, s_stage))
+  if (!decode_wave<T, kStaged, false, false, kCodec, kHiRes>(q.g, q.s, q.aux, q.words, q.minexp, q.step, q.ncomp,
+                                                             q.relmask, reinterpret_cast<const T*>(q.in),
+                                                             reinterpret_cast<T*>(q.out), w - a.wave_prefix[lo],
+                                                             s_squeeze, s_stage))
     atomicOr(a.status, 1u);
 }
 
@@ -1622,10 +1623,17 @@ hipError_t launch_decode_box(const DecArgs<T>& a, const BoxArgs& b, uint64_t max
   }
   return hipGetLastError();
 }
-template <class T> hipError_t launch_decode_queries(const ServeArgs& a, uint64_t max_span, int codec, hipStream_t s) {
+template <class T>
+hipError_t launch_decode_queries(const ServeArgs& a, uint64_t max_span, int codec, bool hires, hipStream_t s) {
   if (a.nwaves == 0) return hipSuccess;
   const dim3 grid(a.nwaves), wg(64);
   const bool staged = max_span <= kStageWords;
+  if constexpr (sizeof(T) == 4) {
+    if (codec == 0 && hires && staged) {
+      hipLaunchKernelGGL((k_decode_queries<T, true, 0, true>), grid, wg, 0, s, a);
+      return hipGetLastError();
+    }
+  }
   if (codec == 0) {
     if (staged) hipLaunchKernelGGL((k_decode_queries<T, true, 0>), grid, wg, 0, s, a);
     else hipLaunchKernelGGL((k_decode_queries<T, false, 0>), grid, wg, 0, s, a);
@@ -1820,8 +1828,8 @@ template hipError_t launch_pack<float>(const PackArgs&, hipStream_t);
 template hipError_t launch_pack<double>(const PackArgs&, hipStream_t);
 template hipError_t launch_decode<float>(const DecArgs<float>&, uint64_t, int, bool, hipStream_t);
 template hipError_t launch_decode<double>(const DecArgs<double>&, uint64_t, int, bool, hipStream_t);
-template hipError_t launch_decode_queries<float>(const ServeArgs&, uint64_t, int, hipStream_t);
-template hipError_t launch_decode_queries<double>(const ServeArgs&, uint64_t, int, hipStream_t);
+template hipError_t launch_decode_queries<float>(const ServeArgs&, uint64_t, int, bool, hipStream_t);
+template hipError_t launch_decode_queries<double>(const ServeArgs&, uint64_t, int, bool, hipStream_t);
 template hipError_t launch_aux<float>(const AuxArgs&, int, hipStream_t);
 template hipError_t launch_aux<double>(const AuxArgs&, int, hipStream_t);
 template hipError_t launch_range<float>(const float*, uint64_t, unsigned long long*, hipStream_t);

@@ -183,7 +183,9 @@ hipError_t launch_scan(const ScanArgs& a, hipStream_t s);
 template <class T> hipError_t launch_aux(const AuxArgs& a, int codec, hipStream_t s);
 // max_span: the largest word span of a wave's four chunks over the decoded
 // streams; spans up to the LDS staging capacity use the staged kernel
-template <class T> hipError_t launch_decode_queries(const ServeArgs& a, uint64_t max_span, int codec, hipStream_t s);
+// hires: as launch_decode's, for every query of the launch
+template <class T>
+hipError_t launch_decode_queries(const ServeArgs& a, uint64_t max_span, int codec, bool hires, hipStream_t s);
 template <class T> hipError_t launch_pack(const PackArgs& a, hipStream_t s);
 // hires: every residual component of the launch (store index > 0) has no
 // block outside the float32 high-half route (CompMeta.full == 0), so the

@@ -115,7 +115,10 @@ struct Step {
 };
 
 constexpr int kMaxInflight = 4;
-constexpr int kGroups = 4;  // (float32, float64) x (block transform, prediction)
+// (float32, float64) x (block transform, prediction), and float32 block
+// transform queries whose residual components all take the decoder's
+// high-half route (launched as their own instantiation)
+constexpr int kGroups = 5;
 
 }  // namespace
 
@@ -276,15 +279,17 @@ bool launch_step(pmc_server* sv) {
     }
     sv->pending.pop_front();
     void* out = q.out ? q.out : (void*)(sv->arena_base + q.slot_off);
-    const int t = (s->f.dtype == PMC_F32 ? 0 : 1) + 2 * s->codec;
+    const int ci = find_cache(sv, q.field, q.k, step_id);
+    const int k0 = ci >= 0 ? sv->cache[ci].k : 0;
+    bool hires = s->f.dtype == PMC_F32 && s->codec == 0;
+    for (int c = k0; c < q.k; ++c)
+      if (c > 0 && s->full[c] != 0) hires = false;
+    const int t = hires ? 4 : (s->f.dtype == PMC_F32 ? 0 : 1) + 2 * s->codec;
     QueryDev& d = hq[t][nq[t]];
     std::memset(&d, 0, sizeof(d));
-    const int ci = find_cache(sv, q.field, q.k, step_id);
-    int k0 = 0;
     d.in = nullptr;
     if (ci >= 0) {
       CacheEntry& e = sv->cache[ci];
-      k0 = e.k;
       d.in = sv->arena_base + e.off;
       e.last_use = step_id;
       e.busy_step = step_id;
@@ -340,9 +345,13 @@ bool launch_step(pmc_server* sv) {
     a.nq = nq[t];
     a.nwaves = nw[t];
     a.status = (unsigned int*)(dtab + sv->table_slot_bytes - 256);
-    const int codec = t / 2;
-    e = t % 2 == 0 ? launch_decode_queries<float>(a, span[t], codec, sv->stream)
-                   : launch_decode_queries<double>(a, span[t], codec, sv->stream);
+    if (t == 4) {
+      e = launch_decode_queries<float>(a, span[t], 0, true, sv->stream);
+    } else {
+      const int codec = t / 2;
+      e = t % 2 == 0 ? launch_decode_queries<float>(a, span[t], codec, false, sv->stream)
+                     : launch_decode_queries<double>(a, span[t], codec, false, sv->stream);
+    }
   }
   for (const CopyJob& c : copies)
     if (e == hipSuccess) e = hipMemcpyAsync(c.dst, c.src, c.bytes, hipMemcpyDeviceToDevice, sv->stream);
