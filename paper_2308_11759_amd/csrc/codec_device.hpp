@@ -709,12 +709,7 @@ __device__ __forceinline__ void dequant_add(const int64_t q[64], int emax, doubl
 // adjacent rows for the x pass (one byte permute per register between).
 // Then h * 2^(emax-14) equals q * 2^(emax-30) exactly while fast_dequant(emax)
 // holds, so the fused multiply-add is the one of dequant_add.
-__device__ __forceinline__ void inverse_dequant_add_hi16(const int32_t c[64], int emax, float acc[64]) {
-  v2s R[32];  // R[m] = (q[2m], q[2m+1]) in block order, high halves
-#pragma unroll
-  for (int m = 0; m < 32; ++m)
-    R[m] = __builtin_bit_cast(v2s, __builtin_amdgcn_perm((uint32_t)c[kInvOrder.at[2 * m + 1]],
-                                                         (uint32_t)c[kInvOrder.at[2 * m]], 0x07060302u));
+__device__ __forceinline__ void lift_dequant_add_hi16(v2s R[32], int emax, float acc[64]) {
 #pragma unroll
   for (int m = 0; m < 8; ++m) lift_inv(R[m], R[m + 8], R[m + 16], R[m + 24]);  // z: l, l+16, l+32, l+48
 #pragma unroll
@@ -739,6 +734,13 @@ __device__ __forceinline__ void inverse_dequant_add_hi16(const int32_t c[64], in
       acc[8 * s + 4 + x] = __builtin_fmaf((float)T[x].y, scale, acc[8 * s + 4 + x]);
     }
   }
+}
+// R[m] = (q[2m], q[2m+1]) in block order: high halves of the coded-order words c
+__device__ __forceinline__ void pack_hi16(const int32_t c[64], v2s R[32]) {
+#pragma unroll
+  for (int m = 0; m < 32; ++m)
+    R[m] = __builtin_bit_cast(v2s, __builtin_amdgcn_perm((uint32_t)c[kInvOrder.at[2 * m + 1]],
+                                                         (uint32_t)c[kInvOrder.at[2 * m]], 0x07060302u));
 }
 
 template <class U> __device__ __forceinline__ U plane_mask(int P, int p) {
@@ -833,8 +835,25 @@ template <int W> __device__ __forceinline__ void transpose_groups(uint32_t A[2 *
   gstage<1, 0x55555555u, 2 * W>(A);
 }
 
-// planes [zlead, p) of one block through W slots (slot t' = plane base + t'),
-// transposed into W-bit slices (transpose_groups); returns base.
+// the block's planes in [zlead, p) that fall in W slots (slot t' = plane
+// base + t', base <= zlead), transposed into W-bit slices (transpose_groups);
+// any deeper planes are left to the caller
+template <int W, class R>
+__device__ __forceinline__ void read_slots_at(R& r, uint32_t A[2 * W], int base, int p, int zlead, const uint8_t* sq,
+                                              uint32_t& n) {
+  n = 0;
+#pragma unroll
+  for (int tp = 0; tp < W; ++tp) {
+    const int t = base + tp;
+    uint64_t wd = 0;
+    if (t >= zlead && t < p) wd = plane_read(r, n, sq);
+    A[W - 1 - tp] = (uint32_t)wd;
+    A[2 * W - 1 - tp] = (uint32_t)(wd >> 32);
+  }
+  transpose_groups<W>(A);
+}
+
+// the same with the slot base of the block's component (below); returns base
 template <class T, int W, class R>
 __device__ __forceinline__ int read_slots(R& r, uint32_t A[2 * W], int p, int zlead, const uint8_t* sq, bool rel,
                                           uint32_t& n) {
@@ -851,15 +870,7 @@ __device__ __forceinline__ int read_slots(R& r, uint32_t A[2 * W], int p, int zl
   // hold no plane).  Planes above base are empty in either case (base <=
   // zlead).
   const int base = rel ? (zlead < P - W ? zlead : P - W) : (p - W < zlead ? p - W : zlead);
-#pragma unroll
-  for (int tp = 0; tp < W; ++tp) {
-    const int t = base + tp;
-    uint64_t wd = 0;
-    if (t >= zlead && t < p) wd = plane_read(r, n, sq);
-    A[W - 1 - tp] = (uint32_t)wd;
-    A[2 * W - 1 - tp] = (uint32_t)(wd >> 32);
-  }
-  transpose_groups<W>(A);
+  read_slots_at<W>(r, A, base, p, zlead, sq, n);
   return base;
 }
 
@@ -993,7 +1004,55 @@ __device__ __forceinline__ void decode_hi32(R& r, int p, int zlead, int emax, do
   for (int l = 0; l < 64; ++l) acc[l] = acc[l] + __builtin_ldexp((double)q[l], emax - 30);
 }
 
-// a coded float32 block decodes on the high-half route (inverse_dequant_add_hi16)
+// The high-half route straight from the slots of a residual component (W =
+// 4 or 8): the pairs R[m] = (h(2m), h(2m+1)) that lift_dequant_add_hi16
+// starts from, h(b) the high half of the coded-order word of block position
+// b, are formed from the transposed words without the 32-bit words.  With
+// slice X of that position (W bits, its negabinary mask bits M already
+// flipped, see planes_slots) and sh = 32 - W - base >= 16 + (W == 4 ? 4 : 0)
+// (base <= 8 here), the word is ((X - M) << sh) modulo 2^32, whose high half
+// is ((X - M) << (sh - 16)) modulo 2^16.  One byte permute moves the byte
+// holding each position's slice into the low byte of its half (W = 4: a
+// mask then keeps the nibble), and one packed multiply-add forms X * 2^(sh -
+// 16) - M * 2^(sh - 16) in both halves (a slice in a byte's upper nibble
+// stands for 16 X and takes 2^(sh - 20)).
+template <int W, class R>
+__device__ __forceinline__ void slots_hi16(R& r, int p, int zlead, const uint8_t* sq, v2s Rp[32]) {
+  static_assert(W == 4 || W == 8, "byte-sized slices or smaller");
+  uint32_t A[2 * W], n;
+  // base <= 8 keeps sh - 16 >= 4 (W = 4) or >= 0 (W = 8); p <= 10 and a
+  // block with zlead = 9 codes one plane, which slot 1 then holds
+  const int base = zlead < 8 ? zlead : 8;
+  read_slots_at<W>(r, A, base, p, zlead, sq, n);
+  const int sh = 32 - W - base;
+  const uint32_t MM = (sh & 1) ? 0x55555555u : 0xAAAAAAAAu;
+#pragma unroll
+  for (int i = 0; i < 2 * W; ++i) A[i] ^= MM;
+  constexpr uint32_t kSlice = (1u << W) - 1u;
+  const uint32_t d = (uint32_t)(sh - 16);
+  const uint32_t off = (0u - ((MM & kSlice) << d)) & 0xFFFFu;  // -M * 2^(sh - 16) modulo 2^16
+  const v2u offp = {(unsigned short)off, (unsigned short)off};
+  // multipliers by the nibble each half takes: [lower][lower], [lower][upper], ...
+  const unsigned short mlo = (unsigned short)(1u << d), mhi = (unsigned short)(W == 4 ? 1u << (d - 4) : 0u);
+  const v2u mul[4] = {{mlo, mlo}, {mhi, mlo}, {mlo, mhi}, {mhi, mhi}};
+#pragma unroll
+  for (int m = 0; m < 32; ++m) {
+    // coded positions of block positions 2m and 2m+1, and where their slices sit
+    constexpr int kNone = 0x0C;  // v_perm selector of a zero byte
+    const int j0 = kInvOrder.at[2 * m], j1 = kInvOrder.at[2 * m + 1];
+    const int w0 = (j0 >> 5) * W + (j0 & 31) % W, g0 = (j0 & 31) / W;
+    const int w1 = (j1 >> 5) * W + (j1 & 31) % W, g1 = (j1 & 31) / W;
+    const int b0 = W == 4 ? g0 >> 1 : g0, b1 = W == 4 ? g1 >> 1 : g1;  // bytes
+    const int u0 = W == 4 ? g0 & 1 : 0, u1 = W == 4 ? g1 & 1 : 0;      // upper nibbles
+    // perm(x, y, sel): selector 0-3 picks a byte of y, 4-7 one of x
+    const uint32_t sel = (uint32_t)b0 | ((uint32_t)kNone << 8) | ((uint32_t)(4 + b1) << 16) | ((uint32_t)kNone << 24);
+    uint32_t v = __builtin_amdgcn_perm(A[w1], A[w0], sel);
+    if constexpr (W == 4) v &= (u0 ? 0xF0u : 0x0Fu) | ((u1 ? 0xF0u : 0x0Fu) << 16);
+    Rp[m] = (v2s)(__builtin_bit_cast(v2u, v) * mul[u0 + 2 * u1] + offp);
+  }
+}
+
+// a coded float32 block decodes on the high-half route (lift_dequant_add_hi16)
 // when its coded planes all lie in the top ten bit positions and its
 // exponent keeps the scaled values normal
 template <class T> __device__ __forceinline__ bool hi16_block(int p, int emax) {

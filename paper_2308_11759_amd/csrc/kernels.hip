@@ -995,12 +995,25 @@ __device__ __forceinline__ bool decode_block_add(R& r, int minexp, T acc[64], co
       return true;
     }
   }
-  typename FT<T>::S c[64], q[64];
-  planes_read<T>(r, c, p, zlead, sq, rel);
   if constexpr (sizeof(T) == 4 && kRoute == kRouteHi16) {
-    inverse_dequant_add_hi16(c, emax, acc);
+    // residual components (rel): the packed pairs straight from 4 or 8
+    // slots, else from the 32-bit words of 16
+    v2s R2[32];
+    const int np = p - zlead;
+    if (__all(np <= 4)) {
+      slots_hi16<4>(r, p, zlead, sq, R2);
+    } else if (__all(np <= 8)) {
+      slots_hi16<8>(r, p, zlead, sq, R2);
+    } else {
+      typename FT<T>::S c[64];
+      planes_slots<T, 16>(r, c, p, zlead, sq, rel);
+      pack_hi16(c, R2);
+    }
+    lift_dequant_add_hi16(R2, emax, acc);
     return true;
   }
+  typename FT<T>::S c[64], q[64];
+  planes_read<T>(r, c, p, zlead, sq, rel);
   inverse_zy_ints<T>(c, q);
   inverse_x<T>(q);
   dequant_add(q, emax, acc);
