@@ -260,6 +260,11 @@ __device__ __forceinline__ double fma_exact(double v, double scale, double a) { 
 
 // NaN-propagating max, matching "take a if not a <= m"
 __device__ __forceinline__ double nmax(double m, double a) { return a <= m ? m : a; }
+// the same maximum where no operand is NaN: one v_max_f64 instead of a
+// compare and two selects.  The candidate checks take it: |x - x~_i| with
+// x finite (an input with NaN or Inf fails the call whatever its streams)
+// and x~_i finite or, on overflow, infinite (x~_{i-1} stays within tau of x)
+__device__ __forceinline__ double nmax_num(double m, double a) { return __builtin_fmax(m, a); }
 
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
@@ -411,7 +416,7 @@ __device__ __forceinline__ double check_rows_pq(const XLds<T>& XL, const T* tin,
         const int l = 4 * r + t;
         const typename FT<T>::S q = (typename FT<T>::S)__builtin_rint((double)opaque(e[l]) * inv);
         row[t] = tr[4 * k + t] + (T)((double)q * h);  // x~_{i-1} + x_i in the field precision
-        ea = nmax(ea, masked_abs(vmask, l, (double)XL.at(l) - (double)row[t]));
+        ea = nmax_num(ea, masked_abs(vmask, l, (double)XL.at(l) - (double)row[t]));
       }
       if (tout) tile_store_row(tout, lane, r, row);
     }
@@ -577,7 +582,8 @@ __device__ __forceinline__ void encode_wave(const EncArgs<T> a, uint32_t wave, T
               for (int t = 0; t < 4; ++t) {
                 const int l = 4 * r + t;
                 row[t] = fma_exact(dv[l], scale, tr[4 * k + t]);  // x~_{i-1} + x_i in the field precision
-                ea = nmax(ea, masked_abs(vmask, l, (double)XL.at(l) - (double)row[t]));
+                const double dl = masked_abs(vmask, l, (double)XL.at(l) - (double)row[t]);
+                ea = sizeof(T) == 4 ? nmax_num(ea, dl) : nmax(ea, dl);  // (float64: nmax holds fewer registers)
               }
               if (tile_out) tile_store_row(tile_out, ln, r, row);
             }
