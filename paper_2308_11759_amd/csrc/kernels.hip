@@ -1435,12 +1435,22 @@ __global__ void k_fill64(unsigned long long* p, uint64_t n, unsigned long long v
 // batches: many fields of mixed size and type in persistent launches.  Work
 // is listed as items; each workgroup walks the list with a static stride, so
 // a field's bytes depend only on its own blocks, never on the schedule.
-template <class T> __device__ __forceinline__ EncArgs<T> field_enc_args(const FieldDev& f, int comp) {
+template <class T, class F> __device__ __forceinline__ EncArgs<T> field_enc_args(const F& f, int comp) {
   EncArgs<T> a;
   a.x = reinterpret_cast<const T*>(f.x);
   a.xt_in = reinterpret_cast<const T*>(comp > 0 ? f.xt[(comp - 1) & 1] : nullptr);
   a.xt_out = reinterpret_cast<T*>(f.xt[comp & 1]);
-  a.g = f.g;
+  // member by member: F may live in the constant address space
+  a.g.nx = f.g.nx;
+  a.g.ny = f.g.ny;
+  a.g.nz = f.g.nz;
+  a.g.nbx = f.g.nbx;
+  a.g.nby = f.g.nby;
+  a.g.nbz = f.g.nbz;
+  a.g.nblocks = f.g.nblocks;
+  a.g.nchunks = f.g.nchunks;
+  a.g.rows_aligned = f.g.rows_aligned;
+  a.g.pad = 0;
   a.tau = f.tau[comp];
   a.minexp = f.minexp[comp];
   a.first = comp == 0;
@@ -1458,10 +1468,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
   __shared__ T s_x[64 * 64];
   __shared__ uint16_t s_unsq[256];
   unsqueeze_table(s_unsq);
+  // the field table is read-only for the launch: read through the constant
+  // address space, so its values can be loaded again where needed instead of
+  // being held across the wave's work
+  typedef __attribute__((address_space(4))) const FieldDev CFieldDev;
+  const CFieldDev* const fields = (const CFieldDev*)b.fields;
   for (uint32_t it = blockIdx.x; it < b.nitems; it += gridDim.x) {
     const Item w = b.items[it];
-    const FieldDev* f = b.fields + w.field;
-    if (b.comp < f->ncomp) encode_wave<T, false, 0, false>(field_enc_args<T>(*f, b.comp), w.index, s_x, s_unsq);
+    const CFieldDev& f = fields[w.field];
+    if (b.comp < f.ncomp) encode_wave<T, false, 0, false>(field_enc_args<T>(f, b.comp), w.index, s_x, s_unsq);
     __syncthreads();  // the next item reuses s_x
   }
 }
