@@ -1281,11 +1281,26 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     if (a.wave_prefix[mid] <= w) lo = mid;
     else hi = mid;
   }
-  const QueryDev& q = a.q[lo];
-  if (!decode_wave<T, kStaged, false, false, kCodec, kHiRes>(q.g, q.s, q.aux, q.words, q.minexp, q.step, q.ncomp,
-                                                             q.relmask, reinterpret_cast<const T*>(q.in),
-                                                             reinterpret_cast<T*>(q.out), w - a.wave_prefix[lo],
-                                                             s_squeeze, s_stage))
+  // the query table is read-only for the launch: read through the constant
+  // address space, so its values can be loaded again where needed instead of
+  // being held across the wave's work
+  typedef __attribute__((address_space(4))) const QueryDev CQueryDev;
+  const CQueryDev& q = ((const CQueryDev*)a.q)[lo];
+  Geo g;
+  g.nx = q.g.nx;
+  g.ny = q.g.ny;
+  g.nz = q.g.nz;
+  g.nbx = q.g.nbx;
+  g.nby = q.g.nby;
+  g.nbz = q.g.nbz;
+  g.nblocks = q.g.nblocks;
+  g.nchunks = q.g.nchunks;
+  g.rows_aligned = q.g.rows_aligned;
+  g.pad = 0;
+  if (!decode_wave<T, kStaged, false, false, kCodec, kHiRes>(
+          g, (const uint8_t* const*)q.s, (const uint32_t* const*)q.aux, (const uint64_t*)q.words,
+          (const int*)q.minexp, (const double*)q.step, q.ncomp, q.relmask, reinterpret_cast<const T*>(q.in),
+          reinterpret_cast<T*>(q.out), w - a.wave_prefix[lo], s_squeeze, s_stage))
     atomicOr(a.status, 1u);
 }
 
