@@ -233,6 +233,35 @@ def test_float32_decode_routes(ctx):
     assert [c["high_half"] for c in st.info] == [False, False]
 
 
+def test_float32_high_half_route_sixteen_slots(ctx):
+    """The high-half route where a residual component codes 9 or 10 planes
+    in a block, all in the top ten bit positions (the 16-slot path).  The
+    encoder's guard planes leave each component's error far below its
+    tolerance, so its own residual components code a few planes; the store
+    here is assembled from two oracle streams instead: a field x at tau
+    2^-1, then the encoding of a field y that is constant on each 4^3 block
+    with |y| in [0.5, 1), at tau 2^-2 (p = 10 planes, the DC coefficient
+    near full scale), as the second component.  The deserialiser finds the
+    route from the payload, and x~_2, retrieved and refined from x~_1,
+    equals the oracle's decode of the same streams."""
+    rng = np.random.default_rng(5)
+    x = inputs.spectral_field((20, 24, 36), seed=34, dtype=np.float32)
+    v = (rng.uniform(0.5, 0.99, (5, 6, 9)) * rng.choice([-1.0, 1.0], (5, 6, 9))).astype(np.float32)
+    y = np.ascontiguousarray(np.repeat(np.repeat(np.repeat(v, 4, 0), 4, 1), 4, 2))
+    cx, mx, _ = oracle_run(x, [0.5])
+    cy, my, _ = oracle_run(y, [0.25])
+    comps, meta = [cx[0], cy[0]], [mx[0], my[0]]
+    recon = [driver.reconstruct(comps, k, x.shape, x.dtype) for k in (1, 2)]
+    st = ctx.deserialize(store_blob(x.shape, x.dtype, comps, meta))
+    assert st.info[1]["high_half"]
+    got = ctx.retrieve(st, 2).cpu().numpy()
+    assert np.array_equal(got, recon[1])
+    xt = ctx.retrieve(st, 1)
+    assert np.array_equal(xt.cpu().numpy(), recon[0])
+    ctx.refine(st, 1, 2, xt)
+    assert np.array_equal(xt.cpu().numpy(), recon[1])
+
+
 def test_fused_literal_refine_agree(ctx):
     from paper_2308_11759_amd import pmc
     x = inputs.spectral_field((24, 28, 40), seed=9, dtype=np.float32)
