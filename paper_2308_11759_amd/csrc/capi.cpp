@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstddef>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -377,11 +378,11 @@ pmc_status pmc_compress(pmc_ctx* ctx, const pmc_field* f, const void* d_x, int n
   if (e != hipSuccess) return hipfail(ctx, e, "hipSetDevice");
   uint8_t* ws = (uint8_t*)d_ws;
   CompMeta* meta = (CompMeta*)(ws + w.meta);
-  if ((e = launch_fill64((unsigned long long*)meta, (uint64_t)n * sizeof(CompMeta) / 8, 0ull, ctx->stream)) !=
-      hipSuccess)
-    return hipfail(ctx, e, "meta init");
+  // every counter zero; component 0's stream starts after the n block indexes
   const uint64_t auxb = aux_bytes(g);
-  if ((e = launch_fill64(&meta[0].stream_offset, 1, (unsigned long long)(n * auxb), ctx->stream)) != hipSuccess)
+  if ((e = launch_fill64_one((unsigned long long*)meta, (uint64_t)n * sizeof(CompMeta) / 8, 0ull,
+                             offsetof(CompMeta, stream_offset) / 8, (unsigned long long)(n * auxb), ctx->stream)) !=
+      hipSuccess)
     return hipfail(ctx, e, "meta init");
 
   std::vector<int> minexp(n);
@@ -598,7 +599,9 @@ static pmc_status decode_range(pmc_ctx* ctx, const pmc_store* s, int k0, int k1,
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hipfail(ctx, e, "hipSetDevice");
   unsigned int* status = (unsigned int*)d_ws;
-  if ((e = launch_fill64((unsigned long long*)status, 1, 0ull, ctx->stream)) != hipSuccess)
+  // the kernels only ever set the status word; it is cleared, and read,
+  // when the call checks it
+  if (ctx->sync_check && (e = launch_fill64((unsigned long long*)status, 1, 0ull, ctx->stream)) != hipSuccess)
     return hipfail(ctx, e, "status init");
   const int group = ctx->fused_decode ? kMaxDecode : 1;
   const void* in = d_in;
@@ -654,7 +657,9 @@ pmc_status pmc_retrieve_box(pmc_ctx* ctx, const pmc_store* s, int k, const uint6
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hipfail(ctx, e, "hipSetDevice");
   unsigned int* status = (unsigned int*)d_ws;
-  if ((e = launch_fill64((unsigned long long*)status, 1, 0ull, ctx->stream)) != hipSuccess)
+  // the kernels only ever set the status word; it is cleared, and read,
+  // when the call checks it
+  if (ctx->sync_check && (e = launch_fill64((unsigned long long*)status, 1, 0ull, ctx->stream)) != hipSuccess)
     return hipfail(ctx, e, "status init");
   BoxArgs b{};
   for (int a = 0; a < 3; ++a) {

@@ -783,9 +783,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
 }
 
 // ---------------------------------------------------------------------------
-// chunk offsets: exclusive prefix sum of chunk word counts in three passes
-// over tiles of kScanTile chunks (tile sums, scan of the tile sums with the
-// stream size bookkeeping, per-tile scans)
+// chunk offsets: exclusive prefix sum of chunk word counts in two passes
+// over tiles of kScanTile chunks (tile sums; then per tile the sum of the
+// tile sums before it plus the scan inside it, with the stream size
+// bookkeeping in the first tile's workgroup).  The batched path keeps three
+// passes (tile sums, their scan per field, per-tile scans)
 __device__ __forceinline__ unsigned long long wave_incl_scan(unsigned long long v, uint32_t lane) {
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
@@ -820,21 +822,32 @@ __global__ __launch_bounds__(1024) void k_tile_sums(ScanArgs a) {
   if (threadIdx.x == kScanTile - 1) a.tile_sums[blockIdx.x] = v;
 }
 
-__global__ __launch_bounds__(1024) void k_tile_scan(ScanArgs a) {
+// chunk offsets of one tile: the words of the tiles before it (from the
+// tile sums) plus the exclusive scan inside the tile; workgroup 0 also
+// records the stream's size and where the next component's stream starts
+__global__ __launch_bounds__(1024) void k_tile_offsets(ScanArgs a) {
   __shared__ unsigned long long sh[16];
   const uint64_t ntiles = (a.nchunks + kScanTile - 1) / kScanTile;
-  unsigned long long carry = 0;
-  for (uint64_t base = 0; base < ntiles; base += 1024) {  // exclusive scan in place
-    const uint64_t i = base + threadIdx.x;
-    unsigned long long v = i < ntiles ? a.tile_sums[i] : 0ull;
-    unsigned long long inc = block_incl_scan(v, sh);
-    if (i < ntiles) a.tile_sums[i] = carry + inc - v;
-    carry += sh[15];  // tile total (read before the barrier below)
-    __syncthreads();
+  unsigned long long before = 0, total = 0;
+  for (uint64_t base = 0; base < ntiles; base += 1024) {
+    const uint64_t j = base + threadIdx.x;
+    const unsigned long long v = j < ntiles ? a.tile_sums[j] : 0ull;
+    before += j < blockIdx.x ? v : 0ull;
+    total += v;
   }
-  if (threadIdx.x == 0) {
+  (void)block_incl_scan(before, sh);
+  before = sh[15];  // the workgroup's sum (sh is stable until the next scan writes it)
+  __syncthreads();
+  (void)block_incl_scan(total, sh);
+  total = sh[15];
+  __syncthreads();
+  const uint64_t i = (uint64_t)blockIdx.x * kScanTile + threadIdx.x;
+  const unsigned long long v = i < a.nchunks ? a.chunk_words[i] : 0ull;
+  const unsigned long long inc = block_incl_scan(v, sh);
+  if (i < a.nchunks) a.offsets[i] = (uint32_t)(before + inc - v);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     CompMeta* m = &a.meta[a.comp];
-    const unsigned long long words = carry;
+    const unsigned long long words = total;
     const unsigned long long bytes = (unsigned long long)kHeaderBytes + 4ull * a.nchunks + 4ull * words;
     m->payload_words = words;
     m->stream_bytes = bytes;
@@ -843,14 +856,6 @@ __global__ __launch_bounds__(1024) void k_tile_scan(ScanArgs a) {
     if (words > 0xFFFFFFFFull) m->flags |= FLAG_INDEX;
     if (a.comp + 1 < a.ncomp) a.meta[a.comp + 1].stream_offset = (end + 255ull) & ~255ull;
   }
-}
-
-__global__ __launch_bounds__(1024) void k_tile_offsets(ScanArgs a) {
-  __shared__ unsigned long long sh[16];
-  const uint64_t i = (uint64_t)blockIdx.x * kScanTile + threadIdx.x;
-  unsigned long long v = i < a.nchunks ? a.chunk_words[i] : 0ull;
-  unsigned long long inc = block_incl_scan(v, sh);
-  if (i < a.nchunks) a.offsets[i] = (uint32_t)(a.tile_sums[blockIdx.x] + inc - v);
 }
 
 // ---------------------------------------------------------------------------
@@ -1441,9 +1446,10 @@ __global__ __launch_bounds__(256) void k_range(const T* __restrict__ x, uint64_t
   }
 }
 
-__global__ void k_fill64(unsigned long long* p, uint64_t n, unsigned long long v) {
+// p[0, n) = v, except p[j] = vj (j >= n: none)
+__global__ void k_fill64(unsigned long long* p, uint64_t n, unsigned long long v, uint64_t j, unsigned long long vj) {
   uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
+  if (i < n) p[i] = i == j ? vj : v;
 }
 
 // ---------------------------------------------------------------------------
@@ -1618,7 +1624,6 @@ template <class T> hipError_t launch_encode(const EncArgs<T>& a, int codec, hipS
 hipError_t launch_scan(const ScanArgs& a, hipStream_t s) {
   const uint64_t tiles = (a.nchunks + kScanTile - 1) / kScanTile;
   hipLaunchKernelGGL(k_tile_sums, dim3((uint32_t)tiles), dim3(kScanTile), 0, s, a);
-  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, a);
   hipLaunchKernelGGL(k_tile_offsets, dim3((uint32_t)tiles), dim3(kScanTile), 0, s, a);
   return hipGetLastError();
 }
@@ -1864,8 +1869,12 @@ hipError_t launch_batch_init(const FieldDev* fields, uint32_t nfields, hipStream
   return hipGetLastError();
 }
 hipError_t launch_fill64(unsigned long long* p, uint64_t n, unsigned long long v, hipStream_t s) {
+  return launch_fill64_one(p, n, v, n, v, s);
+}
+hipError_t launch_fill64_one(unsigned long long* p, uint64_t n, unsigned long long v, uint64_t j,
+                             unsigned long long vj, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fill64, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+  hipLaunchKernelGGL(k_fill64, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, p, n, v, j, vj);
   return hipGetLastError();
 }
 

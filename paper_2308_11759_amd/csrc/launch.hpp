@@ -198,6 +198,9 @@ hipError_t launch_decode_box(const DecArgs<T>& a, const BoxArgs& b, uint64_t max
 uint64_t stage_words();  // capacity of the decoder's LDS staging buffer, in words
 template <class T> hipError_t launch_range(const T* x, uint64_t n, unsigned long long* out, hipStream_t s);
 hipError_t launch_fill64(unsigned long long* p, uint64_t n, unsigned long long v, hipStream_t s);
+// the same with p[j] = vj instead (one launch)
+hipError_t launch_fill64_one(unsigned long long* p, uint64_t n, unsigned long long v, uint64_t j,
+                             unsigned long long vj, hipStream_t s);
 // out[0] = sum of d, out[1] = sum of d^2 in float64, d = a - b - shift (b NULL: 0);
 // ws holds sum_sq_ws_bytes() bytes of partials; out may lie inside ws past them
 template <class T>
