@@ -74,8 +74,11 @@ inline hipEvent_t prof_event(pmc_ctx* c) {
     c->prof_pool.pop_back();
     return e;
   }
+  // timing only: pmc_prof_read synchronises the stream before it reads
+  // them, so the events need no system-scope fence (whose cache writeback
+  // and invalidation would also land between the kernels they bracket)
   hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
   return e;
 }
 
