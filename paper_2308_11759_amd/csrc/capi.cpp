@@ -112,6 +112,7 @@ pmc_store* store_from_meta(const pmc_field* f, const Geo& g, int n, const double
 // memory): pmc_ctx_create looks up its device address once per device with
 // hipGetSymbolAddress, and only that address is passed on.
 static_assert(PMC_STATIC_WS_BYTES % 256 == 0, "static workspace size");
+static_assert(kPinBytes >= kMaxComps * sizeof(CompMeta), "the pinned buffer holds every component's metadata");
 static __device__ __align__(256) uint8_t scratch[PMC_STATIC_WS_BYTES];
 
 namespace {
@@ -157,8 +158,20 @@ pmc_status pmc_ctx_create(int device, void* hip_stream, pmc_ctx** out) {
   pmc_ctx* c = new pmc_ctx();
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
+  if (hipSetDevice(device) != hipSuccess || hipHostMalloc(&c->pin, kPinBytes, hipHostMallocDefault) != hipSuccess)
+    c->pin = nullptr;
   *out = c;
   return PMC_OK;
+}
+
+// copy `bytes` of device memory to host `dst` on the context stream and wait
+// for it, through the context's pinned buffer when it holds them
+static hipError_t read_back(pmc_ctx* ctx, void* dst, const void* src, size_t bytes) {
+  void* via = ctx->pin && bytes <= kPinBytes ? ctx->pin : dst;
+  hipError_t e = hipMemcpyAsync(via, src, bytes, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e == hipSuccess && via != dst) std::memcpy(dst, via, bytes);
+  return e;
 }
 
 void pmc_ctx_destroy(pmc_ctx* ctx) {
@@ -169,6 +182,10 @@ void pmc_ctx_destroy(pmc_ctx* ctx) {
     (void)hipEventDestroy(r.stop);
   }
   for (auto e : ctx->prof_pool) (void)hipEventDestroy(e);
+  if (ctx->pin) {
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipHostFree(ctx->pin);
+  }
   delete ctx;
 }
 
@@ -230,15 +247,13 @@ pmc_status pmc_range(pmc_ctx* ctx, const pmc_field* f, const void* d_x, void* d_
   if (e != hipSuccess) return hipfail(ctx, e, "hipSetDevice");
   unsigned long long* w = (unsigned long long*)d_ws;
   const uint64_t n = g.nx * g.ny * g.nz;
-  if ((e = launch_fill64(w, 1, ~0ull, ctx->stream)) != hipSuccess) return hipfail(ctx, e, "fill");
-  if ((e = launch_fill64(w + 1, 2, 0ull, ctx->stream)) != hipSuccess) return hipfail(ctx, e, "fill");
+  // min key all ones; max key and non-finite count zero
+  if ((e = launch_fill64_one(w, 3, 0ull, 0, ~0ull, ctx->stream)) != hipSuccess) return hipfail(ctx, e, "fill");
   if (f->dtype == PMC_F32) e = launch_range<float>((const float*)d_x, n, w, ctx->stream);
   else e = launch_range<double>((const double*)d_x, n, w, ctx->stream);
   if (e != hipSuccess) return hipfail(ctx, e, "range kernel");
   unsigned long long h[3];
-  if ((e = hipMemcpyAsync(h, w, sizeof(h), hipMemcpyDeviceToHost, ctx->stream)) != hipSuccess)
-    return hipfail(ctx, e, "copy");
-  if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return hipfail(ctx, e, "sync");
+  if ((e = read_back(ctx, h, w, sizeof(h))) != hipSuccess) return hipfail(ctx, e, "range read");
   auto unorder = [](unsigned long long o) {
     uint64_t b = (o >> 63) ? (o & 0x7FFFFFFFFFFFFFFFull) : ~o;
     double v;
@@ -477,10 +492,7 @@ pmc_status pmc_compress(pmc_ctx* ctx, const pmc_field* f, const void* d_x, int n
     }
   }
   std::vector<CompMeta> hm(n);
-  if ((e = hipMemcpyAsync(hm.data(), meta, n * sizeof(CompMeta), hipMemcpyDeviceToHost, ctx->stream)) !=
-      hipSuccess)
-    return hipfail(ctx, e, "meta copy");
-  if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return hipfail(ctx, e, "sync");
+  if ((e = read_back(ctx, hm.data(), meta, n * sizeof(CompMeta))) != hipSuccess) return hipfail(ctx, e, "meta read");
 
   unsigned int flags = 0;
   unsigned long long misses = 0;
@@ -637,9 +649,7 @@ static pmc_status decode_range(pmc_ctx* ctx, const pmc_store* s, int k0, int k1,
   }
   if (ctx->sync_check) {
     unsigned int h = 0;
-    if ((e = hipMemcpyAsync(&h, status, 4, hipMemcpyDeviceToHost, ctx->stream)) != hipSuccess)
-      return hipfail(ctx, e, "status copy");
-    if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return hipfail(ctx, e, "sync");
+    if ((e = read_back(ctx, &h, status, 4)) != hipSuccess) return hipfail(ctx, e, "status read");
     if (h) return fail(ctx, PMC_E_CORRUPT, "malformed stream");
   }
   return PMC_OK;
@@ -696,9 +706,7 @@ pmc_status pmc_retrieve_box(pmc_ctx* ctx, const pmc_store* s, int k, const uint6
   }
   if (ctx->sync_check) {
     unsigned int h = 0;
-    if ((e = hipMemcpyAsync(&h, status, 4, hipMemcpyDeviceToHost, ctx->stream)) != hipSuccess)
-      return hipfail(ctx, e, "status copy");
-    if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return hipfail(ctx, e, "sync");
+    if ((e = read_back(ctx, &h, status, 4)) != hipSuccess) return hipfail(ctx, e, "status read");
     if (h) return fail(ctx, PMC_E_CORRUPT, "malformed stream");
   }
   return PMC_OK;

@@ -31,7 +31,13 @@ struct pmc_ctx {
   std::vector<double> prof_ms;
   std::vector<ProfRec> prof_pending;
   std::vector<hipEvent_t> prof_pool;
+  // pinned host memory for the small device-to-host reads of the calls that
+  // synchronise (range, compressed sizes, decode status): a direct copy
+  // instead of one staged through pageable memory; null if it could not be
+  // allocated (the calls then read into pageable memory)
+  void* pin = nullptr;
 };
+constexpr size_t kPinBytes = 8192;  // >= kMaxComps * sizeof(CompMeta)
 
 struct pmc_store {
   pmc_field f{};
