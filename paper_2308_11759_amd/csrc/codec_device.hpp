@@ -709,7 +709,22 @@ __device__ __forceinline__ void dequant_add(const int64_t q[64], int emax, doubl
 // adjacent rows for the x pass (one byte permute per register between).
 // Then h * 2^(emax-14) equals q * 2^(emax-30) exactly while fast_dequant(emax)
 // holds, so the fused multiply-add is the one of dequant_add.
-__device__ __forceinline__ void lift_dequant_add_hi16(v2s R[32], int emax, float acc[64]) {
+// Float64 has the same property at the top of its 64-bit words: with p <= 10
+// the coefficients are multiples of 2^54, the words the lifting forms are
+// multiples of 2^48, and their top 16 bits h follow the same packed lifting;
+// q = h * 2^48 is exact in double, so q * 2^(emax-62) = h * 2^(emax-14),
+// computed exactly while it is normal (emax >= -1008), is what dequantize()
+// gives, and the fused multiply-add of that exact product is acc + it.
+template <class T> __device__ __forceinline__ T hi16_scale(int emax);
+template <> __device__ __forceinline__ float hi16_scale<float>(int emax) {
+  return __uint_as_float((uint32_t)(emax - 14 + 127) << 23);
+}
+template <> __device__ __forceinline__ double hi16_scale<double>(int emax) {
+  return __longlong_as_double((long long)((uint64_t)(emax - 14 + 1023) << 52));
+}
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+template <class T> __device__ __forceinline__ void lift_dequant_add_hi16(v2s R[32], int emax, T acc[64]) {
 #pragma unroll
   for (int m = 0; m < 8; ++m) lift_inv(R[m], R[m + 8], R[m + 16], R[m + 24]);  // z: l, l+16, l+32, l+48
 #pragma unroll
@@ -717,21 +732,21 @@ __device__ __forceinline__ void lift_dequant_add_hi16(v2s R[32], int emax, float
     const int m = 8 * (k >> 1) + (k & 1);
     lift_inv(R[m], R[m + 2], R[m + 4], R[m + 6]);
   }
-  const float scale = __uint_as_float((uint32_t)(emax - 14 + 127) << 23);
+  const T scale = hi16_scale<T>(emax);
 #pragma unroll
-  for (int s = 0; s < 8; ++s) {  // rows 2s and 2s+1: T[x] = (q[8s + x], q[8s + 4 + x])
+  for (int s = 0; s < 8; ++s) {  // rows 2s and 2s+1: X[x] = (q[8s + x], q[8s + 4 + x])
     const uint32_t a0 = __builtin_bit_cast(uint32_t, R[4 * s]), a1 = __builtin_bit_cast(uint32_t, R[4 * s + 1]);
     const uint32_t b0 = __builtin_bit_cast(uint32_t, R[4 * s + 2]), b1 = __builtin_bit_cast(uint32_t, R[4 * s + 3]);
-    v2s T0 = __builtin_bit_cast(v2s, __builtin_amdgcn_perm(b0, a0, 0x05040100u));
-    v2s T1 = __builtin_bit_cast(v2s, __builtin_amdgcn_perm(b0, a0, 0x07060302u));
-    v2s T2 = __builtin_bit_cast(v2s, __builtin_amdgcn_perm(b1, a1, 0x05040100u));
-    v2s T3 = __builtin_bit_cast(v2s, __builtin_amdgcn_perm(b1, a1, 0x07060302u));
-    lift_inv(T0, T1, T2, T3);
-    const v2s T[4] = {T0, T1, T2, T3};
+    v2s X0 = __builtin_bit_cast(v2s, __builtin_amdgcn_perm(b0, a0, 0x05040100u));
+    v2s X1 = __builtin_bit_cast(v2s, __builtin_amdgcn_perm(b0, a0, 0x07060302u));
+    v2s X2 = __builtin_bit_cast(v2s, __builtin_amdgcn_perm(b1, a1, 0x05040100u));
+    v2s X3 = __builtin_bit_cast(v2s, __builtin_amdgcn_perm(b1, a1, 0x07060302u));
+    lift_inv(X0, X1, X2, X3);
+    const v2s X[4] = {X0, X1, X2, X3};
 #pragma unroll
     for (int x = 0; x < 4; ++x) {
-      acc[8 * s + x] = __builtin_fmaf((float)T[x].x, scale, acc[8 * s + x]);
-      acc[8 * s + 4 + x] = __builtin_fmaf((float)T[x].y, scale, acc[8 * s + 4 + x]);
+      acc[8 * s + x] = fma_t((T)X[x].x, scale, acc[8 * s + x]);
+      acc[8 * s + 4 + x] = fma_t((T)X[x].y, scale, acc[8 * s + 4 + x]);
     }
   }
 }
@@ -1015,7 +1030,9 @@ __device__ __forceinline__ void decode_hi32(R& r, int p, int zlead, int emax, do
 // holding each position's slice into the low byte of its half (W = 4: a
 // mask then keeps the nibble), and one packed multiply-add forms X * 2^(sh -
 // 16) - M * 2^(sh - 16) in both halves (a slice in a byte's upper nibble
-// stands for 16 X and takes 2^(sh - 20)).
+// stands for 16 X and takes 2^(sh - 20)).  A float64 word's top 16 bits come
+// out the same: its shift is sh + 32, of the same parity, and the top half
+// of (X - M) << (sh + 32) modulo 2^64 is again (X - M) << (sh - 16).
 template <int W, class R>
 __device__ __forceinline__ void slots_hi16(R& r, int p, int zlead, const uint8_t* sq, v2s Rp[32]) {
   static_assert(W == 4 || W == 8, "byte-sized slices or smaller");

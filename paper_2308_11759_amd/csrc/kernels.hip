@@ -995,6 +995,23 @@ __device__ __forceinline__ bool decode_block_add(R& r, int minexp, T acc[64], co
   const int zlead = z0 < p ? z0 : p;
   r.skip((uint32_t)zlead);
   if constexpr (sizeof(T) == 8 && kRoute == kRouteAuto) {
+    // residual components whose coded planes all lie in the top ten bit
+    // positions and keep every result normal: the lifting on the words' top
+    // 16 bits, two per register, from 4 or 8 slots (wave-uniform choices)
+    if (rel && __all(p <= 10 && emax >= -1008)) {
+      const int np = p - zlead;
+      v2s R2[32];
+      if (__all(np <= 4)) {
+        slots_hi16<4>(r, p, zlead, sq, R2);
+        lift_dequant_add_hi16(R2, emax, acc);
+        return true;
+      }
+      if (__all(np <= 8)) {
+        slots_hi16<8>(r, p, zlead, sq, R2);
+        lift_dequant_add_hi16(R2, emax, acc);
+        return true;
+      }
+    }
     // every coded plane in the top 26 bit positions and every result
     // normal: the lifting on the coefficients' high words (a wave-uniform
     // choice; both routes give the same sums)

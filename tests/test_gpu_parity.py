@@ -262,6 +262,31 @@ def test_float32_high_half_route_sixteen_slots(ctx):
     assert np.array_equal(xt.cpu().numpy(), recon[1])
 
 
+def test_float64_residual_high_half_route(ctx):
+    """Float64 residual components whose coded planes lie in the top ten bit
+    positions run the inverse lifting on the words' top 16 bits, two per
+    register (a per-wave choice).  On this field every residual wave takes
+    it with 4 plane slots at 3 bits per component and with 8 at 4 bits; at 5
+    bits the blocks code deeper planes and take the high-word route instead.
+    Every x~_k, retrieved and refined one component at a time, equals the
+    oracle's on the GPU's streams and on the oracle's own."""
+    x = inputs.spectral_field((20, 24, 36), seed=35, dtype=np.float64)
+    for bits in (3, 4, 5):
+        taus = [2.0 ** (-bits * (i + 1)) for i in range(5)]
+        comps, meta, recon = oracle_run(x, taus)
+        store = ctx.compress(to_dev(x), taus)
+        for i in range(len(taus)):
+            assert store.info[i]["bytes"] == len(comps[i]), (bits, i)
+        theirs = ctx.deserialize(store_blob(x.shape, x.dtype, comps, meta))
+        for st in (store, theirs):
+            for k in range(1, len(taus) + 1):
+                assert np.array_equal(ctx.retrieve(st, k).cpu().numpy(), recon[k - 1]), (bits, k)
+            for j in range(1, len(taus)):
+                xt = ctx.retrieve(st, j)
+                ctx.refine(st, j, j + 1, xt)
+                assert np.array_equal(xt.cpu().numpy(), recon[j]), (bits, j)
+
+
 def test_fused_literal_refine_agree(ctx):
     from paper_2308_11759_amd import pmc
     x = inputs.spectral_field((24, 28, 40), seed=9, dtype=np.float32)
