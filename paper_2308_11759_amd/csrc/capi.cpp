@@ -158,8 +158,13 @@ pmc_status pmc_ctx_create(int device, void* hip_stream, pmc_ctx** out) {
   pmc_ctx* c = new pmc_ctx();
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
-  if (hipSetDevice(device) != hipSuccess || hipHostMalloc(&c->pin, kPinBytes, hipHostMallocDefault) != hipSuccess)
-    c->pin = nullptr;
+  // the pinned readback buffer, allocated with the context's device current
+  // (the caller's current device is restored afterwards)
+  int prev = 0;
+  if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(device) == hipSuccess) {
+    if (hipHostMalloc(&c->pin, kPinBytes, hipHostMallocDefault) != hipSuccess) c->pin = nullptr;
+    (void)hipSetDevice(prev);
+  }
   *out = c;
   return PMC_OK;
 }
